@@ -1,0 +1,158 @@
+"""Throughput benchmark of the Zakharov/HOS wave step on one MI355X.
+
+Workload (default): 512 x 512 periodic grid, 200 m x 200 m, depth 20 m,
+g = 9.81, HOS order M = 4, FP64, RK4 with dt = 0.05 s and the state filter,
+seeded JONSWAP random-phase sea state (k_p = 2 pi / 12.5 m, gamma 3.3,
+steepness 0.1, seed 1).  One step = one RK4 step (four right-hand sides:
+the DtN series, the Bernoulli term, the RK4 combination and the filter).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line: the whole-job throughput in grid-point-steps/s with
+the state resident in HBM when the timed region starts, the roofline of the
+dominant kernel (algorithmic bytes / its average launch time, timed with HIP
+events on the launch stream in a separate instrumented pass), and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "grid-point-steps/sec (RK4, HOS order M) + %HBM roofline; learned/FP32 vs FP64 at 1e-4"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(w, eta, psi, nsteps):
+    """The CPU oracle (numpy/pocketfft, FP64, as it stands) on nsteps RK4 steps
+    of the same workload; threads = os.cpu_count() for the FFTs."""
+    from oracle.hos import Grid, HOSModel, PocketDFT
+
+    workers = os.cpu_count() or 1
+    g = Grid(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], dft=PocketDFT(workers=workers))
+    m = HOSModel(g, w["M"])
+    t0 = time.perf_counter()
+    m.step(eta, psi, w["dt"], nsteps)
+    t = time.perf_counter() - t0
+    return {"value": w["nx"] * w["ny"] * nsteps / t, "unit": "grid-point-steps/s", "cores": workers,
+            "kind": "oracle", "cpu": cpu_model(),
+            "sample": f"{nsteps} RK4 steps of the benchmark workload ({t:.1f} s, pocketfft workers={workers})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="c2_512_m4")
+    ap.add_argument("--precision", type=int, default=64, choices=(32, 64))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2608_25203_amd.inputs import WORKLOADS, jonswap_state
+    from paper_2608_25203_amd.zk import ZK_OPT_PROFILE, Solver
+
+    w = dict(WORKLOADS[args.workload])
+    eta, psi = jonswap_state(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"], w["kp"], w["steepness"],
+                             w["seed"])
+    dev = torch.device("cuda:0")
+    s = Solver(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"], w["M"], precision=args.precision,
+               check=False, device=dev)
+    e = torch.tensor(eta, dtype=torch.float64, device=dev)
+    p = torch.tensor(psi, dtype=torch.float64, device=dev)
+
+    # warmup (also uploads the dt-dependent schedule)
+    if args.warmup > 0:
+        s.step(e, p, w["dt"], args.warmup)
+    torch.cuda.synchronize()
+
+    # timed region: exactly `steps` RK4 steps in one call, inputs resident in HBM
+    t0 = time.perf_counter()
+    s.step(e, p, w["dt"], args.steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    finite = bool(torch.isfinite(e).all().item() and torch.isfinite(p).all().item())
+    npts = w["nx"] * w["ny"]
+    value = npts * args.steps / t
+
+    # instrumented pass (separate): per-kernel event times, algorithmic bytes and FFT flops
+    s.set_option(ZK_OPT_PROFILE, 1)
+    s.reset_stats()
+    nprof = min(args.steps, 100)
+    s.step(e, p, w["dt"], nprof)
+    torch.cuda.synchronize()
+    st = s.kernel_stats()
+    s.set_option(ZK_OPT_PROFILE, 0)
+    kern = {k: {"ms_total": v[0], "launches": v[3], "avg_us": (1e3 * v[0] / v[3]) if v[3] else 0.0,
+                "GB_per_s": (v[1] / (v[0] * 1e-3) / 1e9) if v[0] else 0.0,
+                "fft_GFLOP_per_s": (v[2] / (v[0] * 1e-3) / 1e9) if v[0] else 0.0,
+                "alg_bytes_per_launch": (v[1] / v[3]) if v[3] else 0.0}
+            for k, v in st.items()}
+    dom = max(kern, key=lambda k: kern[k]["ms_total"])
+    d = kern[dom]
+    achieved = d["GB_per_s"]
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "kernel_avg_us": round(d["avg_us"], 2),
+                "alg_bytes_per_launch": d["alg_bytes_per_launch"],
+                "fft_GFLOP_per_s": round(d["fft_GFLOP_per_s"], 1),
+                "fft_flop_peak_TFLOPs": FP64_PEAK_TFLOPS if args.precision == 64 else FP32_PEAK_TFLOPS}
+    step_kernel_ms = sum(v["ms_total"] for v in kern.values()) / nprof
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 64 else "f32-transforms/f64-series",
+        "data": "synthetic (seeded JONSWAP random-phase sea state)",
+        "config": {"workload": f"{args.workload}: {w['nx']}x{w['ny']} grid, {w['Lx']:g} m x {w['Ly']:g} m, "
+                               f"depth {w['depth']:g} m, HOS order M={w['M']}, RK4 dt={w['dt']}, "
+                               f"JONSWAP steepness {w['steepness']}",
+                   "nx": w["nx"], "ny": w["ny"], "M": w["M"], "dt": w["dt"], "precision": args.precision},
+        "roofline": roofline,
+        "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kern.items()},
+        "kernel_ms_per_step": round(step_kernel_ms, 4),
+        "finite": finite,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, eta, psi, args.cpu_steps)
+        out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 1)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

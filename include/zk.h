@@ -1,0 +1,145 @@
+/*
+ * zk.h -- C ABI of the MI355X (gfx950) Zakharov/HOS wave-step library.
+ *
+ * The library evaluates the right-hand side of the canonical Zakharov system
+ * for the surface elevation eta and surface potential psi (Sec. 3.1,
+ * eq:zakharov_kin and eq:zakharov_dyn), whose cost is the Dirichlet-Neumann
+ * operator G(eta) psi expanded in the Craig-Sulem / high-order-spectral
+ * series of order M (Sec. 3.2, eq:G0, eq:G1, eq:G2, eq:dno_truncated; the
+ * series is continued past G_2 by the surface-potential recursion of Sec. 4.2,
+ * eq:phi0-eq:phi2).  Every product is dealiased by the 3/2 rule and tapered
+ * (Sec. 6.1); the state filter of Sec. 3.4 (eq:state_filter) follows each
+ * full RK4 step.
+ *
+ * Conventions shared by every entry point
+ *   Layout     fields are device pointers to nx*ny doubles, row-major [ny][nx]
+ *              (x fastest), contiguous, at least 16-byte aligned, on the
+ *              device that was current when zk_bind was called.
+ *   Ownership  the caller owns every field buffer and the workspace; the
+ *              library never allocates device memory.  A context owns only
+ *              host-side plans.
+ *   Aliasing   outputs must not alias inputs (zk_step works in place).
+ *   Asynchrony every call is enqueued on the bound stream and returns before
+ *              the GPU finishes, except zk_hamiltonian, which synchronises
+ *              the stream to return a host double.
+ *   Errors     0 on success, a negative ZK_E* code otherwise, with a message
+ *              in zk_last_error.  No exception crosses the ABI.
+ *   Threads    a context is not thread-safe; use one context per stream.
+ *   Sizes      nx and ny must be powers of two in [64, 2048]; nx is the fast
+ *              (row) axis.  The dealiased products run on the 3nx/2 x 3ny/2
+ *              grid.  Spectra keep their Nyquist row and column at zero, so
+ *              input fields are projected onto |m_x| < nx/2, |m_y| < ny/2.
+ */
+#ifndef ZK_H
+#define ZK_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct zk_ctx zk_ctx;
+
+enum {
+    ZK_OK = 0,
+    ZK_EINVAL = -1,    /* invalid argument or state                          */
+    ZK_ENOWS = -2,     /* workspace unbound or smaller than zk_workspace_bytes */
+    ZK_EDEVICE = -3,   /* a HIP call failed; its text is in zk_last_error     */
+    ZK_EDIVERGED = -4  /* NaN or Inf in the state after zk_step              */
+};
+
+/* Option keys for zk_set_option. */
+enum {
+    ZK_OPT_EPS = 1,       /* nonlinear-amplitude dial eps in [0, 1] (Sec. 3.2,
+                             eq:dno_truncated, eq:dyn_truncated); default 1  */
+    ZK_OPT_TAPER = 2,     /* 1: taper exp(-(|k|/kc)^8) on every product
+                             (Sec. 6.1); 0: off.  Default 1                  */
+    ZK_OPT_FILTER = 3,    /* 1: state filter A(k) after each RK4 step
+                             (Sec. 3.4, eq:state_filter); 0: off.  Default 1 */
+    ZK_OPT_PRECISION = 4, /* 64: transforms and products in FP64 (default);
+                             32: transforms and products in FP32 with the
+                             series sum, the state and the Hamiltonian in
+                             FP64.  Changes the workspace size: set it before
+                             zk_bind.                                         */
+    ZK_OPT_CHECK = 5,     /* 1: zk_step checks the result for NaN/Inf, which
+                             synchronises the stream (default); 0: no check,
+                             zk_step stays fully asynchronous                 */
+    ZK_OPT_PROFILE = 6    /* 1: bracket every kernel launch with HIP events on
+                             the bound stream and accumulate per-kind times for
+                             zk_kernel_stats (adds event records between
+                             launches); 0: off (default)                      */
+};
+
+/* Kernel kinds reported by zk_kernel_stats. */
+enum {
+    ZK_KERNEL_ROW_PAD = 0,   /* row pass on the 3/2-padded grid              */
+    ZK_KERNEL_ROW_BASE = 1,  /* row pass of the base-grid entry/exit transforms */
+    ZK_KERNEL_COL_PAD = 2,   /* column pass on the 3/2-padded grid           */
+    ZK_KERNEL_COL_BASE = 3,  /* column pass of the entry/exit transforms     */
+    ZK_KERNEL_REDUCE = 4     /* FP64 Parseval reduction                     */
+};
+
+/* Create a context for an nx x ny periodic grid of size Lx x Ly, still-water
+ * depth `depth` (<= 0 or +inf: deep water, tanh -> 1), gravity g and HOS order
+ * M (keeps G_0 .. G_{M-1}; M = 3 is the paper's "Order 3 / HOS-3", Sec. 3.2).
+ * Returns NULL on invalid arguments (sizes outside the rule above, Lx, Ly or
+ * g <= 0, M outside 1..8).  Host-side only: no device call is made. */
+zk_ctx *zk_create(int nx, int ny, double Lx, double Ly, double depth, double g, int M);
+
+/* Destroy a context (host memory only; the workspace stays the caller's). */
+void zk_destroy(zk_ctx *ctx);
+
+/* Set an option (keys above).  EPS, TAPER and FILTER may change at any time
+ * and apply from the next call; PRECISION must be set before zk_bind. */
+int zk_set_option(zk_ctx *ctx, int key, double value);
+
+/* Bytes of device workspace the context needs for its current options. */
+size_t zk_workspace_bytes(const zk_ctx *ctx);
+
+/* Bind a caller-owned device workspace (>= zk_workspace_bytes, 256-byte
+ * aligned) and a HIP stream (hipStream_t passed as void*, NULL = default
+ * stream).  Uploads the context's tables and schedules into the workspace
+ * with copies on that stream.  May be called again to rebind. */
+int zk_bind(zk_ctx *ctx, void *workspace, size_t bytes, void *stream);
+
+/* G_psi = G^[M](eta) psi = sum_{j<M} eps^j G_j(eta) psi on the base grid:
+ * the forward DNO map v = G(eta) psi (Sec. 3.5, eq:v_forward). */
+int zk_dtn(zk_ctx *ctx, const double *eta, const double *psi, double *G_psi);
+
+/* Zakharov right-hand side (Sec. 3.1 eq:zakharov_kin; Sec. 3.2
+ * eq:dyn_truncated with eq:W):
+ *   eta_t = G^[M](eta) psi,
+ *   psi_t = -g eta + eps [ -1/2 |grad psi|^2 + 1/2 (1 + eps^2 |grad eta|^2) W^2 ],
+ *   W = (G^[M] psi + eps grad eta . grad psi) / (1 + eps^2 |grad eta|^2). */
+int zk_rhs(zk_ctx *ctx, const double *eta, const double *psi, double *eta_t, double *psi_t);
+
+/* Advance (eta, psi) in place by nsteps classical RK4 steps of size dt, each
+ * followed by the state filter A(k) when ZK_OPT_FILTER is on (Sec. 3.4,
+ * eq:state_filter).  The state is kept spectral inside the call and
+ * transformed in and out once.  Returns ZK_EDIVERGED if the result holds a
+ * NaN or Inf (that check synchronises the stream). */
+int zk_step(zk_ctx *ctx, double *eta, double *psi, double dt, int nsteps);
+
+/* Hamiltonian H = 1/2 int psi G^[M](eta) psi dx + 1/2 g int eta^2 dx
+ * (Sec. 3.1, eq:hamiltonian), reduced in FP64 in a fixed order by Parseval on
+ * the half spectrum.  Synchronises the stream; writes the value to *H_host. */
+int zk_hamiltonian(zk_ctx *ctx, const double *eta, const double *psi, double *H_host);
+
+/* Diagnostic, for measurement: totals accumulated while ZK_OPT_PROFILE is on
+ * for one kernel kind -- summed event time in ms, algorithmic bytes (every
+ * field a launch reads or writes counted once), FFT flops (5 N log2 N per
+ * complex transform of length N) and the launch count.  Synchronises the
+ * stream to read pending events.  kind = -1 resets all totals (outputs may
+ * then be NULL). */
+int zk_kernel_stats(zk_ctx *ctx, int kind, double *ms, double *bytes, double *flops, long long *launches);
+
+/* Text of the last error on this context ("" if none).  Valid until the next
+ * call on the context. */
+const char *zk_last_error(const zk_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZK_H */

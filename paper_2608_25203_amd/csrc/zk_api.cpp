@@ -1,0 +1,496 @@
+// zk_api.cpp -- context, workspace layout, schedule upload and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "zk.h"
+#include "zk_kernels.hpp"
+#include "zk_plan.hpp"
+
+using namespace zk;
+
+struct zk_ctx {
+  PlanParams pp{};
+  int precision = 64;
+  int check = 1;
+  std::string err;
+
+  Plan plan;
+  double plan_dt = NAN;
+  bool have_plan = false;
+  bool dirty = true;  // schedules must be (re)uploaded
+
+  // binding
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  bool bound = false;
+
+  // workspace layout (byte offsets)
+  size_t off_tw[4] = {0, 0, 0, 0};  // row pad, row base, col pad, col base
+  size_t off_ops = 0, off_progs = 0, off_terms = 0, off_outs = 0, off_tasks = 0;
+  size_t off_red = 0, off_base = 0, off_mix = 0, total = 0;
+  long long base_stride = 0, mix_stride = 0;
+  size_t sched_cap[5] = {0, 0, 0, 0, 0};  // capacities (elements) reserved for the schedules
+
+  // optional per-kernel timing (ZK_OPT_PROFILE)
+  struct Rec {
+    int kind;
+    double bytes, flops;
+    hipEvent_t a, b;
+  };
+  bool prof = false;
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double st_ms[5] = {0, 0, 0, 0, 0}, st_bytes[5] = {0, 0, 0, 0, 0}, st_flops[5] = {0, 0, 0, 0, 0};
+  long long st_n[5] = {0, 0, 0, 0, 0};
+  ~zk_ctx() {
+    for (auto &r : pending) {
+      hipEventDestroy(r.a);
+      hipEventDestroy(r.b);
+    }
+    for (auto e : pool) hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+bool pow2_in(int n) { return n >= 64 && n <= 2048 && (n & (n - 1)) == 0; }
+
+int fail(zk_ctx *c, int code, const std::string &m) {
+  if (c) c->err = m;
+  return code;
+}
+int hip_fail(zk_ctx *c, hipError_t e, const char *what) {
+  return fail(c, ZK_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIP_TRY(c, call)                          \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return hip_fail(c, e_, #call); \
+  } while (0)
+
+size_t real_size(const zk_ctx *c) { return c->precision == 32 ? sizeof(float) : sizeof(double); }
+
+hipError_t take_event(zk_ctx *c, hipEvent_t *e) {
+  if (!c->pool.empty()) {
+    *e = c->pool.back();
+    c->pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+// Wait for pending launch events and fold them into the per-kind totals.
+int flush_prof(zk_ctx *c) {
+  if (c->pending.empty()) return ZK_OK;
+  HIP_TRY(c, hipEventSynchronize(c->pending.back().b));
+  for (auto &r : c->pending) {
+    float ms = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, r.a, r.b));
+    c->st_ms[r.kind] += ms;
+    c->st_bytes[r.kind] += r.bytes;
+    c->st_flops[r.kind] += r.flops;
+    c->st_n[r.kind] += 1;
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->pending.clear();
+  return ZK_OK;
+}
+
+// Schedule capacities: plans for the same (nx, ny, M) have identical sizes
+// for every dt and option, so one capacity computed at layout time suffices.
+void compute_layout(zk_ctx *c) {
+  const int nx = c->pp.nx, ny = c->pp.ny;
+  const size_t rs = real_size(c);
+  const size_t cs = 2 * rs;
+  const int lens[4] = {3 * nx / 2, nx, 3 * ny / 2, ny};
+  size_t off = 0;
+  for (int i = 0; i < 4; ++i) {
+    c->off_tw[i] = off;
+    off = align_up(off + lens[i] * cs);
+  }
+  Plan probe = build_plan(c->pp, 1.0);
+  c->sched_cap[0] = probe.ops.size();
+  c->sched_cap[1] = probe.progs.size();
+  c->sched_cap[2] = probe.terms.size();
+  c->sched_cap[3] = probe.outs.size();
+  c->sched_cap[4] = probe.tasks.size();
+  c->off_ops = off;
+  off = align_up(off + c->sched_cap[0] * sizeof(RowOp));
+  c->off_progs = off;
+  off = align_up(off + c->sched_cap[1] * sizeof(RowProg));
+  c->off_terms = off;
+  off = align_up(off + c->sched_cap[2] * sizeof(ColTerm));
+  c->off_outs = off;
+  off = align_up(off + c->sched_cap[3] * sizeof(ColOut));
+  c->off_tasks = off;
+  off = align_up(off + c->sched_cap[4] * sizeof(ColTask));
+  c->off_red = off;
+  off = align_up(off + (2 * kRedBlocks + 8) * sizeof(double));
+  c->base_stride = (long long)(align_up((size_t)(nx / 2) * ny * 16) / 16);
+  c->off_base = off;
+  off = align_up(off + (size_t)probe.nbase * c->base_stride * 16);
+  c->mix_stride = (long long)(align_up((size_t)(nx / 2) * (3 * ny / 2) * cs) / cs);
+  c->off_mix = off;
+  off = align_up(off + (size_t)probe.nmix * c->mix_stride * cs);
+  c->total = off;
+}
+
+template <typename real>
+std::vector<cpx<real>> twiddles(int n) {
+  std::vector<cpx<real>> t(n);
+  for (int j = 0; j < n; ++j) {
+    const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)n;
+    t[j] = {(real)cosl(a), (real)sinl(a)};
+  }
+  return t;
+}
+
+int upload(zk_ctx *c, double dt) {
+  if (!c->bound) return fail(c, ZK_ENOWS, "workspace not bound");
+  const bool need = !c->have_plan || c->dirty || !(dt == c->plan_dt || (std::isnan(dt) && std::isnan(c->plan_dt)));
+  if (!need) return ZK_OK;
+  try {
+    c->plan = build_plan(c->pp, std::isnan(dt) ? 1.0 : dt);
+  } catch (const std::exception &e) {
+    return fail(c, ZK_EINVAL, std::string("plan: ") + e.what());
+  }
+  const std::string v = validate_plan(c->plan, 3 * c->pp.ny / 2, c->pp.ny);
+  if (!v.empty()) return fail(c, ZK_EINVAL, "plan validation: " + v);
+  const Plan &p = c->plan;
+  if (p.ops.size() > c->sched_cap[0] || p.progs.size() > c->sched_cap[1] || p.terms.size() > c->sched_cap[2] ||
+      p.outs.size() > c->sched_cap[3] || p.tasks.size() > c->sched_cap[4])
+    return fail(c, ZK_EINVAL, "schedule exceeds reserved capacity");
+  HIP_TRY(c, hipSetDevice(c->device));
+  auto put = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+    if (!bytes) return hipSuccess;
+    return hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream);
+  };
+  HIP_TRY(c, put(c->off_ops, p.ops.data(), p.ops.size() * sizeof(RowOp)));
+  HIP_TRY(c, put(c->off_progs, p.progs.data(), p.progs.size() * sizeof(RowProg)));
+  HIP_TRY(c, put(c->off_terms, p.terms.data(), p.terms.size() * sizeof(ColTerm)));
+  HIP_TRY(c, put(c->off_outs, p.outs.data(), p.outs.size() * sizeof(ColOut)));
+  HIP_TRY(c, put(c->off_tasks, p.tasks.data(), p.tasks.size() * sizeof(ColTask)));
+  if (c->dirty) {
+    const int nx = c->pp.nx, ny = c->pp.ny;
+    const int lens[4] = {3 * nx / 2, nx, 3 * ny / 2, ny};
+    for (int i = 0; i < 4; ++i) {
+      if (c->precision == 32) {
+        auto t = twiddles<float>(lens[i]);
+        HIP_TRY(c, put(c->off_tw[i], t.data(), t.size() * sizeof(t[0])));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+      } else {
+        auto t = twiddles<double>(lens[i]);
+        HIP_TRY(c, put(c->off_tw[i], t.data(), t.size() * sizeof(t[0])));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+      }
+    }
+  }
+  HIP_TRY(c, hipStreamSynchronize(c->stream));  // host vectors may change after return
+  c->plan_dt = dt;
+  c->have_plan = true;
+  c->dirty = false;
+  return ZK_OK;
+}
+
+struct Phys {
+  const double *in0 = nullptr, *in1 = nullptr;
+  double *out0 = nullptr, *out1 = nullptr;
+};
+
+template <typename real>
+int run_seq_t(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
+  const int nx = c->pp.nx, ny = c->pp.ny;
+  const int Tx = nx / 8, Ty = ny / 8;
+  char *ws = c->ws;
+  auto twp = [&](int i) { return reinterpret_cast<const cpx<real> *>(ws + c->off_tw[i]); };
+  cpx<real> *mix = reinterpret_cast<cpx<real> *>(ws + c->off_mix);
+  cpx<double> *base = reinterpret_cast<cpx<double> *>(ws + c->off_base);
+  const double kc = 2.0 / 3.0 * std::min(M_PI * nx / c->pp.Lx, M_PI * ny / c->pp.Ly);
+  for (const Launch &l : seq) {
+    hipError_t e = hipSuccess;
+    zk_ctx::Rec rec{l.kind, l.bytes, l.flops, nullptr, nullptr};
+    if (c->prof) {
+      HIP_TRY(c, take_event(c, &rec.a));
+      HIP_TRY(c, take_event(c, &rec.b));
+      HIP_TRY(c, hipEventRecord(rec.a, c->stream));
+    }
+    if (l.kind == L_ROW_PAD || l.kind == L_ROW_BASE) {
+      const bool pad = l.kind == L_ROW_PAD;
+      RowArgs<real> a{};
+      a.ops = reinterpret_cast<const RowOp *>(ws + c->off_ops);
+      a.progs = reinterpret_cast<const RowProg *>(ws + c->off_progs);
+      a.prog0 = l.first;
+      a.mix = mix;
+      a.mix_stride = c->mix_stride;
+      a.rows = pad ? 3 * ny / 2 : ny;
+      a.nx = nx;
+      a.pin0 = ph.in0;
+      a.pin1 = ph.in1;
+      a.pout0 = ph.out0;
+      a.pout1 = ph.out1;
+      a.tw = twp(pad ? 0 : 1);
+      a.kx_scale = 2.0 * M_PI / c->pp.Lx;
+      const int rpb = 256 / Tx;
+      if (a.rows % rpb) return fail(c, ZK_EINVAL, "row blocking");
+      e = launch_row<real>(a, Tx, pad ? 12 : 8, a.rows / rpb, l.count, c->stream);
+    } else if (l.kind == L_COL_PAD || l.kind == L_COL_BASE) {
+      const bool pad = l.kind == L_COL_PAD;
+      ColArgs<real> a{};
+      a.tasks = reinterpret_cast<const ColTask *>(ws + c->off_tasks);
+      a.task0 = l.first;
+      a.outs = reinterpret_cast<const ColOut *>(ws + c->off_outs);
+      a.terms = reinterpret_cast<const ColTerm *>(ws + c->off_terms);
+      a.mix = mix;
+      a.mix_stride = c->mix_stride;
+      a.rows = pad ? 3 * ny / 2 : ny;
+      a.base = base;
+      a.base_stride = c->base_stride;
+      a.ny = ny;
+      a.nx = nx;
+      a.tw = twp(pad ? 2 : 3);
+      a.kx_scale = 2.0 * M_PI / c->pp.Lx;
+      a.ky_scale = 2.0 * M_PI / c->pp.Ly;
+      a.depth = c->pp.depth;
+      a.inv_kc = 1.0 / kc;
+      a.taper_on = c->pp.taper ? 1 : 0;
+      const int cpb = std::min(4, 256 / Ty);
+      const int ncols = nx / 2;
+      if (ncols % cpb) return fail(c, ZK_EINVAL, "column blocking");
+      e = launch_col<real>(a, Ty, pad ? 12 : 8, ncols / cpb, l.count, c->stream);
+    } else if (l.kind == L_PARSEVAL) {
+      double *red = reinterpret_cast<double *>(ws + c->off_red);
+      e = launch_parseval(base + (long long)l.first * c->base_stride, base + (long long)l.count * c->base_stride,
+                          base + (long long)l.c2 * c->base_stride, base + (long long)l.d2 * c->base_stride, nx / 2, ny,
+                          red, red + 2 * kRedBlocks, c->stream);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+    if (c->prof) {
+      HIP_TRY(c, hipEventRecord(rec.b, c->stream));
+      c->pending.push_back(rec);
+      if (c->pending.size() >= 4096) {
+        const int rc = flush_prof(c);
+        if (rc) return rc;
+      }
+    }
+  }
+  return ZK_OK;
+}
+
+int run_seq(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
+  return c->precision == 32 ? run_seq_t<float>(c, seq, ph) : run_seq_t<double>(c, seq, ph);
+}
+
+int check_call(zk_ctx *c) {
+  if (!c) return ZK_EINVAL;
+  c->err.clear();
+  if (!c->bound) return fail(c, ZK_ENOWS, "workspace not bound (call zk_bind)");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(c, e, "hipSetDevice");
+  return ZK_OK;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+zk_ctx *zk_create(int nx, int ny, double Lx, double Ly, double depth, double g, int M) {
+  if (!pow2_in(nx) || !pow2_in(ny)) return nullptr;
+  if (!(Lx > 0) || !(Ly > 0) || !(g > 0) || M < 1 || M > 8) return nullptr;
+  zk_ctx *c = new (std::nothrow) zk_ctx();
+  if (!c) return nullptr;
+  c->pp.nx = nx;
+  c->pp.ny = ny;
+  c->pp.Lx = Lx;
+  c->pp.Ly = Ly;
+  c->pp.depth = (std::isfinite(depth) && depth > 0) ? depth : 0.0;
+  c->pp.g = g;
+  c->pp.M = M;
+  c->pp.eps = 1.0;
+  c->pp.taper = true;
+  c->pp.filt = true;
+  c->pp.real_bytes = 8;
+  try {
+    compute_layout(c);
+  } catch (...) {
+    delete c;
+    return nullptr;
+  }
+  return c;
+}
+
+void zk_destroy(zk_ctx *c) { delete c; }
+
+int zk_set_option(zk_ctx *c, int key, double v) {
+  if (!c) return ZK_EINVAL;
+  c->err.clear();
+  switch (key) {
+    case ZK_OPT_EPS:
+      if (!(v >= 0.0 && v <= 1.0)) return fail(c, ZK_EINVAL, "eps must be in [0, 1]");
+      c->pp.eps = v;
+      break;
+    case ZK_OPT_TAPER:
+      c->pp.taper = v != 0.0;
+      break;
+    case ZK_OPT_FILTER:
+      c->pp.filt = v != 0.0;
+      break;
+    case ZK_OPT_PRECISION:
+      if (v != 32.0 && v != 64.0) return fail(c, ZK_EINVAL, "precision must be 32 or 64");
+      if (c->bound && (int)v != c->precision) return fail(c, ZK_EINVAL, "set precision before zk_bind");
+      c->precision = (int)v;
+      c->pp.real_bytes = c->precision == 32 ? 4 : 8;
+      compute_layout(c);
+      break;
+    case ZK_OPT_CHECK:
+      c->check = v != 0.0;
+      return ZK_OK;
+    case ZK_OPT_PROFILE:
+      c->prof = v != 0.0;
+      return ZK_OK;
+    default:
+      return fail(c, ZK_EINVAL, "unknown option");
+  }
+  c->dirty = true;
+  c->have_plan = false;
+  return ZK_OK;
+}
+
+size_t zk_workspace_bytes(const zk_ctx *c) { return c ? c->total : 0; }
+
+int zk_bind(zk_ctx *c, void *ws, size_t bytes, void *stream) {
+  if (!c) return ZK_EINVAL;
+  c->err.clear();
+  if (!ws || ((uintptr_t)ws % kAlign) != 0) return fail(c, ZK_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < c->total) return fail(c, ZK_ENOWS, "workspace smaller than zk_workspace_bytes");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
+  c->ws = static_cast<char *>(ws);
+  c->ws_bytes = bytes;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->device = dev;
+  c->bound = true;
+  c->dirty = true;
+  c->have_plan = false;
+  return upload(c, NAN);
+}
+
+int zk_dtn(zk_ctx *c, const double *eta, const double *psi, double *G) {
+  int rc = check_call(c);
+  if (rc) return rc;
+  if (!eta || !psi || !G || !aligned16(eta) || !aligned16(psi) || !aligned16(G))
+    return fail(c, ZK_EINVAL, "null or misaligned field pointer");
+  if ((rc = upload(c, c->have_plan ? c->plan_dt : NAN))) return rc;
+  Phys ph;
+  ph.in0 = eta;
+  ph.in1 = psi;
+  ph.out0 = G;
+  return run_seq(c, c->plan.dtn, ph);
+}
+
+int zk_rhs(zk_ctx *c, const double *eta, const double *psi, double *eta_t, double *psi_t) {
+  int rc = check_call(c);
+  if (rc) return rc;
+  if (!eta || !psi || !eta_t || !psi_t || !aligned16(eta) || !aligned16(psi) || !aligned16(eta_t) ||
+      !aligned16(psi_t))
+    return fail(c, ZK_EINVAL, "null or misaligned field pointer");
+  if ((rc = upload(c, c->have_plan ? c->plan_dt : NAN))) return rc;
+  Phys ph;
+  ph.in0 = eta;
+  ph.in1 = psi;
+  ph.out0 = eta_t;
+  ph.out1 = psi_t;
+  return run_seq(c, c->plan.rhs, ph);
+}
+
+int zk_step(zk_ctx *c, double *eta, double *psi, double dt, int nsteps) {
+  int rc = check_call(c);
+  if (rc) return rc;
+  if (!eta || !psi || !aligned16(eta) || !aligned16(psi)) return fail(c, ZK_EINVAL, "null or misaligned field pointer");
+  if (!(std::isfinite(dt)) || nsteps < 0) return fail(c, ZK_EINVAL, "dt must be finite and nsteps >= 0");
+  if (nsteps == 0) return ZK_OK;
+  if ((rc = upload(c, dt))) return rc;
+  Phys ph;
+  ph.in0 = eta;
+  ph.in1 = psi;
+  ph.out0 = eta;
+  ph.out1 = psi;
+  const Plan &p = c->plan;
+  if ((rc = run_seq(c, p.step_entry, ph))) return rc;
+  for (int i = 0; i < nsteps; ++i) {
+    const int par = i & 1;
+    if ((rc = run_seq(c, p.step_body[par], ph))) return rc;
+    if (i + 1 < nsteps && (rc = run_seq(c, p.step_lift[1 - par], ph))) return rc;
+  }
+  const int fin = nsteps & 1;
+  if ((rc = run_seq(c, p.step_exit[fin], ph))) return rc;
+  if (c->check) {
+    std::vector<Launch> chk{Launch{L_PARSEVAL, p.chk_e[fin], p.chk_e[fin], p.chk_p[fin], p.chk_p[fin], 0.0, 0.0}};
+    if ((rc = run_seq(c, chk, ph))) return rc;
+    double h[2] = {0, 0};
+    HIP_TRY(c, hipMemcpyAsync(h, c->ws + c->off_red + 2 * kRedBlocks * sizeof(double), sizeof(h),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (!std::isfinite(h[0]) || !std::isfinite(h[1])) return fail(c, ZK_EDIVERGED, "state is not finite");
+  }
+  return ZK_OK;
+}
+
+int zk_hamiltonian(zk_ctx *c, const double *eta, const double *psi, double *H) {
+  int rc = check_call(c);
+  if (rc) return rc;
+  if (!eta || !psi || !H || !aligned16(eta) || !aligned16(psi)) return fail(c, ZK_EINVAL, "null or misaligned pointer");
+  if ((rc = upload(c, c->have_plan ? c->plan_dt : NAN))) return rc;
+  Phys ph;
+  ph.in0 = eta;
+  ph.in1 = psi;
+  if ((rc = run_seq(c, c->plan.ham, ph))) return rc;
+  double h[2] = {0, 0};
+  HIP_TRY(c, hipMemcpyAsync(h, c->ws + c->off_red + 2 * kRedBlocks * sizeof(double), sizeof(h),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const double N = (double)c->pp.nx * c->pp.ny;
+  const double dA = c->pp.Lx * c->pp.Ly / N;
+  *H = 0.5 * dA * h[0] / N + 0.5 * c->pp.g * dA * h[1] / N;
+  return ZK_OK;
+}
+
+int zk_kernel_stats(zk_ctx *c, int kind, double *ms, double *bytes, double *flops, long long *launches) {
+  if (!c) return ZK_EINVAL;
+  c->err.clear();
+  if (c->bound) {
+    const int rc = flush_prof(c);
+    if (rc) return rc;
+  }
+  if (kind == -1) {
+    for (int k = 0; k < 5; ++k) {
+      c->st_ms[k] = c->st_bytes[k] = c->st_flops[k] = 0.0;
+      c->st_n[k] = 0;
+    }
+    return ZK_OK;
+  }
+  if (kind < 0 || kind > 4 || !ms || !bytes || !flops || !launches) return fail(c, ZK_EINVAL, "bad kind or output");
+  *ms = c->st_ms[kind];
+  *bytes = c->st_bytes[kind];
+  *flops = c->st_flops[kind];
+  *launches = c->st_n[kind];
+  return ZK_OK;
+}
+
+const char *zk_last_error(const zk_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,267 @@
+// zk_fft.hpp -- register-resident Stockham FFT for one team of T threads.
+//
+// A team transforms one sequence of N = E * T complex points.  Thread t holds
+// the E elements t + T*r in registers on entry and the E outputs t + T*q on
+// exit, so a pointwise operation between two transforms never needs a data
+// exchange.  The first pass is a radix-E butterfly entirely in registers
+// (E = 12 = 3 * 4 for the 3/2-padded lengths 3*2^k, E = 8 for the base
+// lengths 2^k); the remaining passes are radix-8/4/2 butterflies with one LDS
+// exchange each (Stockham autosort: natural order in, natural order out).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+namespace zk {
+
+template <typename R>
+struct cpx {
+  R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ cpx<R> cadd(cpx<R> a, cpx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> csub(cpx<R> a, cpx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename R>
+__device__ __forceinline__ cpx<R> cscale(cpx<R> a, R s) { return {a.x * s, a.y * s}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cconj(cpx<R> a) { return {a.x, -a.y}; }
+// multiply by (DIR * i)
+template <int DIR, typename R>
+__device__ __forceinline__ cpx<R> mul_diri(cpx<R> a) {
+  if constexpr (DIR > 0) return {-a.y, a.x};
+  else return {a.y, -a.x};
+}
+
+// cos and sin of 2 pi j / 48 (quarter turns are special-cased exactly)
+__host__ __device__ constexpr double cos48(int j) {
+  constexpr double tab[48] = {
+    1, 0.99144486137381038, 0.96592582628906831, 0.92387953251128674,
+    0.8660254037844386, 0.79335334029123517, 0.70710678118654757, 0.60876142900872066,
+    0.5, 0.38268343236508978, 0.25881904510252074, 0.1305261922200516,
+    0, -0.1305261922200516, -0.25881904510252074, -0.38268343236508978,
+    -0.5, -0.60876142900872066, -0.70710678118654757, -0.79335334029123517,
+    -0.8660254037844386, -0.92387953251128674, -0.96592582628906831, -0.99144486137381038,
+    -1, -0.99144486137381038, -0.96592582628906831, -0.92387953251128674,
+    -0.8660254037844386, -0.79335334029123517, -0.70710678118654757, -0.60876142900872066,
+    -0.5, -0.38268343236508978, -0.25881904510252074, -0.1305261922200516,
+    0, 0.1305261922200516, 0.25881904510252074, 0.38268343236508978,
+    0.5, 0.60876142900872066, 0.70710678118654757, 0.79335334029123517,
+    0.8660254037844386, 0.92387953251128674, 0.96592582628906831, 0.99144486137381038};
+  return tab[j];
+}
+__host__ __device__ constexpr double sin48(int j) {
+  constexpr double tab[48] = {
+    0, 0.1305261922200516, 0.25881904510252074, 0.38268343236508978,
+    0.5, 0.60876142900872066, 0.70710678118654757, 0.79335334029123517,
+    0.8660254037844386, 0.92387953251128674, 0.96592582628906831, 0.99144486137381038,
+    1, 0.99144486137381038, 0.96592582628906831, 0.92387953251128674,
+    0.8660254037844386, 0.79335334029123517, 0.70710678118654757, 0.60876142900872066,
+    0.5, 0.38268343236508978, 0.25881904510252074, 0.1305261922200516,
+    0, -0.1305261922200516, -0.25881904510252074, -0.38268343236508978,
+    -0.5, -0.60876142900872066, -0.70710678118654757, -0.79335334029123517,
+    -0.8660254037844386, -0.92387953251128674, -0.96592582628906831, -0.99144486137381038,
+    -1, -0.99144486137381038, -0.96592582628906831, -0.92387953251128674,
+    -0.8660254037844386, -0.79335334029123517, -0.70710678118654757, -0.60876142900872066,
+    -0.5, -0.38268343236508978, -0.25881904510252074, -0.1305261922200516};
+  return tab[j];
+}
+
+// a * exp(DIR * 2 pi i * M / NN) for compile-time M, NN (48 % NN == 0)
+template <int M, int NN, int DIR, typename R>
+__device__ __forceinline__ cpx<R> twc(cpx<R> a) {
+  constexpr int mm = ((M % NN) + NN) % NN;
+  if constexpr (mm == 0) {
+    return a;
+  } else if constexpr (4 * mm == NN) {
+    return mul_diri<DIR>(a);
+  } else if constexpr (2 * mm == NN) {
+    return {-a.x, -a.y};
+  } else if constexpr (4 * mm == 3 * NN) {
+    return mul_diri<-DIR>(a);
+  } else {
+    static_assert(48 % NN == 0, "twiddle base must divide 48");
+    constexpr int j = mm * (48 / NN);
+    constexpr double cd = cos48(j);
+    constexpr double sd = DIR * sin48(j);
+    const R c = (R)cd;
+    const R s = (R)sd;
+    return {a.x * c - a.y * s, a.x * s + a.y * c};
+  }
+}
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// In-register DFT of R points, x[k] <- sum_n x[n] exp(DIR 2 pi i n k / R).
+template <int RR, int DIR, typename R>
+struct DFT;
+
+template <int DIR, typename R>
+struct DFT<2, DIR, R> {
+  __device__ __forceinline__ static void run(cpx<R> *x) {
+    cpx<R> a = cadd(x[0], x[1]), b = csub(x[0], x[1]);
+    x[0] = a;
+    x[1] = b;
+  }
+};
+
+template <int DIR, typename R>
+struct DFT<3, DIR, R> {
+  __device__ __forceinline__ static void run(cpx<R> *x) {
+    const R h = (R)0.8660254037844386;  // sqrt(3)/2
+    cpx<R> t1 = cadd(x[1], x[2]);
+    cpx<R> d = csub(x[1], x[2]);
+    cpx<R> t2 = mul_diri<DIR>(cscale(d, h));
+    cpx<R> m = {x[0].x - (R)0.5 * t1.x, x[0].y - (R)0.5 * t1.y};
+    x[0] = cadd(x[0], t1);
+    x[1] = cadd(m, t2);
+    x[2] = csub(m, t2);
+  }
+};
+
+template <int DIR, typename R>
+struct DFT<4, DIR, R> {
+  __device__ __forceinline__ static void run(cpx<R> *x) {
+    cpx<R> a0 = cadd(x[0], x[2]), a1 = csub(x[0], x[2]);
+    cpx<R> a2 = cadd(x[1], x[3]), a3 = mul_diri<DIR>(csub(x[1], x[3]));
+    x[0] = cadd(a0, a2);
+    x[2] = csub(a0, a2);
+    x[1] = cadd(a1, a3);
+    x[3] = csub(a1, a3);
+  }
+};
+
+// Composite RR = A * B, A in {4, 2, 3}:  n = B n1 + n2, k = k1 + A k2,
+// X[k1 + A k2] = sum_n2 W_RR^(n2 k1) W_B^(n2 k2) [sum_n1 x[B n1 + n2] W_A^(n1 k1)].
+template <int RR, int DIR, typename R>
+struct DFT {
+  static constexpr int A = (RR % 4 == 0) ? 4 : ((RR % 2 == 0) ? 2 : 3);
+  static constexpr int B = RR / A;
+  __device__ __forceinline__ static void run(cpx<R> *x) {
+    cpx<R> y[B][A];
+    static_for<0, B>([&](auto n2c) {
+      constexpr int n2 = decltype(n2c)::value;
+      cpx<R> t[A];
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) t[n1] = x[B * n1 + n2];
+      DFT<A, DIR, R>::run(t);
+      static_for<0, A>([&](auto k1c) {
+        constexpr int k1 = decltype(k1c)::value;
+        y[n2][k1] = twc<n2 * k1, RR, DIR>(t[k1]);
+      });
+    });
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      cpx<R> t[B];
+#pragma unroll
+      for (int n2 = 0; n2 < B; ++n2) t[n2] = y[n2][k1];
+      DFT<B, DIR, R>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) x[k1 + A * k2] = t[k2];
+    }
+  }
+};
+
+// ---- pass plan ----------------------------------------------------------
+__host__ __device__ constexpr int next_radix(int E, int rem) {
+  const int big = (E % 8 == 0) ? 8 : 4;
+  return (rem % big == 0) ? big : ((rem % 4 == 0 && E % 4 == 0) ? 4 : 2);
+}
+__host__ __device__ constexpr int num_passes(int E, int T) {
+  int n = 1, rem = T;
+  while (rem > 1) {
+    rem /= next_radix(E, rem);
+    ++n;
+  }
+  return n;
+}
+__host__ __device__ constexpr int pass_radix(int E, int T, int p) {
+  if (p == 0) return E;
+  int rem = T;
+  for (int i = 1; i < p; ++i) rem /= next_radix(E, rem);
+  return next_radix(E, rem);
+}
+__host__ __device__ constexpr int pass_ns(int E, int T, int p) {
+  int ns = 1;
+  for (int i = 0; i < p; ++i) ns *= pass_radix(E, T, i);
+  return ns;
+}
+
+// LDS index with one pad slot every 16 elements (spreads strided accesses over banks)
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lds_len(int N) { return N + N / 16 + 1; }
+
+// Team FFT: v[r] holds element t + T*r on entry, element t + T*r of the
+// transform on exit (unnormalised, sign DIR).  tw[i] = exp(-2 pi i * i / N).
+// Every thread of the block must call it (it contains __syncthreads); lds is
+// this team's private region of lds_len(N) elements.
+template <typename R, int N, int E, int DIR>
+__device__ __forceinline__ void team_fft(cpx<R> (&v)[E], cpx<R> *lds, const cpx<R> *__restrict__ tw, int t) {
+  constexpr int T = N / E;
+  constexpr int NP = num_passes(E, T);
+  static_assert(NP >= 2, "team FFT needs at least two passes");
+  DFT<E, DIR, R>::run(v);
+  static_for<1, NP>([&](auto pc) {
+    constexpr int p = decltype(pc)::value;
+    constexpr int Rp = pass_radix(E, T, p);
+    constexpr int Rq = pass_radix(E, T, p - 1);
+    constexpr int Nsq = pass_ns(E, T, p - 1);
+    constexpr int Ns = pass_ns(E, T, p);
+    __syncthreads();
+    if constexpr (p == 1) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) lds[lpad(t * E + e)] = v[e];
+    } else {
+#pragma unroll
+      for (int m = 0; m < E / Rq; ++m) {
+        const int j = t + T * m;
+        const int k = j % Nsq;
+        const int base = (j / Nsq) * Nsq * Rq + k;
+#pragma unroll
+        for (int r = 0; r < Rq; ++r) lds[lpad(base + r * Nsq)] = v[m * Rq + r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E / Rp; ++m) {
+      const int j = t + T * m;
+#pragma unroll
+      for (int r = 0; r < Rp; ++r) v[m * Rp + r] = lds[lpad(j + r * (N / Rp))];
+    }
+#pragma unroll
+    for (int m = 0; m < E / Rp; ++m) {
+      const int j = t + T * m;
+      const int k = j % Ns;
+      constexpr int step = N / (Ns * Rp);
+#pragma unroll
+      for (int r = 1; r < Rp; ++r) {
+        cpx<R> w = tw[r * k * step];
+        if constexpr (DIR > 0) w.y = -w.y;
+        v[m * Rp + r] = cmul(v[m * Rp + r], w);
+      }
+      DFT<Rp, DIR, R>::run(&v[m * Rp]);
+    }
+  });
+  constexpr int Rl = pass_radix(E, T, NP - 1);
+  constexpr int nbl = E / Rl;
+  cpx<R> o[E];
+#pragma unroll
+  for (int m = 0; m < nbl; ++m)
+#pragma unroll
+    for (int r = 0; r < Rl; ++r) o[m + r * nbl] = v[m * Rl + r];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = o[e];
+}
+
+}  // namespace zk

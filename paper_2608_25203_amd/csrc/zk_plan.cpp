@@ -1,0 +1,646 @@
+// zk_plan.cpp -- host planner (pure C++; no device code).
+#include "zk_plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <stdexcept>
+#include <utility>
+
+namespace zk {
+namespace {
+
+constexpr int kMaxM = 8;
+
+struct Fac {  // a factor of a product: mixed field id and x-derivative flag
+  int f;
+  uint8_t fl;
+  bool operator==(const Fac &o) const { return f == o.f && fl == o.fl; }
+  bool operator<(const Fac &o) const { return f < o.f || (f == o.f && fl < o.fl); }
+};
+
+struct Prod {
+  Fac a, b;
+  int out;  // logical output index inside the program
+  double coef;
+};
+
+struct TermSpec {
+  int src;
+  uint32_t sym;
+  double coef;
+};
+
+struct OutSpec {
+  int dst_base = -1, dst_mixed = -1;
+  std::vector<TermSpec> terms;
+  double lift_coef = 1.0;
+};
+
+struct TaskSpec {
+  int fwd = -1;
+  uint32_t fwd_sym = 0;
+  double fwd_coef = 1.0;
+  std::vector<OutSpec> outs;
+};
+
+class Builder {
+ public:
+  explicit Builder(const PlanParams &pp) : pp_(pp) {
+    M = pp.M;
+    const double N = (double)pp.nx * pp.ny;
+    const double Np = (1.5 * pp.nx) * (1.5 * pp.ny);
+    inv_n = 1.0 / N;
+    fold = N / Np;
+  }
+
+  Plan P;
+  int M;
+  double inv_n, fold;
+
+  int mix() { return P.nmix++; }
+  int base() { return P.nbase++; }
+
+  // ---- row programs --------------------------------------------------------
+  int prog_begin() {
+    P.progs.push_back({(int32_t)P.ops.size(), 0});
+    return (int)P.progs.size() - 1;
+  }
+  void op(uint8_t code, uint8_t a, uint8_t b, uint8_t c, int fa, uint8_t fla, int fb, uint8_t flb, double coef) {
+    RowOp o{};
+    o.code = code;
+    o.a = a;
+    o.b = b;
+    o.c = c;
+    o.fla = fla;
+    o.flb = flb;
+    o.fa = fa;
+    o.fb = fb;
+    o.coef = coef;
+    P.ops.push_back(o);
+    P.progs.back().nop++;
+  }
+  void ld2(Fac x, int y_f, uint8_t y_fl) { op(OP_LD2, 0, 0, 0, x.f, x.fl, y_f, y_fl, 0.0); }
+  void mac(int out, uint8_t x, uint8_t y, double c) { op(OP_MAC, (uint8_t)(RS_O0 + out), x, y, -1, 0, -1, 0, c); }
+
+  // One program computing sum-of-products outputs (at most 3) and storing
+  // them to the mixed fields outf[].  Greedy: take the factor shared by the
+  // most products, load it with its first partner, hold it in A, then load
+  // the remaining partners in pairs.
+  int product_program(std::vector<Prod> prods, const std::vector<int> &outf) {
+    if (outf.empty() || outf.size() > 3) throw std::runtime_error("program outputs");
+    const int pg = prog_begin();
+    for (size_t k = 0; k < outf.size(); ++k) op(OP_ZERO, (uint8_t)(RS_O0 + k), 0, 0, -1, 0, -1, 0, 0.0);
+    while (!prods.empty()) {
+      std::map<Fac, int> cnt;
+      for (auto &p : prods) {
+        cnt[p.a]++;
+        if (!(p.b == p.a)) cnt[p.b]++;
+      }
+      Fac x = prods[0].a;
+      int best = -1;
+      for (auto &kv : cnt)
+        if (kv.second > best) {
+          best = kv.second;
+          x = kv.first;
+        }
+      std::vector<Prod> nonself, self, rest;
+      std::vector<Prod> keep;
+      for (auto &p : prods) {
+        if (p.a == x && p.b == x) self.push_back(p);
+        else if (p.a == x) nonself.push_back(p);
+        else if (p.b == x) nonself.push_back({p.b, p.a, p.out, p.coef});
+        else keep.push_back(p);
+      }
+      if (!nonself.empty()) {
+        const Prod &f = nonself[0];
+        ld2(x, f.b.f, f.b.fl);
+        mac(f.out, RS_U, RS_V, f.coef);
+        rest.assign(nonself.begin() + 1, nonself.end());
+      } else {
+        ld2(x, -1, 0);
+      }
+      if (!self.empty() || !rest.empty()) op(OP_MOV, RS_A, RS_U, 0, -1, 0, -1, 0, 0.0);
+      for (auto &p : self) mac(p.out, RS_A, RS_A, p.coef);
+      for (size_t i = 0; i < rest.size(); i += 2) {
+        if (i + 1 < rest.size()) {
+          ld2(rest[i].b, rest[i + 1].b.f, rest[i + 1].b.fl);
+          mac(rest[i].out, RS_A, RS_U, rest[i].coef);
+          mac(rest[i + 1].out, RS_A, RS_V, rest[i + 1].coef);
+        } else {
+          ld2(rest[i].b, -1, 0);
+          mac(rest[i].out, RS_A, RS_U, rest[i].coef);
+        }
+      }
+      prods.swap(keep);
+    }
+    for (size_t k = 0; k < outf.size(); k += 2) {
+      if (k + 1 < outf.size())
+        op(OP_ST2, (uint8_t)(RS_O0 + k), (uint8_t)(RS_O0 + k + 1), 0, outf[k], 0, outf[k + 1], 0, 0.0);
+      else
+        op(OP_ST2, (uint8_t)(RS_O0 + k), RS_NONE, 0, outf[k], 0, -1, 0, 0.0);
+    }
+    return pg;
+  }
+
+  // ---- column tasks --------------------------------------------------------
+  void add_tasks(const std::vector<TaskSpec> &ts) {
+    for (auto &t : ts) {
+      ColTask ct{};
+      ct.fwd = t.fwd;
+      ct.fwd_sym = t.fwd_sym;
+      ct.fwd_coef = t.fwd_coef;
+      ct.o0 = (int32_t)P.outs.size();
+      ct.no = (int32_t)t.outs.size();
+      for (auto &o : t.outs) {
+        ColOut co{};
+        co.dst_base = o.dst_base;
+        co.dst_mixed = o.dst_mixed;
+        co.t0 = (int32_t)P.terms.size();
+        co.nt = (int32_t)o.terms.size();
+        co.lift_coef = o.lift_coef;
+        for (auto &tm : o.terms) P.terms.push_back({tm.src, tm.sym, tm.coef});
+        P.outs.push_back(co);
+      }
+      P.tasks.push_back(ct);
+    }
+  }
+  Launch col_launch(int kind, const std::vector<TaskSpec> &ts) {
+    Launch l{kind, (int)P.tasks.size(), (int)ts.size(), 0, 0, 0.0, 0.0};
+    add_tasks(ts);
+    return l;
+  }
+  OutSpec lift(int dst_mixed, std::vector<TermSpec> terms) {
+    OutSpec o;
+    o.dst_mixed = dst_mixed;
+    o.terms = std::move(terms);
+    o.lift_coef = inv_n;
+    return o;
+  }
+  OutSpec store(int dst_base, std::vector<TermSpec> terms) {
+    OutSpec o;
+    o.dst_base = dst_base;
+    o.terms = std::move(terms);
+    return o;
+  }
+  TaskSpec fold_task(int fwd) {  // fold of a dealiased product
+    TaskSpec t;
+    t.fwd = fwd;
+    t.fwd_sym = SYM_TAPER;
+    t.fwd_coef = fold;
+    return t;
+  }
+
+ private:
+  PlanParams pp_;
+};
+
+double fact(int l) {
+  double f = 1.0;
+  for (int i = 2; i <= l; ++i) f *= i;
+  return f;
+}
+
+}  // namespace
+
+Plan build_plan(const PlanParams &pp, double dt) {
+  if (pp.M < 1 || pp.M > kMaxM) throw std::runtime_error("M out of range");
+  Builder B(pp);
+  const int M = B.M;
+  const double eps = pp.eps, g = pp.g;
+  const uint32_t FILT = pp.filt ? SYM_FILT : 0u;
+  auto epow = [&](int j) { return std::pow(eps, (double)j); };
+  // Fields are stored in kref units so that the two real fields sharing one
+  // complex FFT have comparable magnitudes: lifted L_l fields divided by
+  // kref^l, eta and its powers multiplied by kref^l (dimensionless, like the
+  // slopes), the W products divided by kref.  The factors are undone in the
+  // product and fold coefficients.  kref = kNyq / 3, a fixed mid-band
+  // wavenumber.
+  const double kref = std::min(M_PI * pp.nx / pp.Lx, M_PI * pp.ny / pp.Ly) / 3.0;
+  auto kpow = [&](int l) { return std::pow(kref, (double)l); };
+
+  // ---- field ids -------------------------------------------------------------
+  const int mE = B.mix(), mEy = B.mix(), mP = B.mix(), mPy = B.mix();
+  int mL[kMaxM + 2], mEP[kMaxM + 2], mLPhi[kMaxM + 2][kMaxM + 2];
+  for (int l = 1; l <= M; ++l) mL[l] = B.mix();
+  for (int l = 2; l <= M - 1; ++l) mEP[l] = B.mix();
+  for (int m = 1; m <= M - 2; ++m)
+    for (int l = 1; l <= M - m; ++l) mLPhi[m][l] = B.mix();
+  const int mS = (M >= 3) ? B.mix() : -1;
+  const int mV = (M >= 4) ? B.mix() : -1;
+  const int mG = B.mix(), mN = B.mix();
+  const int oPHI = B.mix(), oWP = B.mix(), oEP = B.mix(), oS = B.mix(), oGX = B.mix();
+  const int mbA = B.mix(), mbB = B.mix();
+
+  int bUE[2], bUP[2], bSE[2], bSP[2];
+  for (int i = 0; i < 2; ++i) {
+    bUE[i] = B.base();
+    bUP[i] = B.base();
+  }
+  for (int i = 0; i < 2; ++i) {
+    bSE[i] = B.base();
+    bSP[i] = B.base();
+  }
+  const int bAE = B.base(), bAP = B.base(), bG = B.base(), bPT = B.base();
+  int bPHI[kMaxM + 2], bWP[kMaxM + 2], bGX[kMaxM + 2];
+  for (int r = 1; r <= M - 1; ++r) {
+    bPHI[r] = B.base();
+    bWP[r] = B.base();
+    bGX[r] = B.base();
+  }
+
+  auto etapow = [&](int l) { return Fac{l == 1 ? mE : mEP[l], 0}; };
+  auto lphi = [&](int m, int l) { return Fac{m == 0 ? mL[l] : mLPhi[m][l], 0}; };
+  const bool hasGX1 = M >= 2;
+  const bool hasGXlast = M >= 3;
+
+  // ---- row programs of the levels (state independent) ------------------------
+  std::vector<std::vector<int>> level_progs(M + 1);
+  for (int r = 1; r <= M - 1; ++r) {
+    // outputs of this level, in order
+    std::vector<int> outs;  // mixed ids
+    std::vector<std::vector<Prod>> pr;
+    auto out_index = [&](int fid) {
+      outs.push_back(fid);
+      pr.emplace_back();
+      return (int)outs.size() - 1;
+    };
+    const int iPHI = out_index(oPHI);
+    const int iWP = out_index(oWP);
+    const int iEP = (r + 1 <= M - 1) ? out_index(oEP) : -1;
+    const int iGX = ((r == 1 && hasGX1) || (r == M - 1 && hasGXlast)) ? out_index(oGX) : -1;
+    const int iS = (r == 1 && M >= 3) ? out_index(oS) : -1;
+    for (int l = 1; l <= r; ++l) {
+      pr[iPHI].push_back({etapow(l), lphi(r - l, l), 0, -1.0 / fact(l)});
+      pr[iWP].push_back({etapow(l), lphi(r - l, l + 1), 0, 1.0 / fact(l)});
+    }
+    if (iEP >= 0) pr[iEP].push_back({Fac{mE, 0}, etapow(r), 0, 1.0});
+    if (r == 1 && iGX >= 0) {
+      pr[iGX].push_back({Fac{mE, FL_DX}, Fac{mP, FL_DX}, 0, -eps / kref});
+      pr[iGX].push_back({Fac{mEy, 0}, Fac{mPy, 0}, 0, -eps});
+    }
+    if (iS >= 0) {
+      pr[iS].push_back({Fac{mE, FL_DX}, Fac{mE, FL_DX}, 0, 1.0 / (kref * kref)});
+      pr[iS].push_back({Fac{mEy, 0}, Fac{mEy, 0}, 0, 1.0});
+    }
+    if (r == M - 1 && hasGXlast) {
+      if (M == 3) pr[iGX].push_back({Fac{mS, 0}, Fac{mL[1], 0}, 0, eps * eps * kpow(1)});
+      else pr[iGX].push_back({Fac{mS, 0}, Fac{mV, 0}, 0, 1.0});
+    }
+    // group outputs by three: [PHI, WP, EP] [GX, S]
+    for (size_t k0 = 0; k0 < outs.size(); k0 += 3) {
+      std::vector<int> of;
+      std::vector<Prod> ps;
+      for (size_t k = k0; k < outs.size() && k < k0 + 3; ++k) {
+        of.push_back(outs[k]);
+        for (auto p : pr[k]) {
+          p.out = (int)(k - k0);
+          ps.push_back(p);
+        }
+      }
+      level_progs[r].push_back(B.product_program(ps, of));
+    }
+  }
+
+  // Bernoulli program: o0 = |grad eta|^2, o1 = grad eta . grad psi, o2 = |grad psi|^2
+  int bern_prog = B.prog_begin();
+  for (int k = 0; k < 3; ++k) B.op(OP_ZERO, (uint8_t)(RS_O0 + k), 0, 0, -1, 0, -1, 0, 0.0);
+  B.ld2(Fac{mE, FL_DX}, mP, FL_DX);
+  B.mac(0, RS_U, RS_U, 1.0 / (kref * kref));
+  B.mac(1, RS_U, RS_V, 1.0 / kref);
+  B.mac(2, RS_V, RS_V, 1.0);
+  B.ld2(Fac{mEy, 0}, mPy, 0);
+  B.mac(0, RS_U, RS_U, 1.0);
+  B.mac(1, RS_U, RS_V, 1.0);
+  B.mac(2, RS_V, RS_V, 1.0);
+  B.ld2(Fac{mG, 0}, -1, 0);
+  B.op(OP_BERN, 0, 0, 0, -1, 0, -1, 0, eps);
+  B.op(OP_ST2, RS_O0, RS_NONE, 0, mN, 0, -1, 0, 0.0);
+
+  // entry / exit programs on the base grid
+  const int entry_prog = B.prog_begin();
+  B.op(OP_LDP, 0, 0, 0, 0, 0, 1, 0, 0.0);
+  B.op(OP_ST2, RS_U, RS_V, 0, mbA, 0, mbB, 0, 0.0);
+  const int exit2_prog = B.prog_begin();
+  B.ld2(Fac{mbA, 0}, mbB, 0);
+  B.op(OP_STP, RS_U, 0, 0, 0, 0, -1, 0, 0.0);
+  B.op(OP_STP, RS_V, 0, 0, 1, 0, -1, 0, 0.0);
+  const int exit1_prog = B.prog_begin();
+  B.ld2(Fac{mbA, 0}, -1, 0);
+  B.op(OP_STP, RS_U, 0, 0, 0, 0, -1, 0, 0.0);
+
+  auto row_launch = [&](int kind, const std::vector<int> &progs) {
+    // programs of one launch must be contiguous
+    for (size_t i = 1; i < progs.size(); ++i)
+      if (progs[i] != progs[0] + (int)i) throw std::runtime_error("non-contiguous programs");
+    return Launch{kind, progs[0], (int)progs.size(), 0, 0, 0.0, 0.0};
+  };
+
+  // ---- column task builders -----------------------------------------------------
+  // lifts of the stage state (e, p) for level 1 (and G for M == 1)
+  auto l0_tasks = [&](int e, int p, bool lift_g) {
+    std::vector<TaskSpec> ts;
+    auto one = [&](OutSpec o) {
+      TaskSpec t;
+      t.outs.push_back(std::move(o));
+      ts.push_back(std::move(t));
+    };
+    one(B.lift(mE, {{e, 0, kref}}));
+    one(B.lift(mEy, {{e, SYM_IKY, 1.0}}));
+    one(B.lift(mP, {{p, 0, 1.0}}));
+    one(B.lift(mPy, {{p, SYM_IKY, 1.0}}));
+    for (int l = 1; l <= M; ++l) one(B.lift(mL[l], {{p, (uint32_t)l, 1.0 / kpow(l)}}));
+    if (M == 1) {
+      TaskSpec t;
+      t.outs.push_back(B.store(bG, {{p, 1u, 1.0}}));
+      if (lift_g) t.outs.push_back(B.lift(mG, {{p, 1u, 1.0}}));
+      ts.push_back(std::move(t));
+    }
+    return ts;
+  };
+  auto g_terms = [&](int p) {
+    std::vector<TermSpec> tm{{p, 1u, 1.0}};
+    for (int r = 1; r <= M - 1; ++r) {
+      tm.push_back({bPHI[r], 1u, epow(r)});
+      tm.push_back({bWP[r], 0u, epow(r)});
+    }
+    if (hasGX1) tm.push_back({bGX[1], 0u, 1.0});
+    if (hasGXlast && M - 1 != 1) tm.push_back({bGX[M - 1], 0u, 1.0});
+    return tm;
+  };
+  // levels 1..M-1 for stage state (e, p); ends with G stored (and lifted)
+  auto core = [&](std::vector<Launch> &seq, int e, int p, bool lift_g) {
+    (void)e;
+    for (int r = 1; r <= M - 1; ++r) {
+      seq.push_back(row_launch(L_ROW_PAD, level_progs[r]));
+      std::vector<TaskSpec> A;
+      {
+        TaskSpec t = B.fold_task(oPHI);
+        t.outs.push_back(B.store(bPHI[r], {{-1, 0, 1.0}}));
+        if (r <= M - 2)
+          for (int l = 1; l <= M - r; ++l) t.outs.push_back(B.lift(mLPhi[r][l], {{-1, (uint32_t)l, 1.0 / kpow(l)}}));
+        A.push_back(std::move(t));
+      }
+      {
+        TaskSpec t = B.fold_task(oWP);
+        t.fwd_coef *= kref;
+        t.outs.push_back(B.store(bWP[r], {{-1, 0, 1.0}}));
+        A.push_back(std::move(t));
+      }
+      if (r + 1 <= M - 1) {
+        TaskSpec t = B.fold_task(oEP);
+        t.outs.push_back(B.lift(mEP[r + 1], {{-1, 0, 1.0}}));
+        A.push_back(std::move(t));
+      }
+      if (r == 1 && M >= 3) {
+        TaskSpec t = B.fold_task(oS);
+        t.outs.push_back(B.lift(mS, {{-1, 0, 1.0}}));
+        A.push_back(std::move(t));
+      }
+      if ((r == 1 && hasGX1) || (r == M - 1 && hasGXlast)) {
+        TaskSpec t = B.fold_task(oGX);
+        t.outs.push_back(B.store(bGX[r], {{-1, 0, 1.0}}));
+        A.push_back(std::move(t));
+      }
+      if (r == M - 2 && M >= 4) {
+        std::vector<TermSpec> tm{{p, 1u, epow(2)}};
+        for (int i = 1; i <= M - 3; ++i) {
+          tm.push_back({bPHI[i], 1u, epow(i + 2)});
+          tm.push_back({bWP[i], 0u, epow(i + 2)});
+        }
+        TaskSpec t;
+        t.outs.push_back(B.lift(mV, tm));
+        A.push_back(std::move(t));
+      }
+      seq.push_back(B.col_launch(L_COL_PAD, A));
+    }
+    if (M >= 2) {
+      TaskSpec t;
+      t.outs.push_back(B.store(bG, g_terms(p)));
+      if (lift_g) t.outs.push_back(B.lift(mG, g_terms(p)));
+      seq.push_back(B.col_launch(L_COL_PAD, {t}));
+    }
+  };
+  auto entry = [&](std::vector<Launch> &seq) {
+    seq.push_back(row_launch(L_ROW_BASE, {entry_prog}));
+    std::vector<TaskSpec> ts(2);
+    ts[0].fwd = mbA;
+    ts[0].outs.push_back(B.store(bUE[0], {{-1, 0, 1.0}}));
+    ts[1].fwd = mbB;
+    ts[1].outs.push_back(B.store(bUP[0], {{-1, 0, 1.0}}));
+    seq.push_back(B.col_launch(L_COL_BASE, ts));
+  };
+  auto exit_seq = [&](std::vector<Launch> &seq, int a, int b) {
+    std::vector<TaskSpec> ts(b >= 0 ? 2 : 1);
+    ts[0].outs.push_back(B.lift(mbA, {{a, 0, 1.0}}));
+    if (b >= 0) ts[1].outs.push_back(B.lift(mbB, {{b, 0, 1.0}}));
+    seq.push_back(B.col_launch(L_COL_BASE, ts));
+    seq.push_back(row_launch(L_ROW_BASE, {b >= 0 ? exit2_prog : exit1_prog}));
+  };
+
+  Plan &P = B.P;
+  // zk_dtn
+  entry(P.dtn);
+  P.dtn.push_back(B.col_launch(L_COL_PAD, l0_tasks(bUE[0], bUP[0], false)));
+  core(P.dtn, bUE[0], bUP[0], false);
+  exit_seq(P.dtn, bG, -1);
+  // zk_hamiltonian
+  entry(P.ham);
+  P.ham.push_back(B.col_launch(L_COL_PAD, l0_tasks(bUE[0], bUP[0], false)));
+  core(P.ham, bUE[0], bUP[0], false);
+  P.ham.push_back(Launch{L_PARSEVAL, bUP[0], bG, bUE[0], bUE[0], 0.0, 0.0});
+  // zk_rhs
+  entry(P.rhs);
+  P.rhs.push_back(B.col_launch(L_COL_PAD, l0_tasks(bUE[0], bUP[0], true)));
+  core(P.rhs, bUE[0], bUP[0], true);
+  P.rhs.push_back(row_launch(L_ROW_PAD, {bern_prog}));
+  {
+    TaskSpec t = B.fold_task(mN);
+    t.outs.push_back(B.store(bPT, {{bUE[0], 0, -g}, {-1, 0, 1.0}}));
+    P.rhs.push_back(B.col_launch(L_COL_PAD, {t}));
+  }
+  exit_seq(P.rhs, bG, bPT);
+
+  // zk_step: RK4 stages, state U[par] -> U[1 - par]
+  entry(P.step_entry);
+  P.step_entry.push_back(B.col_launch(L_COL_PAD, l0_tasks(bUE[0], bUP[0], true)));
+  const double cnext[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};
+  const double wacc[4] = {1.0, 2.0, 2.0, 0.0};
+  for (int par = 0; par < 2; ++par) {
+    auto &seq = P.step_body[par];
+    const int se[5] = {0, bUE[par], bSE[0], bSE[1], bSE[0]};
+    const int sp[5] = {0, bUP[par], bSP[0], bSP[1], bSP[0]};
+    const int ne[5] = {0, bSE[0], bSE[1], bSE[0], bUE[1 - par]};
+    const int np[5] = {0, bSP[0], bSP[1], bSP[0], bUP[1 - par]};
+    for (int s = 1; s <= 4; ++s) {
+      core(seq, se[s], sp[s], true);
+      seq.push_back(row_launch(L_ROW_PAD, {bern_prog}));
+      TaskSpec tp = B.fold_task(mN), te;
+      const double c = cnext[s - 1], w = wacc[s - 1];
+      if (s < 4) {
+        std::vector<TermSpec> ap{{se[s], 0, -g * w}, {-1, 0, w}};
+        std::vector<TermSpec> ae{{bG, 0, w}};
+        if (s > 1) {
+          ap.push_back({bAP, 0, 1.0});
+          ae.push_back({bAE, 0, 1.0});
+        }
+        tp.outs.push_back(B.store(bAP, ap));
+        tp.outs.push_back(B.store(np[s], {{bUP[par], 0, 1.0}, {se[s], 0, -g * c}, {-1, 0, c}}));
+        te.outs.push_back(B.store(bAE, ae));
+        te.outs.push_back(B.store(ne[s], {{bUE[par], 0, 1.0}, {bG, 0, c}}));
+      } else {
+        const double h = dt / 6.0;
+        tp.outs.push_back(B.store(np[s], {{bUP[par], FILT, 1.0}, {bAP, FILT, h}, {se[s], FILT, -g * h}, {-1, FILT, h}}));
+        te.outs.push_back(B.store(ne[s], {{bUE[par], FILT, 1.0}, {bAE, FILT, h}, {bG, FILT, h}}));
+      }
+      seq.push_back(B.col_launch(L_COL_PAD, {tp, te}));
+      if (s < 4) seq.push_back(B.col_launch(L_COL_PAD, l0_tasks(ne[s], np[s], true)));
+    }
+    P.step_lift[par].push_back(B.col_launch(L_COL_PAD, l0_tasks(bUE[par], bUP[par], true)));
+    exit_seq(P.step_exit[par], bUE[par], bUP[par]);
+    P.chk_e[par] = bUE[par];
+    P.chk_p[par] = bUP[par];
+  }
+
+  // ---- algorithmic bytes and FFT flops per launch ------------------------------
+  // Every program or task streams its fields through HBM once: a row program
+  // reads each mixed field it loads (kx < nx/2 of one row per team) and writes
+  // each field it stores; a column task reads the mixed field it folds and the
+  // base spectra of its terms and writes its stores and lifts.
+  {
+    const double rb = pp.real_bytes, cb = 2.0 * rb, K = pp.nx / 2;
+    const double rows_pad = 1.5 * pp.ny, rows_base = pp.ny;
+    auto fft_flops = [](double n) { return 5.0 * n * std::log2(n); };
+    auto annotate = [&](std::vector<Launch> &seq) {
+      for (auto &l : seq) {
+        l.bytes = l.flops = 0.0;
+        if (l.kind == L_ROW_PAD || l.kind == L_ROW_BASE) {
+          const double rows = l.kind == L_ROW_PAD ? rows_pad : rows_base;
+          const double nrow = l.kind == L_ROW_PAD ? 1.5 * pp.nx : pp.nx;
+          for (int k = l.first; k < l.first + l.count; ++k) {
+            const RowProg &pg = P.progs[k];
+            for (int i = 0; i < pg.nop; ++i) {
+              const RowOp &o = P.ops[pg.op0 + i];
+              const int nf = (o.fa >= 0) + (o.fb >= 0);
+              if (o.code == OP_LD2) {
+                l.bytes += nf * rows * K * cb;
+                l.flops += rows * fft_flops(nrow);
+              } else if (o.code == OP_ST2) {
+                l.bytes += nf * rows * K * cb;
+                l.flops += rows * fft_flops(nrow);
+              } else if (o.code == OP_LDP || o.code == OP_STP) {
+                l.bytes += (o.code == OP_LDP ? nf : 1) * rows * pp.nx * 8.0;
+              }
+            }
+          }
+        } else if (l.kind == L_COL_PAD || l.kind == L_COL_BASE) {
+          const double rows = l.kind == L_COL_PAD ? rows_pad : rows_base;
+          for (int k = l.first; k < l.first + l.count; ++k) {
+            const ColTask &t = P.tasks[k];
+            if (t.fwd >= 0) {
+              l.bytes += rows * K * cb;
+              l.flops += K * fft_flops(rows);
+            }
+            for (int i = 0; i < t.no; ++i) {
+              const ColOut &o = P.outs[t.o0 + i];
+              for (int j = 0; j < o.nt; ++j)
+                if (P.terms[o.t0 + j].src >= 0) l.bytes += rows_base * K * 16.0;
+              if (o.dst_base >= 0) l.bytes += rows_base * K * 16.0;
+              if (o.dst_mixed >= 0) {
+                l.bytes += rows * K * cb;
+                l.flops += K * fft_flops(rows);
+              }
+            }
+          }
+        } else if (l.kind == L_PARSEVAL) {
+          l.bytes = 4.0 * rows_base * K * 16.0;
+        }
+      }
+    };
+    for (auto *seq : {&P.dtn, &P.rhs, &P.ham, &P.step_entry, &P.step_body[0], &P.step_body[1], &P.step_lift[0],
+                      &P.step_lift[1], &P.step_exit[0], &P.step_exit[1]})
+      annotate(*seq);
+  }
+  return P;
+}
+
+std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
+  (void)rows_pad;
+  (void)rows_base;
+  auto bad = [](const std::string &m) { return m; };
+  for (auto &pg : p.progs) {
+    if (pg.op0 < 0 || pg.nop < 0 || pg.op0 + pg.nop > (int)p.ops.size()) return bad("program range");
+    for (int i = 0; i < pg.nop; ++i) {
+      const RowOp &o = p.ops[pg.op0 + i];
+      switch (o.code) {
+        case OP_LD2:
+          if (o.fa < 0 || o.fa >= p.nmix || o.fb >= p.nmix) return bad("LD2 field");
+          break;
+        case OP_ST2:
+          if (o.fa < 0 || o.fa >= p.nmix || o.fb >= p.nmix) return bad("ST2 field");
+          if (o.a > RS_O2 || (o.b != RS_NONE && o.b > RS_O2)) return bad("ST2 reg");
+          break;
+        case OP_LDP:
+          if (o.fa < 0 || o.fa > 1 || o.fb > 1) return bad("LDP slot");
+          break;
+        case OP_STP:
+          if (o.fa < 0 || o.fa > 1 || o.a > RS_O2) return bad("STP");
+          break;
+        case OP_MAC:
+          if (o.a < RS_O0 || o.a > RS_O2 || o.b > RS_A || o.c > RS_A) return bad("MAC regs");
+          break;
+        case OP_MOV:
+          if (o.a > RS_O2 || o.b > RS_O2) return bad("MOV regs");
+          break;
+        case OP_ZERO:
+          if (o.a > RS_O2) return bad("ZERO reg");
+          break;
+        case OP_BERN:
+          break;
+        default:
+          return bad("op code");
+      }
+    }
+  }
+  for (auto &t : p.tasks) {
+    if (t.fwd >= p.nmix) return bad("task fwd");
+    if (t.o0 < 0 || t.no < 0 || t.o0 + t.no > (int)p.outs.size()) return bad("task outs");
+    for (int i = 0; i < t.no; ++i) {
+      const ColOut &o = p.outs[t.o0 + i];
+      if (o.dst_base >= p.nbase || o.dst_mixed >= p.nmix) return bad("out dst");
+      if (o.t0 < 0 || o.nt < 0 || o.t0 + o.nt > (int)p.terms.size()) return bad("out terms");
+      for (int k = 0; k < o.nt; ++k) {
+        const ColTerm &tm = p.terms[o.t0 + k];
+        if (tm.src >= p.nbase) return bad("term src");
+        if (tm.src < 0 && t.fwd < 0) return bad("term uses missing fold");
+      }
+    }
+  }
+  auto chk = [&](const std::vector<Launch> &seq) -> std::string {
+    for (auto &l : seq) {
+      if (l.kind == L_ROW_PAD || l.kind == L_ROW_BASE) {
+        if (l.first < 0 || l.count < 1 || l.first + l.count > (int)p.progs.size()) return "row launch";
+        for (int k = l.first; k < l.first + l.count; ++k)
+          for (int i = 0; i < p.progs[k].nop; ++i) {
+            const int code = p.ops[p.progs[k].op0 + i].code;
+            if (l.kind == L_ROW_PAD && (code == OP_LDP || code == OP_STP)) return "caller field op on padded rows";
+          }
+      } else if (l.kind == L_COL_PAD || l.kind == L_COL_BASE) {
+        if (l.first < 0 || l.count < 1 || l.first + l.count > (int)p.tasks.size()) return "col launch";
+      } else if (l.kind == L_PARSEVAL) {
+        if (l.first >= p.nbase || l.count >= p.nbase || l.c2 >= p.nbase || l.d2 >= p.nbase) return "parseval";
+      } else {
+        return "launch kind";
+      }
+    }
+    return "";
+  };
+  for (auto *seq : {&p.dtn, &p.rhs, &p.ham, &p.step_entry, &p.step_body[0], &p.step_body[1], &p.step_lift[0],
+                    &p.step_lift[1], &p.step_exit[0], &p.step_exit[1]}) {
+    std::string e = chk(*seq);
+    if (!e.empty()) return e;
+  }
+  return "";
+}
+
+}  // namespace zk

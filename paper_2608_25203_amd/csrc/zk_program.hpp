@@ -1,0 +1,81 @@
+// zk_program.hpp -- schedule records shared by the host planner and the kernels.
+//
+// One right-hand-side evaluation is a chain of two kinds of launches:
+//
+//  * row passes: one team of T = n/8 threads per padded (or base) grid row.
+//    A row program is a short list of RowOps: inverse x-FFT of pairs of
+//    "mixed" fields (y physical, kx spectral) into physical row values held in
+//    registers, pointwise sums of products, forward x-FFT of pairs of results
+//    back to mixed fields.  Pointwise work never leaves registers.
+//  * column passes: one team per kx column.  A ColTask optionally runs the
+//    forward y-FFT of one mixed field, truncates it to the base band and
+//    tapers it (the fold of the dealiased product), then produces ColOuts:
+//    linear combinations of that result and stored base-band spectra, each
+//    multiplied by a Fourier symbol, stored as a base spectrum and/or
+//    zero-padded and inverse y-FFT'd into a mixed field (the lift).
+#pragma once
+#include <stdint.h>
+
+namespace zk {
+
+// ---- row programs -------------------------------------------------------
+enum RowCode : uint8_t {
+  OP_LD2 = 1,  // u + i v <- inverse x-FFT of (F_a, F_b) mixed rows (Hermitian ext.)
+  OP_LDP = 2,  // u, v <- physical rows of caller fields (base grid)
+  OP_MOV = 3,  // R[a] <- R[b]
+  OP_MAC = 4,  // R[a] += coef * R[b] * R[c]
+  OP_ZERO = 5, // R[a] <- 0
+  OP_BERN = 6, // o0 <- Bernoulli term from o0 = |grad eta|^2, o1 = grad eta.grad psi,
+               //       o2 = |grad psi|^2, u = G psi; coef = eps
+  OP_ST2 = 7,  // forward x-FFT of R[a] + i R[b]; split; store kx < nx/2 to mixed fa, fb
+  OP_STP = 8   // physical row of R[a] -> caller field slot fa (base grid)
+};
+
+// register sets of a row team (each E values per thread)
+enum RowReg : uint8_t { RS_U = 0, RS_V = 1, RS_A = 2, RS_O0 = 3, RS_O1 = 4, RS_O2 = 5, RS_NONE = 255 };
+constexpr int kRowRegs = 6;
+
+enum RowFlag : uint8_t { FL_DX = 1 };  // multiply the spectrum by i*kx before the inverse FFT
+
+struct RowOp {
+  uint8_t code, a, b, c;
+  uint8_t fla, flb, pad0, pad1;
+  int32_t fa, fb;  // mixed-field ids, or caller-field slots for LDP/STP; -1 = none
+  double coef;
+};
+
+struct RowProg {
+  int32_t op0, nop;
+};
+
+// ---- column tasks -------------------------------------------------------
+// Fourier symbol bits; the symbol is the product of the selected factors.
+enum SymBits : uint32_t {
+  SYM_LMASK = 0xF,   // L_l(k) = |k|^l (tanh(|k| d) if l odd), l = bits & 0xF
+  SYM_IKY = 0x10,    // i * ky
+  SYM_FILT = 0x20,   // state filter A(k)
+  SYM_TAPER = 0x40   // taper exp(-(|k|/kc)^8) (only if the taper option is on)
+};
+
+struct ColTerm {
+  int32_t src;   // base-spectrum id, or -1 = result of the task's forward FFT
+  uint32_t sym;
+  double coef;
+};
+
+struct ColOut {
+  int32_t dst_base;   // base-spectrum id to store the combination, or -1
+  int32_t dst_mixed;  // mixed-field id to lift the combination into, or -1
+  int32_t t0, nt;     // terms [t0, t0 + nt)
+  double lift_coef;   // extra factor applied before the lift (1/N)
+};
+
+struct ColTask {
+  int32_t fwd;       // mixed-field id to fold (forward y-FFT + band + taper), or -1
+  uint32_t fwd_sym;  // symbol applied to the folded result
+  double fwd_coef;   // scale applied to the folded result
+  int32_t o0, no;    // outputs [o0, o0 + no)
+  int32_t pad0, pad1;
+};
+
+}  // namespace zk

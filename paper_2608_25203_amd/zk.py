@@ -1,0 +1,202 @@
+"""Thin ctypes binding of libzk.so (argument marshalling only).
+
+The functions below carry the C ABI's names (include/zk.h) and pass device
+pointers and the current torch stream straight through; every step of the
+computation runs in the HIP library.  PyTorch is used only to own device
+memory (fields and the workspace) and to name the stream.  There is no
+fallback: if libzk.so is missing or fails to load, `lib()` raises.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libzk.so")
+
+ZK_OK, ZK_EINVAL, ZK_ENOWS, ZK_EDEVICE, ZK_EDIVERGED = 0, -1, -2, -3, -4
+ZK_OPT_EPS, ZK_OPT_TAPER, ZK_OPT_FILTER, ZK_OPT_PRECISION, ZK_OPT_CHECK, ZK_OPT_PROFILE = 1, 2, 3, 4, 5, 6
+ZK_KERNEL_ROW_PAD, ZK_KERNEL_ROW_BASE, ZK_KERNEL_COL_PAD, ZK_KERNEL_COL_BASE, ZK_KERNEL_REDUCE = 0, 1, 2, 3, 4
+KERNEL_NAMES = {0: "row_pad", 1: "row_base", 2: "col_pad", 3: "col_base", 4: "reduce"}
+
+EXPORTS = ("zk_create", "zk_destroy", "zk_set_option", "zk_workspace_bytes", "zk_bind", "zk_dtn",
+           "zk_rhs", "zk_step", "zk_hamiltonian", "zk_kernel_stats", "zk_last_error")
+
+_lib = None
+
+
+class ZKError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"zk error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libzk.so once and declare the signatures of include/zk.h."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    L.zk_create.argtypes = [i, i, d, d, d, d, i]
+    L.zk_create.restype = vp
+    L.zk_destroy.argtypes = [vp]
+    L.zk_destroy.restype = None
+    L.zk_set_option.argtypes = [vp, i, d]
+    L.zk_set_option.restype = i
+    L.zk_workspace_bytes.argtypes = [vp]
+    L.zk_workspace_bytes.restype = sz
+    L.zk_bind.argtypes = [vp, vp, sz, vp]
+    L.zk_bind.restype = i
+    L.zk_dtn.argtypes = [vp, vp, vp, vp]
+    L.zk_dtn.restype = i
+    L.zk_rhs.argtypes = [vp, vp, vp, vp, vp]
+    L.zk_rhs.restype = i
+    L.zk_step.argtypes = [vp, vp, vp, d, i]
+    L.zk_step.restype = i
+    L.zk_hamiltonian.argtypes = [vp, vp, vp, ctypes.POINTER(d)]
+    L.zk_hamiltonian.restype = i
+    L.zk_kernel_stats.argtypes = [vp, i, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d),
+                                  ctypes.POINTER(ctypes.c_longlong)]
+    L.zk_kernel_stats.restype = i
+    L.zk_last_error.argtypes = [vp]
+    L.zk_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(ctx, rc):
+    if rc != ZK_OK:
+        raise ZKError(rc, lib().zk_last_error(ctx).decode())
+    return rc
+
+
+# ---- C-ABI mirrors --------------------------------------------------------------
+def zk_create(nx, ny, Lx, Ly, depth, g, M):
+    ctx = lib().zk_create(int(nx), int(ny), float(Lx), float(Ly), float(depth), float(g), int(M))
+    if not ctx:
+        raise ZKError(ZK_EINVAL, "zk_create rejected the arguments")
+    return ctx
+
+
+def zk_destroy(ctx):
+    lib().zk_destroy(ctx)
+
+
+def zk_set_option(ctx, key, value):
+    return _check(ctx, lib().zk_set_option(ctx, int(key), float(value)))
+
+
+def zk_workspace_bytes(ctx):
+    return int(lib().zk_workspace_bytes(ctx))
+
+
+def zk_bind(ctx, ws_ptr, nbytes, stream_ptr):
+    return _check(ctx, lib().zk_bind(ctx, ws_ptr, nbytes, stream_ptr))
+
+
+def zk_dtn(ctx, eta_ptr, psi_ptr, g_ptr):
+    return _check(ctx, lib().zk_dtn(ctx, eta_ptr, psi_ptr, g_ptr))
+
+
+def zk_rhs(ctx, eta_ptr, psi_ptr, eta_t_ptr, psi_t_ptr):
+    return _check(ctx, lib().zk_rhs(ctx, eta_ptr, psi_ptr, eta_t_ptr, psi_t_ptr))
+
+
+def zk_step(ctx, eta_ptr, psi_ptr, dt, nsteps):
+    return _check(ctx, lib().zk_step(ctx, eta_ptr, psi_ptr, float(dt), int(nsteps)))
+
+
+def zk_hamiltonian(ctx, eta_ptr, psi_ptr):
+    h = ctypes.c_double(0.0)
+    _check(ctx, lib().zk_hamiltonian(ctx, eta_ptr, psi_ptr, ctypes.byref(h)))
+    return h.value
+
+
+def zk_kernel_stats(ctx, kind):
+    """(ms, bytes, flops, launches) accumulated for one kernel kind; kind=-1 resets."""
+    ms, by, fl, n = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_double(0), ctypes.c_longlong(0)
+    if kind == -1:
+        _check(ctx, lib().zk_kernel_stats(ctx, -1, None, None, None, None))
+        return None
+    _check(ctx, lib().zk_kernel_stats(ctx, int(kind), ctypes.byref(ms), ctypes.byref(by), ctypes.byref(fl),
+                                      ctypes.byref(n)))
+    return ms.value, by.value, fl.value, n.value
+
+
+# ---- torch convenience wrapper -------------------------------------------------------
+class Solver:
+    """One context bound to a torch-owned workspace on the current stream.
+
+    Fields are float64 CUDA tensors of shape (ny, nx), contiguous."""
+
+    def __init__(self, nx, ny, Lx, Ly, depth, g, M, eps=1.0, taper=True, filt=True, precision=64,
+                 check=True, device="cuda"):
+        import torch
+
+        self.torch = torch
+        self.nx, self.ny = int(nx), int(ny)
+        self.device = torch.device(device)
+        self.ctx = zk_create(nx, ny, Lx, Ly, depth, g, M)
+        zk_set_option(self.ctx, ZK_OPT_PRECISION, precision)
+        zk_set_option(self.ctx, ZK_OPT_EPS, eps)
+        zk_set_option(self.ctx, ZK_OPT_TAPER, 1.0 if taper else 0.0)
+        zk_set_option(self.ctx, ZK_OPT_FILTER, 1.0 if filt else 0.0)
+        zk_set_option(self.ctx, ZK_OPT_CHECK, 1.0 if check else 0.0)
+        nbytes = zk_workspace_bytes(self.ctx)
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self.ws.data_ptr()) % 256
+            self.stream = torch.cuda.current_stream(self.device)
+            zk_bind(self.ctx, self.ws.data_ptr() + off, nbytes, self.stream.cuda_stream)
+
+    def _field(self, x):
+        t = self.torch
+        x = t.as_tensor(x, dtype=t.float64, device=self.device)
+        if x.shape != (self.ny, self.nx):
+            raise ValueError(f"field shape {tuple(x.shape)} != {(self.ny, self.nx)}")
+        return x.contiguous()
+
+    def dtn(self, eta, psi):
+        eta, psi = self._field(eta), self._field(psi)
+        out = self.torch.empty_like(eta)
+        zk_dtn(self.ctx, eta.data_ptr(), psi.data_ptr(), out.data_ptr())
+        return out
+
+    def rhs(self, eta, psi):
+        eta, psi = self._field(eta), self._field(psi)
+        a, b = self.torch.empty_like(eta), self.torch.empty_like(eta)
+        zk_rhs(self.ctx, eta.data_ptr(), psi.data_ptr(), a.data_ptr(), b.data_ptr())
+        return a, b
+
+    def step(self, eta, psi, dt, nsteps):
+        """In place on the given tensors (they must already be contiguous float64 on the device)."""
+        if eta.dtype != self.torch.float64 or not eta.is_contiguous() or not psi.is_contiguous():
+            raise ValueError("step works in place on contiguous float64 device tensors")
+        zk_step(self.ctx, eta.data_ptr(), psi.data_ptr(), dt, nsteps)
+        return eta, psi
+
+    def hamiltonian(self, eta, psi):
+        eta, psi = self._field(eta), self._field(psi)
+        return zk_hamiltonian(self.ctx, eta.data_ptr(), psi.data_ptr())
+
+    def kernel_stats(self):
+        """{kind name: (ms, bytes, flops, launches)} for launches timed so far."""
+        return {KERNEL_NAMES[k]: zk_kernel_stats(self.ctx, k) for k in KERNEL_NAMES}
+
+    def reset_stats(self):
+        zk_kernel_stats(self.ctx, -1)
+
+    def set_option(self, key, value):
+        zk_set_option(self.ctx, key, value)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            zk_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,240 @@
+"""CPU interpreter of the HIP library's schedules (test infrastructure).
+
+Executes the row programs and column tasks that the host planner
+(paper_2608_25203_amd/csrc/zk_plan.cpp) emits, with the same meaning the
+kernels give them, on numpy arrays: mixed fields are (rows, nx/2) complex
+(y physical, kx spectral), base spectra (ny, nx/2) complex.  It lets the CPU
+suite check the planner's algebra against the oracle before any GPU run.  It
+shares no code with the oracle and is not part of the product path.
+"""
+import json
+import os
+import subprocess
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2608_25203_amd", "csrc")
+EXE = os.path.join(ROOT, "_build", "zk_plan_check")
+
+OP_LD2, OP_LDP, OP_MOV, OP_MAC, OP_ZERO, OP_BERN, OP_ST2, OP_STP = range(1, 9)
+RS_NONE = 255
+SYM_IKY, SYM_FILT, SYM_TAPER = 0x10, 0x20, 0x40
+L_ROW_PAD, L_ROW_BASE, L_COL_PAD, L_COL_BASE, L_PARSEVAL = range(5)
+
+
+def pow2_scale(a):
+    """Per-row power-of-two scale bringing max(|re|, |im|) of each row to [1, 2)."""
+    a = np.asarray(a)
+    m = np.max(np.maximum(np.abs(a.real), np.abs(a.imag)), axis=1, keepdims=True)
+    with np.errstate(divide="ignore"):
+        e = np.where(m > 0, np.floor(np.log2(np.where(m > 0, m, 1.0))), 0.0)
+    return np.exp2(-e)
+
+
+def build_checker():
+    os.makedirs(os.path.dirname(EXE), exist_ok=True)
+    src = [os.path.join(CSRC, "zk_plan.cpp"), os.path.join(CSRC, "zk_plan_check.cpp")]
+    if not os.path.exists(EXE) or any(os.path.getmtime(s) > os.path.getmtime(EXE) for s in src + [
+            os.path.join(CSRC, "zk_plan.hpp"), os.path.join(CSRC, "zk_program.hpp")]):
+        subprocess.run(["g++", "-O1", "-std=c++17", "-I", CSRC] + src + ["-o", EXE], check=True)
+    return EXE
+
+
+def load_plan(nx, ny, M, eps=1.0, taper=True, filt=True, dt=1.0):
+    exe = build_checker()
+    out = subprocess.run([exe, str(nx), str(ny), str(M), repr(float(eps)), str(int(taper)), str(int(filt)),
+                          repr(float(dt))], capture_output=True, text=True, check=True).stdout
+    return json.loads(out)
+
+
+class Interp:
+    def __init__(self, nx, ny, Lx, Ly, depth, g, M, eps=1.0, taper=True, filt=True):
+        self.nx, self.ny, self.Lx, self.Ly, self.g, self.M = nx, ny, Lx, Ly, g, M
+        self.depth = depth if (depth is not None and np.isfinite(depth) and depth > 0) else 0.0
+        self.eps, self.taper, self.filt = eps, taper, filt
+        self.K = nx // 2
+        self.mix = {}
+        self.base = {}
+        self.plan = None
+        self.dt = None
+        kx = 2 * np.pi / Lx * np.arange(self.K)
+        b = np.arange(ny)
+        my = np.where(b < ny // 2, b, b - ny)
+        self.kx, self.my = kx[None, :], my[:, None]
+        self.ky = 2 * np.pi / Ly * self.my
+        self.kk = np.sqrt(self.kx ** 2 + self.ky ** 2)
+        self.th = np.tanh(self.kk * self.depth) if self.depth > 0 else np.ones_like(self.kk)
+        kc = 2.0 / 3.0 * min(np.pi * nx / Lx, np.pi * ny / Ly)
+        self.taper_sym = np.exp(-((self.kk / kc) ** 8))
+
+        def f1(m, n):
+            t = 2 * np.pi * m / n
+            return (5 + 4 * np.cos(t) - np.cos(2 * t)) / 8
+
+        self.filt_sym = f1(np.arange(self.K)[None, :], nx) * f1(self.my, ny)
+
+    def _plan(self, dt):
+        if self.plan is None or dt != self.dt:
+            self.plan = load_plan(self.nx, self.ny, self.M, self.eps, self.taper, self.filt, dt)
+            self.dt = dt
+        return self.plan
+
+    # ---- symbols ---------------------------------------------------------------
+    def sym(self, s):
+        f = np.ones_like(self.kk)
+        l = s & 0xF
+        if l:
+            f = self.kk ** l * (self.th if l % 2 else 1.0)
+        if s & SYM_FILT:
+            f = f * self.filt_sym
+        if (s & SYM_TAPER) and self.taper:
+            f = f * self.taper_sym
+        if s & SYM_IKY:
+            return 1j * self.ky * f
+        return f.astype(complex)
+
+    # ---- row pass ----------------------------------------------------------------
+    def row(self, launch, phys):
+        kind, first, count = launch[0], launch[1], launch[2]
+        pad = kind == L_ROW_PAD
+        N = 3 * self.nx // 2 if pad else self.nx
+        rows = 3 * self.ny // 2 if pad else self.ny
+        K = self.K
+        kxs = 2 * np.pi / self.Lx * np.arange(K)
+        P = self.plan
+        for pi in range(first, first + count):
+            op0, nop = P["progs"][pi]
+            R = [np.zeros((rows, N)) for _ in range(6)]
+            for o in P["ops"][op0:op0 + nop]:
+                code, a, b, c, fa, fla, fb, flb, coef = o
+                if code == OP_LD2:
+                    def spec(f, fl):
+                        S = np.array(self.mix[f][:rows, :K])
+                        if fl & 1:
+                            S = S * (1j * kxs[None, :])
+                        return S
+                    Sa = spec(fa, fla)
+                    Sb = spec(fb, flb) if fb >= 0 else np.zeros_like(Sa)
+                    sa, sb = pow2_scale(Sa), pow2_scale(Sb)
+                    Sa, Sb = Sa * sa, Sb * sb
+                    Z = np.zeros((rows, N), complex)
+                    Z[:, :K] = Sa + 1j * Sb
+                    Z[:, N - K + 1:] = (np.conj(Sa) + 1j * np.conj(Sb))[:, 1:][:, ::-1]
+                    z = np.fft.ifft(Z, axis=1) * N
+                    R[0], R[1] = z.real / sa, z.imag / sb
+                elif code == OP_LDP:
+                    R[0] = np.array(phys[fa], dtype=float)
+                    R[1] = np.array(phys[fb], dtype=float) if fb >= 0 else np.zeros((rows, N))
+                elif code == OP_MOV:
+                    R[a] = R[b].copy()
+                elif code == OP_MAC:
+                    R[a] = R[a] + coef * R[b] * R[c]
+                elif code == OP_ZERO:
+                    R[a] = np.zeros((rows, N))
+                elif code == OP_BERN:
+                    e = coef
+                    S = 1 + e * e * R[3]
+                    W = (R[0] + e * R[4]) / S
+                    R[3] = e * (-0.5 * R[5] + 0.5 * S * W * W)
+                elif code == OP_ST2:
+                    x = R[a]
+                    y = R[b] if b != RS_NONE else np.zeros_like(x)
+                    sx, sy = pow2_scale(x), pow2_scale(y)
+                    Z = np.fft.fft(x * sx + 1j * (y * sy), axis=1)
+                    k = np.arange(K)
+                    Zk = Z[:, k]
+                    Zm = Z[:, (N - k) % N]
+                    self._mix_put(fa, rows, (Zk + np.conj(Zm)) / 2 / sx)
+                    if fb >= 0:
+                        self._mix_put(fb, rows, (Zk - np.conj(Zm)) / 2j / sy)
+                elif code == OP_STP:
+                    phys[2 + fa][...] = R[a]
+                else:
+                    raise ValueError(code)
+
+    def _mix_put(self, f, rows, arr):
+        m = self.mix.setdefault(f, np.zeros((3 * self.ny // 2, self.K), complex))
+        m[:rows, :] = arr
+
+    # ---- column pass ---------------------------------------------------------------
+    def col(self, launch):
+        kind, first, count = launch[0], launch[1], launch[2]
+        pad = kind == L_COL_PAD
+        ny = self.ny
+        rows = 3 * ny // 2 if pad else ny
+        b = np.arange(ny)
+        idx = np.where(b < ny // 2, b, b + (rows - ny))
+        P = self.plan
+        for ti in range(first, first + count):
+            fwd, fsym, fcoef, o0, no = P["tasks"][ti]
+            X = None
+            if fwd >= 0:
+                V = np.fft.fft(self.mix[fwd][:rows, :], axis=0)
+                X = V[idx, :] * fcoef * self.sym(fsym)
+                X[ny // 2, :] = 0
+            for oi in range(o0, o0 + no):
+                dst_b, dst_m, t0, nt, lc = P["outs"][oi]
+                acc = np.zeros((ny, self.K), complex)
+                for src, s, coef in P["terms"][t0:t0 + nt]:
+                    v = X if src < 0 else self.base[src]
+                    acc = acc + coef * self.sym(s) * v
+                acc[ny // 2, :] = 0
+                if dst_b >= 0:
+                    self.base[dst_b] = acc
+                if dst_m >= 0:
+                    Z = np.zeros((rows, self.K), complex)
+                    Z[idx, :] = acc * lc
+                    if pad:
+                        Z[ny // 2 + (rows - ny), :] = 0  # the Nyquist slot mapped by idx is zero anyway
+                    z = np.fft.ifft(Z, axis=0) * rows
+                    self._mix_put(dst_m, rows, z)
+
+    def parseval(self, launch):
+        a, b, c, d = (self.base[i] for i in launch[1:5])
+        w = np.where(np.arange(self.K) == 0, 1.0, 2.0)[None, :]
+        return (float(np.sum(w * np.real(np.conj(a) * b))), float(np.sum(w * np.real(np.conj(c) * d))))
+
+    def run(self, seq, phys):
+        res = None
+        for l in seq:
+            if l[0] in (L_ROW_PAD, L_ROW_BASE):
+                self.row(l, phys)
+            elif l[0] in (L_COL_PAD, L_COL_BASE):
+                self.col(l)
+            else:
+                res = self.parseval(l)
+        return res
+
+    # ---- entry points mirroring the C ABI ---------------------------------------------------
+    def dtn(self, eta, psi):
+        P = self._plan(self.dt if self.dt is not None else 1.0)
+        phys = [eta, psi, np.zeros_like(eta), np.zeros_like(eta)]
+        self.run(P["dtn"], phys)
+        return phys[2]
+
+    def rhs(self, eta, psi):
+        P = self._plan(self.dt if self.dt is not None else 1.0)
+        phys = [eta, psi, np.zeros_like(eta), np.zeros_like(eta)]
+        self.run(P["rhs"], phys)
+        return phys[2], phys[3]
+
+    def hamiltonian(self, eta, psi):
+        P = self._plan(self.dt if self.dt is not None else 1.0)
+        phys = [eta, psi, None, None]
+        s1, s2 = self.run(P["ham"], phys)
+        N = self.nx * self.ny
+        dA = self.Lx * self.Ly / N
+        return 0.5 * dA * s1 / N + 0.5 * self.g * dA * s2 / N
+
+    def step(self, eta, psi, dt, nsteps):
+        P = self._plan(dt)
+        phys = [eta, psi, np.zeros_like(eta), np.zeros_like(eta)]
+        self.run(P["step_entry"], phys)
+        for i in range(nsteps):
+            par = i & 1
+            self.run(P["step_body%d" % par], phys)
+            if i + 1 < nsteps:
+                self.run(P["step_lift%d" % (1 - par)], phys)
+        self.run(P["step_exit%d" % (nsteps & 1)], phys)
+        return phys[2], phys[3]

@@ -1,0 +1,109 @@
+"""Host-side checks that need no GPU: the planner's schedules (validated and
+executed by a numpy interpreter against the oracle) and the C ABI library
+(loads, exports every symbol of include/zk.h, host-only argument checks)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle.hos import Grid, HOSModel
+from paper_2608_25203_amd.inputs import jonswap_state, random_band_fields
+
+from plan_interp import Interp, load_plan
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TWO_PI = 2 * np.pi
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("nx,ny", [(64, 64), (128, 64), (512, 512), (2048, 2048)])
+@pytest.mark.parametrize("M", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_plan_builds_and_validates(nx, ny, M):
+    p = load_plan(nx, ny, M)
+    assert p["nmix"] > 0 and p["nbase"] > 0
+    # every launch of every sequence is non-empty
+    for k in ("dtn", "rhs", "ham", "step_entry", "step_body0", "step_body1", "step_exit0", "step_exit1"):
+        assert len(p[k]) > 0
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 4, 5, 6, 7])
+def test_schedule_algebra_matches_oracle_jonswap(M):
+    """The planner's row programs and column tasks, executed literally, give
+    the oracle's G psi, RHS, Hamiltonian and RK4 steps (64 x 64 deep-water
+    JONSWAP state, steepness 0.05)."""
+    n, L = 64, TWO_PI
+    eta, psi = jonswap_state(n, n, L, L, None, 9.81, 4.0, 0.05, 0)
+    I = Interp(n, n, L, L, None, 9.81, M)
+    m = HOSModel(Grid(n, n, L, L, None), M)
+    assert rel(I.dtn(eta, psi), m.dtn(eta, psi)) < 1e-13
+    a, b = I.rhs(eta, psi)
+    a0, b0 = m.rhs(eta, psi)
+    assert rel(a, a0) < 1e-13 and rel(b, b0) < 1e-13
+    assert abs(I.hamiltonian(eta, psi) / m.hamiltonian(eta, psi) - 1) < 1e-13
+    s, t = I.step(eta, psi, 0.01, 3)
+    s0, t0 = m.step(eta, psi, 0.01, 3)
+    assert rel(s, s0) < 1e-13 and rel(t, t0) < 1e-13
+
+
+@pytest.mark.parametrize("M", [2, 4, 6])
+@pytest.mark.parametrize("eps,taper,filt", [(0.6, True, True), (1.0, False, False)])
+def test_schedule_algebra_matches_oracle_broadband(M, eps, taper, filt):
+    """Band-edge content, finite depth, non-square grid, options varied."""
+    nx, ny = 32, 16
+    eta, psi = random_band_fields(nx, ny, 3, 7, amplitude=0.02)
+    I = Interp(nx, ny, 3.0, 2.0, 1.5, 9.81, M, eps=eps, taper=taper, filt=filt)
+    m = HOSModel(Grid(nx, ny, 3.0, 2.0, 1.5), M, eps=eps, taper=taper, filt=filt)
+    a, b = I.rhs(eta, psi)
+    a0, b0 = m.rhs(eta, psi)
+    assert rel(a, a0) < 1e-13 and rel(b, b0) < 1e-13
+    s, t = I.step(eta, psi, 0.02, 2)
+    s0, t0 = m.step(eta, psi, 0.02, 2)
+    assert rel(s, s0) < 1e-13 and rel(t, t0) < 1e-13
+
+
+# ---------------------------------------------------------------- the library
+LIB = os.path.join(ROOT, "paper_2608_25203_amd", "libzk.so")
+
+
+def _header_symbols():
+    txt = open(os.path.join(ROOT, "include", "zk.h")).read()
+    return sorted(set(re.findall(r"\b(zk_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libzk.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    syms = _header_symbols()
+    assert "zk_dtn" in syms and "zk_step" in syms and "zk_hamiltonian" in syms
+    for s in syms:
+        assert hasattr(lib, s), s
+    from paper_2608_25203_amd import zk
+    assert set(zk.EXPORTS) == set(syms)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libzk.so not built")
+def test_library_host_side_argument_checks():
+    from paper_2608_25203_amd import zk
+    L = zk.lib()
+    assert not L.zk_create(63, 64, 1.0, 1.0, 1.0, 9.81, 3)       # not a power of two
+    assert not L.zk_create(64, 4096, 1.0, 1.0, 1.0, 9.81, 3)     # too large
+    assert not L.zk_create(64, 64, -1.0, 1.0, 1.0, 9.81, 3)      # bad length
+    assert not L.zk_create(64, 64, 1.0, 1.0, 1.0, 9.81, 9)       # M out of range
+    ctx = L.zk_create(512, 512, 200.0, 200.0, 20.0, 9.81, 4)
+    assert ctx
+    n64 = L.zk_workspace_bytes(ctx)
+    assert L.zk_set_option(ctx, zk.ZK_OPT_PRECISION, 32.0) == 0
+    n32 = L.zk_workspace_bytes(ctx)
+    assert 0 < n32 < n64
+    assert L.zk_set_option(ctx, zk.ZK_OPT_EPS, 1.5) == zk.ZK_EINVAL
+    assert L.zk_set_option(ctx, 99, 0.0) == zk.ZK_EINVAL
+    assert b"eps" in L.zk_last_error(ctx) or b"option" in L.zk_last_error(ctx)
+    # calls before zk_bind report a missing workspace without touching a device
+    assert L.zk_dtn(ctx, None, None, None) == zk.ZK_ENOWS
+    L.zk_destroy(ctx)
