@@ -36,7 +36,7 @@ struct zk_ctx {
   // workspace layout (byte offsets)
   size_t off_tw[4] = {0, 0, 0, 0};  // row pad, row base, col pad, col base
   size_t off_ops = 0, off_progs = 0, off_terms = 0, off_outs = 0, off_tasks = 0;
-  size_t off_red = 0, off_base = 0, off_mix = 0, total = 0;
+  size_t off_red = 0, off_cmax = 0, off_sym = 0, off_fx = 0, off_fy = 0, off_base = 0, off_mix = 0, total = 0;
   long long base_stride = 0, mix_stride = 0;
   size_t sched_cap[5] = {0, 0, 0, 0, 0};  // capacities (elements) reserved for the schedules
 
@@ -138,6 +138,14 @@ void compute_layout(zk_ctx *c) {
   off = align_up(off + c->sched_cap[4] * sizeof(ColTask));
   c->off_red = off;
   off = align_up(off + (2 * kRedBlocks + 8) * sizeof(double));
+  c->off_cmax = off;
+  off = align_up(off + (size_t)probe.nmix * (nx / 2) * sizeof(float));
+  c->off_sym = off;
+  off = align_up(off + (size_t)(nx / 2) * ny * sizeof(SymEl));
+  c->off_fx = off;
+  off = align_up(off + (size_t)(nx / 2) * sizeof(double));
+  c->off_fy = off;
+  off = align_up(off + (size_t)ny * sizeof(double));
   c->base_stride = (long long)(align_up((size_t)(nx / 2) * ny * 16) / 16);
   c->off_base = off;
   off = align_up(off + (size_t)probe.nbase * c->base_stride * 16);
@@ -184,6 +192,38 @@ int upload(zk_ctx *c, double dt) {
   HIP_TRY(c, put(c->off_tasks, p.tasks.data(), p.tasks.size() * sizeof(ColTask)));
   if (c->dirty) {
     const int nx = c->pp.nx, ny = c->pp.ny;
+    // Fourier symbol tables (long double on the host, stored as FP64):
+    // |k|, G0 = |k| tanh(|k| d), taper exp(-(|k|/kc)^8) per band element in
+    // the tiled base-spectrum layout; separable filter factors per axis.
+    {
+      const long double pi = 3.14159265358979323846264338327950288L;
+      const long double kxs = 2 * pi / c->pp.Lx, kys = 2 * pi / c->pp.Ly;
+      const long double kc = 2.0L / 3.0L * std::min(pi * nx / c->pp.Lx, pi * ny / c->pp.Ly);
+      std::vector<SymEl> tab((size_t)(nx / 2) * ny);
+      for (int col = 0; col < nx / 2; ++col)
+        for (int b = 0; b < ny; ++b) {
+          const int my = b < ny / 2 ? b : b - ny;
+          const long double kx = kxs * col, ky = kys * my;
+          const long double kk = sqrtl(kx * kx + ky * ky);
+          const long double r = kk / kc, r2 = r * r, r4 = r2 * r2;
+          SymEl e{};
+          e.kk = (double)kk;
+          e.g0 = (double)(c->pp.depth > 0 ? kk * tanhl(kk * c->pp.depth) : kk);
+          e.tp = (double)expl(-(r4 * r4));
+          tab[((size_t)(col / CBB) * ny + b) * CBB + col % CBB] = e;
+        }
+      auto f1 = [&](int m, int n) {
+        const long double th = 2 * pi * m / n;
+        return (double)((5 + 4 * cosl(th) - cosl(2 * th)) / 8);
+      };
+      std::vector<double> fx(nx / 2), fy(ny);
+      for (int col = 0; col < nx / 2; ++col) fx[col] = f1(col, nx);
+      for (int b = 0; b < ny; ++b) fy[b] = f1(b < ny / 2 ? b : b - ny, ny);
+      HIP_TRY(c, put(c->off_sym, tab.data(), tab.size() * sizeof(SymEl)));
+      HIP_TRY(c, put(c->off_fx, fx.data(), fx.size() * sizeof(double)));
+      HIP_TRY(c, put(c->off_fy, fy.data(), fy.size() * sizeof(double)));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
     const int lens[4] = {3 * nx / 2, nx, 3 * ny / 2, ny};
     for (int i = 0; i < 4; ++i) {
       if (c->precision == 32) {
@@ -212,7 +252,9 @@ struct Phys {
 template <typename real>
 int run_seq_t(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
   const int nx = c->pp.nx, ny = c->pp.ny;
-  const int Tx = nx / 8, Ty = ny / 8;
+  // team sizes: T = min(256, n/2) threads; first-pass radix E = N / T
+  const int Tx = std::min(256, nx / 2), Ty = std::min(256, ny / 2);
+  const int Ex_pad = 3 * nx / 2 / Tx, Ex_base = nx / Tx, Ey_pad = 3 * ny / 2 / Ty, Ey_base = ny / Ty;
   char *ws = c->ws;
   auto twp = [&](int i) { return reinterpret_cast<const cpx<real> *>(ws + c->off_tw[i]); };
   cpx<real> *mix = reinterpret_cast<cpx<real> *>(ws + c->off_mix);
@@ -242,9 +284,10 @@ int run_seq_t(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
       a.pout1 = ph.out1;
       a.tw = twp(pad ? 0 : 1);
       a.kx_scale = 2.0 * M_PI / c->pp.Lx;
+      a.colmax = reinterpret_cast<const float *>(ws + c->off_cmax);
       const int rpb = 256 / Tx;
       if (a.rows % rpb) return fail(c, ZK_EINVAL, "row blocking");
-      e = launch_row<real>(a, Tx, pad ? 12 : 8, a.rows / rpb, l.count, c->stream);
+      e = launch_row<real>(a, Tx, pad ? Ex_pad : Ex_base, a.rows / rpb, l.count, c->stream);
     } else if (l.kind == L_COL_PAD || l.kind == L_COL_BASE) {
       const bool pad = l.kind == L_COL_PAD;
       ColArgs<real> a{};
@@ -265,10 +308,14 @@ int run_seq_t(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
       a.depth = c->pp.depth;
       a.inv_kc = 1.0 / kc;
       a.taper_on = c->pp.taper ? 1 : 0;
-      const int cpb = std::min(4, 256 / Ty);
+      a.colmax = reinterpret_cast<float *>(ws + c->off_cmax);
+      a.sym = reinterpret_cast<const SymEl *>(ws + c->off_sym);
+      a.filt_x = reinterpret_cast<const double *>(ws + c->off_fx);
+      a.filt_y = reinterpret_cast<const double *>(ws + c->off_fy);
+      const int cpb = 256 / Ty;
       const int ncols = nx / 2;
       if (ncols % cpb) return fail(c, ZK_EINVAL, "column blocking");
-      e = launch_col<real>(a, Ty, pad ? 12 : 8, ncols / cpb, l.count, c->stream);
+      e = launch_col<real>(a, Ty, pad ? Ey_pad : Ey_base, ncols / cpb, l.count, c->stream);
     } else if (l.kind == L_PARSEVAL) {
       double *red = reinterpret_cast<double *>(ws + c->off_red);
       e = launch_parseval(base + (long long)l.first * c->base_stride, base + (long long)l.count * c->base_stride,

@@ -1,12 +1,12 @@
-// zk_fft.hpp -- register-resident Stockham FFT for one team of T threads.
+// zk_fft.hpp -- Stockham FFT for one team of T threads (T = min(256, n/2)).
 //
 // A team transforms one sequence of N = E * T complex points.  Thread t holds
-// the E elements t + T*r in registers on entry and the E outputs t + T*q on
-// exit, so a pointwise operation between two transforms never needs a data
-// exchange.  The first pass is a radix-E butterfly entirely in registers
-// (E = 12 = 3 * 4 for the 3/2-padded lengths 3*2^k, E = 8 for the base
-// lengths 2^k); the remaining passes are radix-8/4/2 butterflies with one LDS
-// exchange each (Stockham autosort: natural order in, natural order out).
+// the E elements t + T*r in registers on entry; the first pass is a radix-E
+// butterfly entirely in registers (E = 3, 6 or 12 for the 3/2-padded lengths
+// 3*2^k, E = 2, 4 or 8 for the base lengths 2^k); the remaining radix-4/2
+// passes exchange through LDS (Stockham autosort: natural order in, natural
+// order out), and the result is left in LDS for the caller to read in
+// whatever element-to-thread mapping it needs.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -174,94 +174,100 @@ struct DFT {
 };
 
 // ---- pass plan ----------------------------------------------------------
-__host__ __device__ constexpr int next_radix(int E, int rem) {
-  const int big = (E % 8 == 0) ? 8 : 4;
-  return (rem % big == 0) ? big : ((rem % 4 == 0 && E % 4 == 0) ? 4 : 2);
+// After the radix-E first pass (in registers) the remaining factor T = N / E
+// is split into radix-4 passes (and one radix-2 pass if T is an odd power of
+// two).  Every later pass goes through LDS, its N / R butterflies spread over
+// the T threads of the team.
+__host__ __device__ constexpr int later_radix(int T, int p) {  // p >= 1
+  int rem = T;
+  for (int i = 1; i < p; ++i) rem /= (rem % 4 == 0) ? 4 : 2;
+  return (rem % 4 == 0) ? 4 : 2;
 }
-__host__ __device__ constexpr int num_passes(int E, int T) {
+__host__ __device__ constexpr int num_passes(int T) {
   int n = 1, rem = T;
   while (rem > 1) {
-    rem /= next_radix(E, rem);
+    rem /= (rem % 4 == 0) ? 4 : 2;
     ++n;
   }
   return n;
-}
-__host__ __device__ constexpr int pass_radix(int E, int T, int p) {
-  if (p == 0) return E;
-  int rem = T;
-  for (int i = 1; i < p; ++i) rem /= next_radix(E, rem);
-  return next_radix(E, rem);
-}
-__host__ __device__ constexpr int pass_ns(int E, int T, int p) {
-  int ns = 1;
-  for (int i = 0; i < p; ++i) ns *= pass_radix(E, T, i);
-  return ns;
 }
 
 // LDS index with one pad slot every 16 elements (spreads strided accesses over banks)
 __device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int lds_len(int N) { return N + N / 16 + 1; }
 
-// Team FFT: v[r] holds element t + T*r on entry, element t + T*r of the
-// transform on exit (unnormalised, sign DIR).  tw[i] = exp(-2 pi i * i / N).
-// Every thread of the block must call it (it contains __syncthreads); lds is
-// this team's private region of lds_len(N) elements.
-template <typename R, int N, int E, int DIR>
-__device__ __forceinline__ void team_fft(cpx<R> (&v)[E], cpx<R> *lds, const cpx<R> *__restrict__ tw, int t) {
+// Team FFT of N = T * E points (unnormalised, sign DIR).  On entry thread t
+// holds element t + T*r in v[r].  The first pass is a radix-E butterfly in
+// registers; later passes exchange through LDS.  NBUF = 2 ping-pongs between
+// buf0 and buf1 (one barrier per pass); NBUF = 1 works in place in buf0 (two
+// barriers per pass).  Returns the buffer holding the transform in natural
+// order (lpad-indexed); the final barrier is included, so every thread may
+// read any element.  tw[i] = exp(-2 pi i * i / N).  Every thread of the block
+// must call it.
+template <typename R, int N, int E, int NBUF, int DIR>
+__device__ __forceinline__ cpx<R> *team_fft(cpx<R> (&v)[E], cpx<R> *buf0, cpx<R> *buf1,
+                                            const cpx<R> *__restrict__ tw, int t) {
   constexpr int T = N / E;
-  constexpr int NP = num_passes(E, T);
+  constexpr int NP = num_passes(T);
   static_assert(NP >= 2, "team FFT needs at least two passes");
+  // Make the lane index opaque (an empty asm statement, no instruction): the
+  // per-pass LDS and twiddle addresses derived from it are then recomputed at
+  // each transform instead of being hoisted out of the callers' loops and
+  // kept live for the whole kernel.
+  asm volatile("" : "+v"(t));
   DFT<E, DIR, R>::run(v);
+  __syncthreads();  // readers of the previous transform's result are done
+#pragma unroll
+  for (int r = 0; r < E; ++r) buf0[lpad(t * E + r)] = v[r];
+  cpx<R> *in = buf0;
+  cpx<R> *out = NBUF == 2 ? buf1 : buf0;
   static_for<1, NP>([&](auto pc) {
     constexpr int p = decltype(pc)::value;
-    constexpr int Rp = pass_radix(E, T, p);
-    constexpr int Rq = pass_radix(E, T, p - 1);
-    constexpr int Nsq = pass_ns(E, T, p - 1);
-    constexpr int Ns = pass_ns(E, T, p);
+    constexpr int Rp = later_radix(T, p);
+    constexpr int nb = N / Rp;
+    constexpr int IT = (nb + T - 1) / T;
+    constexpr int Ns = [] {
+      int ns = E;
+      for (int i = 1; i < p; ++i) ns *= later_radix(T, i);
+      return ns;
+    }();
     __syncthreads();
-    if constexpr (p == 1) {
+    cpx<R> w[IT][Rp];
 #pragma unroll
-      for (int e = 0; e < E; ++e) lds[lpad(t * E + e)] = v[e];
-    } else {
+    for (int it = 0; it < IT; ++it) {
+      const int j = t + T * it;
+      if (j < nb) {
 #pragma unroll
-      for (int m = 0; m < E / Rq; ++m) {
-        const int j = t + T * m;
-        const int k = j % Nsq;
-        const int base = (j / Nsq) * Nsq * Rq + k;
-#pragma unroll
-        for (int r = 0; r < Rq; ++r) lds[lpad(base + r * Nsq)] = v[m * Rq + r];
+        for (int r = 0; r < Rp; ++r) w[it][r] = in[lpad(j + r * nb)];
       }
     }
-    __syncthreads();
+    if constexpr (NBUF == 1) __syncthreads();
 #pragma unroll
-    for (int m = 0; m < E / Rp; ++m) {
-      const int j = t + T * m;
+    for (int it = 0; it < IT; ++it) {
+      const int j = t + T * it;
+      if (j < nb) {
+        const int k = j % Ns;
+        constexpr int step = N / (Ns * Rp);
 #pragma unroll
-      for (int r = 0; r < Rp; ++r) v[m * Rp + r] = lds[lpad(j + r * (N / Rp))];
-    }
+        for (int r = 1; r < Rp; ++r) {
+          cpx<R> tr = tw[r * k * step];
+          if constexpr (DIR > 0) tr.y = -tr.y;
+          w[it][r] = cmul(w[it][r], tr);
+        }
+        DFT<Rp, DIR, R>::run(w[it]);
+        const int base = (j / Ns) * Ns * Rp + k;
 #pragma unroll
-    for (int m = 0; m < E / Rp; ++m) {
-      const int j = t + T * m;
-      const int k = j % Ns;
-      constexpr int step = N / (Ns * Rp);
-#pragma unroll
-      for (int r = 1; r < Rp; ++r) {
-        cpx<R> w = tw[r * k * step];
-        if constexpr (DIR > 0) w.y = -w.y;
-        v[m * Rp + r] = cmul(v[m * Rp + r], w);
+        for (int r = 0; r < Rp; ++r) out[lpad(base + r * Ns)] = w[it][r];
       }
-      DFT<Rp, DIR, R>::run(&v[m * Rp]);
+    }
+    if constexpr (NBUF == 2) {
+      cpx<R> *tmp = in;
+      in = out;
+      out = tmp;
     }
   });
-  constexpr int Rl = pass_radix(E, T, NP - 1);
-  constexpr int nbl = E / Rl;
-  cpx<R> o[E];
-#pragma unroll
-  for (int m = 0; m < nbl; ++m)
-#pragma unroll
-    for (int r = 0; r < Rl; ++r) o[m + r * nbl] = v[m * Rl + r];
-#pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = o[e];
+  __syncthreads();
+  return in;
 }
 
 }  // namespace zk

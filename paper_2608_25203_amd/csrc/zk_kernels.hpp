@@ -35,8 +35,14 @@ struct RowArgs {
   int nx;                // base-grid row length (physical fields)
   const double *pin0, *pin1;
   double *pout0, *pout1;
-  const cpx<real> *tw;  // exp(-2 pi i j / N), N = row FFT length
-  double kx_scale;      // 2 pi / Lx
+  const cpx<real> *tw;    // exp(-2 pi i j / N), N = row FFT length
+  double kx_scale;        // 2 pi / Lx
+  const float *colmax;    // [mixed field][nx/2]: per-column max |value| written by the lifts
+};
+
+// Per band element symbol data (see symval).
+struct SymEl {
+  double kk, g0, tp, pad;
 };
 
 template <typename real>
@@ -56,6 +62,9 @@ struct ColArgs {
   double depth;   // <= 0: deep water
   double inv_kc;  // 1 / kc of the taper
   int taper_on;
+  float *colmax;  // [mixed field][nx/2]: max |value| of each lifted column
+  const SymEl *sym;               // symbol table, base-spectrum layout
+  const double *filt_x, *filt_y;  // separable state filter factors
 };
 
 // ---- register-set dispatch (keeps every register array statically indexed)
@@ -90,13 +99,26 @@ __device__ __forceinline__ void with_any(int s, F &&f) {
   }
 }
 
+// element offsets inside one field (fields hold < 2^31 elements)
 template <typename real>
-__device__ __forceinline__ long long mix_index(int kx, int y, int rows) {
+__device__ __forceinline__ int mix_index(int kx, int y, int rows) {
   constexpr int CB = MixTile<real>::CB;
-  return ((long long)(kx / CB) * rows + y) * CB + (kx % CB);
+  return ((kx / CB) * rows + y) * CB + (kx % CB);
 }
-__device__ __forceinline__ long long base_index(int kx, int b, int ny) {
-  return ((long long)(kx / CBB) * ny + b) * CBB + (kx % CBB);
+__device__ __forceinline__ int base_index(int kx, int b, int ny) {
+  return ((kx / CBB) * ny + b) * CBB + (kx % CBB);
+}
+
+// XCD-aware block placement.  Consecutive block indices are dispatched
+// round-robin over the 8 XCDs, each with its own L2.  Units (rows or groups
+// of columns) that share 128-byte lines of a tiled field -- `per` units --
+// are given block indices that are congruent mod 8, so they run on one XCD
+// and share its L2 instead of each XCD fetching the line.  Identity when the
+// unit count does not split evenly.
+__device__ __forceinline__ int xcd_unit(int b, int nunits, int per) {
+  if (per <= 1 || nunits % (8 * per) != 0) return b;
+  const int x = b & 7, slot = b >> 3;
+  return ((slot / per) * 8 + x) * per + (slot % per);
 }
 
 // Max over one team of T threads.  Teams of up to 64 threads sit inside one
@@ -109,37 +131,75 @@ __device__ __forceinline__ float team_max(float v, float *red) {
 #pragma unroll
   for (int o = W / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
   if constexpr (T > 64) {
+    const int w0 = (threadIdx.x / T) * (T / 64);  // first wavefront of this team
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    v = red[0];
+    v = red[w0];
 #pragma unroll
-    for (int k = 1; k < T / 64; ++k) v = fmaxf(v, red[k]);
+    for (int k = 1; k < T / 64; ++k) v = fmaxf(v, red[w0 + k]);
   }
   return v;
 }
 
-// Power-of-two scale bringing a magnitude m to [1, 2) (exact; 1 for m == 0).
-__device__ __forceinline__ float pow2_scale(float m) {
-  return (m > 0.f && m < 3.0e38f) ? ldexpf(1.0f, -ilogbf(m)) : 1.0f;
+// Power-of-two scale s bringing a magnitude m to [1, 2), and 1/s (both
+// exact; 1 for m == 0).
+__device__ __forceinline__ float2 pow2_scale(float m) {
+  if (!(m > 0.f && m < 3.0e38f)) return make_float2(1.0f, 1.0f);
+  const int e = ilogbf(m);
+  return make_float2(ldexpf(1.0f, -e), ldexpf(1.0f, e));
 }
 
 // ---------------------------------------------------------------------------
-// Row pass: RPB teams per block, one row each, all running program
-// progs[prog0 + blockIdx.y].  Padded rows use E = 12 (N = 3nx/2), base rows
-// E = 8 (N = nx).  Row K = nx/2 = 4T spectral columns are stored.
+// Shape constants of a team: T threads, E first-pass elements per thread.
+// E % 3 == 0: a 3/2-padded transform of N = T E = 3n/2 points, whose n/2
+// retained band slots are r < E/3 (positive) and r >= 2E/3 (negative);
+// otherwise a base transform of N = n points, retained r < E/2 and r >= E/2.
+// In both cases the band has K = (E/3 or E/2) * T = n/2 positive modes, and
+// slot "first negative, t = 0" is the Nyquist mode (never stored).
+template <int T, int E>
+struct Shape {
+  static constexpr bool PADDED = (E % 3 == 0);
+  static constexpr int N = T * E;
+  static constexpr int KR = PADDED ? E / 3 : E / 2;    // positive slots
+  static constexpr int NEG0 = PADDED ? 2 * E / 3 : E / 2;  // first negative slot
+  static constexpr int QB = PADDED ? 2 * E / 3 : E;    // base-band elements per thread
+  static constexpr int TPB = 256 / T;                  // teams per 256-thread block
+  static constexpr int L = lds_len(N);
+  // two LDS buffers per team when they fit comfortably, else one
+  template <typename real>
+  static constexpr int nbuf() {
+    return (2 * TPB * L + N) * (int)sizeof(cpx<real>) <= 100 * 1024 ? 2 : 1;
+  }
+  template <typename real>
+  static constexpr bool tw_in_lds() {
+    return (nbuf<real>() * TPB * L + N) * (int)sizeof(cpx<real>) <= 100 * 1024;
+  }
+};
+
+// Row pass: TPB teams per block, one row each, all running program
+// progs[prog0 + blockIdx.y].
 template <typename real, int T, int E>
 __global__ __launch_bounds__(256) void row_kernel(RowArgs<real> a) {
-  constexpr int N = T * E;
-  constexpr int RPB = 256 / T;
-  constexpr int L = lds_len(N);
-  __shared__ cpx<real> smem[RPB * L];
+  using S = Shape<T, E>;
+  constexpr int N = S::N, L = S::L, NB = S::template nbuf<real>();
+  constexpr bool TWL = S::template tw_in_lds<real>();
+  __shared__ cpx<real> smem[S::TPB * NB * L];
+  __shared__ cpx<real> twl[TWL ? N : 1];
   __shared__ float red[8];
   const int team = threadIdx.x / T;
   const int t = threadIdx.x % T;
-  const int row = blockIdx.x * RPB + team;
-  cpx<real> *lds = smem + team * L;
+  // rows y and y+1 share 128-byte lines of the tiled fields
+  const int row = (S::TPB == 1 ? xcd_unit(blockIdx.x, a.rows, 2) : (int)blockIdx.x) * S::TPB + team;
+  cpx<real> *b0 = smem + team * NB * L;
+  cpx<real> *b1 = b0 + (NB - 1) * L;
   const RowProg pg = a.progs[a.prog0 + blockIdx.y];
+  const cpx<real> *tw = a.tw;
+  if constexpr (TWL) {
+    for (int i = threadIdx.x; i < N; i += 256) twl[i] = a.tw[i];
+    tw = twl;
+  }
+  __syncthreads();
 
   // Register sets: u = z[].x, v = z[].y (the FFT buffer), then A, o0, o1, o2.
   cpx<real> z[E];
@@ -150,8 +210,8 @@ __global__ __launch_bounds__(256) void row_kernel(RowArgs<real> a) {
   for (int s = 0; s < kRowRegs - 2; ++s)
 #pragma unroll
     for (int e = 0; e < E; ++e) R[s][e] = (real)0;
-  auto reg = [&](auto S, int e) -> real & {
-    constexpr int s = decltype(S)::value;
+  auto reg = [&](auto Sx, int e) -> real & {
+    constexpr int s = decltype(Sx)::value;
     if constexpr (s == RS_U) return z[e].x;
     else if constexpr (s == RS_V) return z[e].y;
     else return R[s - 2][e];
@@ -162,18 +222,34 @@ __global__ __launch_bounds__(256) void row_kernel(RowArgs<real> a) {
     switch (op.code) {
       case OP_LD2: {
         const cpx<real> *Fa = a.mix + (long long)op.fa * a.mix_stride;
-        const cpx<real> *Fb = a.mix + (long long)(op.fb >= 0 ? op.fb : 0) * a.mix_stride;
         const bool has_b = op.fb >= 0;
+        const cpx<real> *Fb = a.mix + (long long)(has_b ? op.fb : op.fa) * a.mix_stride;
         const bool dxa = op.fla & FL_DX, dxb = op.flb & FL_DX;
-        cpx<real> zt[E];
+        // The two real fields share one complex transform; each is scaled by
+        // a power of two from its field maximum (published by the lifts that
+        // wrote it) so that neither drowns in the rounding of the other, and
+        // unscaled exactly afterwards.
+        float ma = 0.f, mb = 0.f;
+        {
+          const float *ca = a.colmax + (long long)op.fa * (S::KR * T);
+          const float *cb = a.colmax + (long long)(has_b ? op.fb : op.fa) * (S::KR * T);
+#pragma unroll
+          for (int q = 0; q < S::KR; ++q) {
+            ma = fmaxf(ma, ca[t + T * q]);
+            mb = fmaxf(mb, cb[t + T * q]);
+          }
+        }
+        const float2 pa = pow2_scale(team_max<T>(ma, red));
+        const float2 pb = has_b ? pow2_scale(team_max<T>(mb, red)) : make_float2(1.f, 1.f);
+        const real sa = (real)pa.x, sb = (real)pb.x;
 #pragma unroll
         for (int r = 0; r < E; ++r) {
           cpx<real> za = {0, 0}, zb = {0, 0};
-          const bool pos = r < 4;
-          const bool neg = (r > E - 4) || (r == E - 4 && t > 0);
+          const bool pos = r < S::KR;
+          const bool neg = (r > S::NEG0) || (r == S::NEG0 && t > 0);
           if (pos || neg) {
             const int kk = pos ? (t + T * r) : ((E - r) * T - t);
-            const long long idx = mix_index<real>(kk, row, a.rows);
+            const int idx = mix_index<real>(kk, row, a.rows);
             za = Fa[idx];
             if (has_b) zb = Fb[idx];
             const real kxv = (real)(a.kx_scale * kk);
@@ -184,30 +260,19 @@ __global__ __launch_bounds__(256) void row_kernel(RowArgs<real> a) {
               zb.y = -zb.y;
             }
           }
-          z[r] = {za.x, za.y};
-          zt[r] = zb;
+          z[r] = {za.x * sa - zb.y * sb, za.y * sa + zb.x * sb};
         }
-        // The two real fields share one complex transform; each is scaled by
-        // a power of two from its row maximum so that neither drowns in the
-        // rounding of the other, and unscaled exactly afterwards.
-        float ma = 0.f, mb = 0.f;
+        const cpx<real> *res = team_fft<real, N, E, NB, +1>(z, b0, b1, tw, t);
+        const real ia = (real)pa.y, ib = (real)pb.y;
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-          ma = fmaxf(ma, fmaxf(fabsf((float)z[r].x), fabsf((float)z[r].y)));
-          mb = fmaxf(mb, fmaxf(fabsf((float)zt[r].x), fabsf((float)zt[r].y)));
+        for (int e = 0; e < E; ++e) {
+          const cpx<real> w = res[lpad(t + T * e)];
+          z[e] = {w.x * ia, w.y * ib};
         }
-        const real sa = (real)pow2_scale(team_max<T>(ma, red));
-        const real sb = (real)pow2_scale(team_max<T>(mb, red));
-#pragma unroll
-        for (int r = 0; r < E; ++r) z[r] = {z[r].x * sa - zt[r].y * sb, z[r].y * sa + zt[r].x * sb};
-        team_fft<real, N, E, +1>(z, lds, a.tw, t);
-        const real ia = (real)1 / sa, ib = (real)1 / sb;
-#pragma unroll
-        for (int e = 0; e < E; ++e) z[e] = {z[e].x * ia, z[e].y * ib};
         break;
       }
       case OP_LDP: {
-        if constexpr (E != 8) break;  // caller fields have base-length rows only
+        if constexpr (S::PADDED) break;  // caller fields have base-length rows only
         const double *pa = op.fa == 0 ? a.pin0 : a.pin1;
         const double *pb = op.fb == 0 ? a.pin0 : a.pin1;
         const long long off = (long long)row * a.nx;
@@ -220,9 +285,9 @@ __global__ __launch_bounds__(256) void row_kernel(RowArgs<real> a) {
       }
       case OP_MOV: {
         with_any(op.a, [&](auto D) {
-          with_any(op.b, [&](auto S) {
+          with_any(op.b, [&](auto Sx) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) reg(D, e) = reg(S, e);
+            for (int e = 0; e < E; ++e) reg(D, e) = reg(Sx, e);
           });
         });
         break;
@@ -250,58 +315,58 @@ __global__ __launch_bounds__(256) void row_kernel(RowArgs<real> a) {
         const real eps = (real)op.coef;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          const real S = (real)1 + eps * eps * R[RS_O0 - 2][e];
-          const real W = (z[e].x + eps * R[RS_O1 - 2][e]) / S;
-          R[RS_O0 - 2][e] = eps * ((real)-0.5 * R[RS_O2 - 2][e] + (real)0.5 * S * W * W);
+          const real Sv = (real)1 + eps * eps * R[RS_O0 - 2][e];
+          const real W = (z[e].x + eps * R[RS_O1 - 2][e]) / Sv;
+          R[RS_O0 - 2][e] = eps * ((real)-0.5 * R[RS_O2 - 2][e] + (real)0.5 * Sv * W * W);
         }
         break;
       }
       case OP_ST2: {
-        real tx[E], ty[E];
-        with_any(op.a, [&](auto X) {
+        // Sources are (u, v) in place, or sets outside the FFT buffer (the
+        // planner never pairs u or v with another set).
+        if (op.a != RS_U) {
+          with_any(op.a, [&](auto X) {
 #pragma unroll
-          for (int e = 0; e < E; ++e) tx[e] = reg(X, e);
-        });
-        if (op.b != RS_NONE) {
+            for (int e = 0; e < E; ++e) z[e].x = reg(X, e);
+          });
+        }
+        if (op.b == RS_NONE) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) z[e].y = (real)0;
+        } else if (op.b != RS_V) {
           with_any(op.b, [&](auto Y) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) ty[e] = reg(Y, e);
+            for (int e = 0; e < E; ++e) z[e].y = reg(Y, e);
           });
-        } else {
-#pragma unroll
-          for (int e = 0; e < E; ++e) ty[e] = (real)0;
         }
         float mx = 0.f, my = 0.f;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          mx = fmaxf(mx, fabsf((float)tx[e]));
-          my = fmaxf(my, fabsf((float)ty[e]));
+          mx = fmaxf(mx, fabsf((float)z[e].x));
+          my = fmaxf(my, fabsf((float)z[e].y));
         }
-        const real sx = (real)pow2_scale(team_max<T>(mx, red));
-        const real sy = (real)pow2_scale(team_max<T>(my, red));
+        const float2 px = pow2_scale(team_max<T>(mx, red));
+        const float2 py = pow2_scale(team_max<T>(my, red));
+        const real sx = (real)px.x, sy = (real)py.x;
 #pragma unroll
-        for (int e = 0; e < E; ++e) z[e] = {tx[e] * sx, ty[e] * sy};
-        team_fft<real, N, E, -1>(z, lds, a.tw, t);
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < E; ++e) lds[lpad(t + T * e)] = z[e];
-        __syncthreads();
+        for (int e = 0; e < E; ++e) z[e] = {z[e].x * sx, z[e].y * sy};
+        const cpx<real> *res = team_fft<real, N, E, NB, -1>(z, b0, b1, tw, t);
         cpx<real> *Fa = a.mix + (long long)op.fa * a.mix_stride;
         cpx<real> *Fb = a.mix + (long long)(op.fb >= 0 ? op.fb : 0) * a.mix_stride;
+        const real hx = (real)0.5 * (real)px.y, hy = (real)0.5 * (real)py.y;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < S::KR; ++q) {
           const int k = t + T * q;
-          const cpx<real> zk = lds[lpad(k)];
-          const cpx<real> zm = lds[lpad(k == 0 ? 0 : N - k)];
-          const long long idx = mix_index<real>(k, row, a.rows);
-          const real hx = (real)0.5 / sx, hy = (real)0.5 / sy;
+          const cpx<real> zk = res[lpad(k)];
+          const cpx<real> zm = res[lpad(k == 0 ? 0 : N - k)];
+          const int idx = mix_index<real>(k, row, a.rows);
           Fa[idx] = {hx * (zk.x + zm.x), hx * (zk.y - zm.y)};
           if (op.fb >= 0) Fb[idx] = {hy * (zk.y + zm.y), -hy * (zk.x - zm.x)};
         }
         break;
       }
       case OP_STP: {
-        if constexpr (E != 8) break;
+        if constexpr (S::PADDED) break;
         double *po = op.fa == 0 ? a.pout0 : a.pout1;
         const long long off = (long long)row * a.nx;
         with_any(op.a, [&](auto X) {
@@ -317,128 +382,143 @@ __global__ __launch_bounds__(256) void row_kernel(RowArgs<real> a) {
 }
 
 // ---------------------------------------------------------------------------
-// Fourier symbols at (kx, b) of the base band.
-__device__ __forceinline__ double filt1(int m, int n) {
-  const double th = 2.0 * M_PI * (double)m / (double)n;
-  return (5.0 + 4.0 * cos(th) - cos(2.0 * th)) * 0.125;
-}
-
-// symbol s at kx = col, ky mode my, |k| = kk, tanh(|k| d) = th
+// Fourier symbols at (kx, b) of the base band, from tables computed once on
+// the host in FP64: |k|, G0 = |k| tanh(|k| d) and the taper, per band element
+// (same tiled layout as a base spectrum); the state filter is separable,
+// A = Ax(kx) Ay(b).
 template <typename real>
-__device__ __forceinline__ cpx<double> symval(uint32_t s, int col, int my, double kk, double th,
-                                              const ColArgs<real> &a) {
+__device__ __forceinline__ cpx<double> symval(uint32_t s, double kk, double g0, double tp, int col, int b,
+                                              double ky, const ColArgs<real> &a) {
   double f = 1.0;
   const int l = s & SYM_LMASK;
-  if (l) {
-    double p = kk;
-    for (int i = 1; i < l; ++i) p *= kk;
-    f = (l & 1) ? p * th : p;
+  if (l) {  // L_l = G0 |k|^(l-1) for odd l, |k|^l for even l
+    f = (l & 1) ? g0 : kk;
+    for (int i = 1; i < l; ++i) f *= kk;
   }
-  if (s & SYM_FILT) f *= filt1(col, a.nx) * filt1(my, a.ny);
-  if ((s & SYM_TAPER) && a.taper_on) {
-    const double r2 = kk * kk * a.inv_kc * a.inv_kc;
-    const double r4 = r2 * r2;
-    f *= exp(-(r4 * r4));
-  }
-  if (s & SYM_IKY) return {0.0, f * (a.ky_scale * my)};
+  if (s & SYM_FILT) f *= a.filt_x[col] * a.filt_y[b];
+  if ((s & SYM_TAPER) && a.taper_on) f *= tp;
+  if (s & SYM_IKY) return {0.0, f * ky};
   return {f, 0.0};
 }
 
-// Column pass: CPB teams per block, one kx column each, all running task
-// tasks[task0 + blockIdx.y].  Padded columns use E = 12 (N = 3ny/2), base
-// columns E = 8 (N = ny).  Thread t owns base-band rows b = t + T q, q < 8.
+// Column pass: TPB teams per block, one kx column each, all running task
+// tasks[task0 + blockIdx.y].  Thread t owns base-band rows b = t + T q,
+// q < QB (q = KR at t = 0 is the ky Nyquist row, kept zero).
 template <typename real, int T, int E>
 __global__ __launch_bounds__(256) void col_kernel(ColArgs<real> a) {
-  constexpr int N = T * E;
-  constexpr int CPB = (256 / T < 4) ? 256 / T : 4;
-  constexpr int L = lds_len(N);
-  constexpr int CB = MixTile<real>::CB;
-  __shared__ cpx<real> smem[CPB * L];
+  using S = Shape<T, E>;
+  constexpr int N = S::N, L = S::L, NB = S::template nbuf<real>(), QB = S::QB;
+  constexpr bool TWL = S::template tw_in_lds<real>();
+  __shared__ cpx<real> smem[S::TPB * NB * L];
+  __shared__ cpx<real> twl[TWL ? N : 1];
+  __shared__ float red[8];
   const int team = threadIdx.x / T;
   const int t = threadIdx.x % T;
-  const int col = blockIdx.x * CPB + team;
-  cpx<real> *lds = smem + team * L;
+  // columns of one tile share 128-byte lines; keep a tile's blocks on one XCD
+  constexpr int CBMAX = MixTile<real>::CB > CBB ? MixTile<real>::CB : CBB;
+  const int col = xcd_unit(blockIdx.x, a.nx / 2 / S::TPB, CBMAX / S::TPB) * S::TPB + team;
+  cpx<real> *b0 = smem + team * NB * L;
+  cpx<real> *b1 = b0 + (NB - 1) * L;
   const ColTask task = a.tasks[a.task0 + blockIdx.y];
   const int ny = a.ny;
-
-  double kk[8], th[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int b = t + T * q;
-    const int my = (b < ny / 2) ? b : b - ny;
-    const double kx = a.kx_scale * col, ky = a.ky_scale * my;
-    kk[q] = sqrt(kx * kx + ky * ky);
-    th[q] = a.depth > 0.0 ? tanh(kk[q] * a.depth) : 1.0;
+  const cpx<real> *tw = a.tw;
+  if constexpr (TWL) {
+    for (int i = threadIdx.x; i < N; i += 256) twl[i] = a.tw[i];
+    tw = twl;
   }
+  __syncthreads();
+
   auto my_of = [&](int q) {
     const int b = t + T * q;
     return (b < ny / 2) ? b : b - ny;
   };
-
-  cpx<double> X[8];
+  // padded (or base) position of base element q
+  auto pos_of = [&](int q) { return t + T * (q < S::KR ? q : q + (S::PADDED ? E / 3 : 0)); };
+  double skk[QB], sg0[QB], stp[QB];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) X[q] = {0.0, 0.0};
+  for (int q = 0; q < QB; ++q) {
+    const SymEl e = a.sym[base_index(col, t + T * q, ny)];
+    skk[q] = e.kk;
+    sg0[q] = e.g0;
+    stp[q] = e.tp;
+  }
+  auto sym = [&](uint32_t s, int q) -> cpx<double> {
+    return symval(s, skk[q], sg0[q], stp[q], col, t + T * q, a.ky_scale * my_of(q), a);
+  };
+
+  cpx<double> X[QB];
+#pragma unroll
+  for (int q = 0; q < QB; ++q) X[q] = {0.0, 0.0};
   if (task.fwd >= 0) {
     const cpx<real> *F = a.mix + (long long)task.fwd * a.mix_stride;
     cpx<real> v[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) v[r] = F[mix_index<real>(col, t + T * r, a.rows)];
-    team_fft<real, N, E, -1>(v, lds, a.tw, t);
+    const cpx<real> *res = team_fft<real, N, E, NB, -1>(v, b0, b1, tw, t);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int src = (E == 12 && q >= 4) ? q + 4 : q;
-      const cpx<double> s = symval(task.fwd_sym, col, my_of(q), kk[q], th[q], a);
-      const cpx<double> x = {(double)v[src].x * task.fwd_coef, (double)v[src].y * task.fwd_coef};
-      X[q] = {x.x * s.x - x.y * s.y, x.x * s.y + x.y * s.x};
+    for (int q = 0; q < QB; ++q) {
+      const cpx<real> w = res[lpad(pos_of(q))];
+      const cpx<double> sv = sym(task.fwd_sym, q);
+      const cpx<double> x = {(double)w.x * task.fwd_coef, (double)w.y * task.fwd_coef};
+      X[q] = {x.x * sv.x - x.y * sv.y, x.x * sv.y + x.y * sv.x};
     }
-    if (t == 0) X[4] = {0.0, 0.0};  // ky Nyquist row
+    if (t == 0) X[S::KR] = {0.0, 0.0};  // ky Nyquist row
   }
 
   for (int o = 0; o < task.no; ++o) {
     const ColOut out = a.outs[task.o0 + o];
-    cpx<double> acc[8];
+    cpx<double> acc[QB];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = {0.0, 0.0};
+    for (int q = 0; q < QB; ++q) acc[q] = {0.0, 0.0};
     for (int i = 0; i < out.nt; ++i) {
       const ColTerm tm = a.terms[out.t0 + i];
-      cpx<double> s0[8];
       if (tm.src >= 0) {
         const cpx<double> *B = a.base + (long long)tm.src * a.base_stride;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) s0[q] = B[base_index(col, t + T * q, ny)];
+        for (int q = 0; q < QB; ++q) {
+          const cpx<double> s0 = B[base_index(col, t + T * q, ny)];
+          cpx<double> sv = sym(tm.sym, q);
+          sv = {sv.x * tm.coef, sv.y * tm.coef};
+          acc[q].x += s0.x * sv.x - s0.y * sv.y;
+          acc[q].y += s0.x * sv.y + s0.y * sv.x;
+        }
       } else {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) s0[q] = X[q];
-      }
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        cpx<double> s = symval(tm.sym, col, my_of(q), kk[q], th[q], a);
-        s = {s.x * tm.coef, s.y * tm.coef};
-        acc[q].x += s0[q].x * s.x - s0[q].y * s.y;
-        acc[q].y += s0[q].x * s.y + s0[q].y * s.x;
+        for (int q = 0; q < QB; ++q) {
+          cpx<double> sv = sym(tm.sym, q);
+          sv = {sv.x * tm.coef, sv.y * tm.coef};
+          acc[q].x += X[q].x * sv.x - X[q].y * sv.y;
+          acc[q].y += X[q].x * sv.y + X[q].y * sv.x;
+        }
       }
     }
-    if (t == 0) acc[4] = {0.0, 0.0};
+    if (t == 0) acc[S::KR] = {0.0, 0.0};
     if (out.dst_base >= 0) {
       cpx<double> *B = a.base + (long long)out.dst_base * a.base_stride;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) B[base_index(col, t + T * q, ny)] = acc[q];
+      for (int q = 0; q < QB; ++q) B[base_index(col, t + T * q, ny)] = acc[q];
     }
     if (out.dst_mixed >= 0) {
       const double lc = out.lift_coef;
       cpx<real> z[E];
 #pragma unroll
-      for (int r = 0; r < E; ++r) {
-        int q = -1;
-        if (E == 8) q = r;
-        else if (r < 4) q = r;
-        else if (r >= 8) q = r - 4;
-        z[r] = q >= 0 ? cpx<real>{(real)(acc[q].x * lc), (real)(acc[q].y * lc)} : cpx<real>{0, 0};
-      }
-      team_fft<real, N, E, +1>(z, lds, a.tw, t);
-      cpx<real> *F = a.mix + (long long)out.dst_mixed * a.mix_stride;
+      for (int r = 0; r < E; ++r) z[r] = {(real)0, (real)0};
 #pragma unroll
-      for (int r = 0; r < E; ++r) F[mix_index<real>(col, t + T * r, a.rows)] = z[r];
+      for (int q = 0; q < QB; ++q) {
+        const int r = q < S::KR ? q : q + (S::PADDED ? E / 3 : 0);
+        z[r] = {(real)(acc[q].x * lc), (real)(acc[q].y * lc)};
+      }
+      const cpx<real> *res = team_fft<real, N, E, NB, +1>(z, b0, b1, tw, t);
+      cpx<real> *F = a.mix + (long long)out.dst_mixed * a.mix_stride;
+      float m = 0.f;
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const cpx<real> w = res[lpad(t + T * r)];
+        F[mix_index<real>(col, t + T * r, a.rows)] = w;
+        m = fmaxf(m, fmaxf(fabsf((float)w.x), fabsf((float)w.y)));
+      }
+      m = team_max<T>(m, red);
+      if (t == 0) a.colmax[(long long)out.dst_mixed * (a.nx / 2) + col] = m;
     }
   }
 }

@@ -579,6 +579,7 @@ std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
         case OP_ST2:
           if (o.fa < 0 || o.fa >= p.nmix || o.fb >= p.nmix) return bad("ST2 field");
           if (o.a > RS_O2 || (o.b != RS_NONE && o.b > RS_O2)) return bad("ST2 reg");
+          if ((o.a == RS_U) != (o.b == RS_V) || o.a == RS_V || o.b == RS_U) return bad("ST2 pairs u with a set");
           break;
         case OP_LDP:
           if (o.fa < 0 || o.fa > 1 || o.fb > 1) return bad("LDP slot");

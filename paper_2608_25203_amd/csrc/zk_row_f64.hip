@@ -3,27 +3,58 @@
 
 namespace zk {
 
-template <int E>
-static bool row_launch_e(const RowArgs<double> &a, int T, dim3 grid, hipStream_t s) {
-  switch (T) {
-    case 8: hipLaunchKernelGGL((row_kernel<double, 8, E>), grid, dim3(256), 0, s, a); return true;
-    case 16: hipLaunchKernelGGL((row_kernel<double, 16, E>), grid, dim3(256), 0, s, a); return true;
-    case 32: hipLaunchKernelGGL((row_kernel<double, 32, E>), grid, dim3(256), 0, s, a); return true;
-    case 64: hipLaunchKernelGGL((row_kernel<double, 64, E>), grid, dim3(256), 0, s, a); return true;
-    case 128: hipLaunchKernelGGL((row_kernel<double, 128, E>), grid, dim3(256), 0, s, a); return true;
-    case 256: hipLaunchKernelGGL((row_kernel<double, 256, E>), grid, dim3(256), 0, s, a); return true;
-    default: return false;
-  }
-}
-
 template <>
 hipError_t launch_row<double>(const RowArgs<double> &a, int T, int E, int nblocks, int nsub, hipStream_t s) {
   const dim3 grid(nblocks, nsub);
-  bool ok = false;
-  if (E == 12) ok = row_launch_e<12>(a, T, grid, s);
-  else if (E == 8) ok = row_launch_e<8>(a, T, grid, s);
-  if (!ok) return hipErrorInvalidValue;
-  return hipGetLastError();
+  if (T == 32 && E == 3) {
+    hipLaunchKernelGGL((row_kernel<double, 32, 3>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (T == 32 && E == 2) {
+    hipLaunchKernelGGL((row_kernel<double, 32, 2>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (T == 64 && E == 3) {
+    hipLaunchKernelGGL((row_kernel<double, 64, 3>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (T == 64 && E == 2) {
+    hipLaunchKernelGGL((row_kernel<double, 64, 2>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 3) {
+    hipLaunchKernelGGL((row_kernel<double, 128, 3>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 2) {
+    hipLaunchKernelGGL((row_kernel<double, 128, 2>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (T == 256 && E == 3) {
+    hipLaunchKernelGGL((row_kernel<double, 256, 3>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (T == 256 && E == 6) {
+    hipLaunchKernelGGL((row_kernel<double, 256, 6>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (T == 256 && E == 12) {
+    hipLaunchKernelGGL((row_kernel<double, 256, 12>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (T == 256 && E == 2) {
+    hipLaunchKernelGGL((row_kernel<double, 256, 2>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (T == 256 && E == 4) {
+    hipLaunchKernelGGL((row_kernel<double, 256, 4>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  if (T == 256 && E == 8) {
+    hipLaunchKernelGGL((row_kernel<double, 256, 8>), grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace zk
