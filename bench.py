@@ -58,6 +58,36 @@ def cpu_baseline(w, eta, psi, nsteps):
             "sample": f"{nsteps} RK4 steps of the benchmark workload ({t:.1f} s, pocketfft workers={workers})"}
 
 
+def kernel_source_hash():
+    """Hash of the HIP kernel sources: counter records apply to this build only."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "paper_2608_25203_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    record (FETCH_SIZE and WRITE_SIZE runs scaled by a copy calibration), or
+    None when the record is missing or was taken on other kernel sources."""
+    path = os.path.join(HERE, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    key = f"{workload}/fp{precision}/{kernel}"
+    r = rec.get(key)
+    if not r or r.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return r["bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,7 +161,8 @@ def main():
     d = kern[dom]
     achieved = d["GB_per_s"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(args.workload, args.precision, dom), "kernel": dom,
                 "kernel_avg_us": round(d["avg_us"], 2),
                 "alg_bytes_per_launch": d["alg_bytes_per_launch"],
                 "fft_GFLOP_per_s": round(d["fft_GFLOP_per_s"], 1),

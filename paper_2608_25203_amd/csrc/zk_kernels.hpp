@@ -142,6 +142,35 @@ __device__ __forceinline__ float team_max(float v, float *red) {
   return v;
 }
 
+// Max of two values over one team at once (same scheme as team_max).
+// red: >= 8 floats of LDS.
+template <int T>
+__device__ __forceinline__ float2 team_max2(float a, float b, float *red) {
+  constexpr int W = T < 64 ? T : 64;
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) {
+    a = fmaxf(a, __shfl_xor(a, o, 64));
+    b = fmaxf(b, __shfl_xor(b, o, 64));
+  }
+  if constexpr (T > 64) {
+    const int w0 = (threadIdx.x / T) * (T / 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+      red[2 * (threadIdx.x >> 6)] = a;
+      red[2 * (threadIdx.x >> 6) + 1] = b;
+    }
+    __syncthreads();
+    a = red[2 * w0];
+    b = red[2 * w0 + 1];
+#pragma unroll
+    for (int k = 1; k < T / 64; ++k) {
+      a = fmaxf(a, red[2 * (w0 + k)]);
+      b = fmaxf(b, red[2 * (w0 + k) + 1]);
+    }
+  }
+  return make_float2(a, b);
+}
+
 // Power-of-two scale s bringing a magnitude m to [1, 2), and 1/s (both
 // exact; 1 for m == 0).
 __device__ __forceinline__ float2 pow2_scale(float m) {
@@ -239,8 +268,9 @@ __global__ __launch_bounds__(256) void row_kernel(RowArgs<real> a) {
             mb = fmaxf(mb, cb[t + T * q]);
           }
         }
-        const float2 pa = pow2_scale(team_max<T>(ma, red));
-        const float2 pb = has_b ? pow2_scale(team_max<T>(mb, red)) : make_float2(1.f, 1.f);
+        const float2 mm = team_max2<T>(ma, mb, red);
+        const float2 pa = pow2_scale(mm.x);
+        const float2 pb = has_b ? pow2_scale(mm.y) : make_float2(1.f, 1.f);
         const real sa = (real)pa.x, sb = (real)pb.x;
 #pragma unroll
         for (int r = 0; r < E; ++r) {
@@ -345,8 +375,9 @@ __global__ __launch_bounds__(256) void row_kernel(RowArgs<real> a) {
           mx = fmaxf(mx, fabsf((float)z[e].x));
           my = fmaxf(my, fabsf((float)z[e].y));
         }
-        const float2 px = pow2_scale(team_max<T>(mx, red));
-        const float2 py = pow2_scale(team_max<T>(my, red));
+        const float2 mxy = team_max2<T>(mx, my, red);
+        const float2 px = pow2_scale(mxy.x);
+        const float2 py = pow2_scale(mxy.y);
         const real sx = (real)px.x, sy = (real)py.x;
 #pragma unroll
         for (int e = 0; e < E; ++e) z[e] = {z[e].x * sx, z[e].y * sy};
