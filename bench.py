@@ -88,6 +88,117 @@ def measured_traffic(workload, precision, kernel):
     return r["bytes_per_launch"]
 
 
+def rel_max(a, b):
+    """max |a - b| / max |b| over one field (the error measure of the parity tests)."""
+    return float((a - b).abs().max().item() / max(b.abs().max().item(), 1e-300))
+
+
+def precision_form(segments=(1, 9, 90, 400)):
+    """FP32-transform form against the FP64 run on the 2048 x 2048, M = 5
+    workload: both advance the same JONSWAP state for sum(segments) RK4 steps
+    (in calls of the given lengths); reported are each run's grid-point-steps/s
+    and the max relative eta and psi error of the FP32 form after each call."""
+    import torch
+
+    from paper_2608_25203_amd.inputs import WORKLOADS, jonswap_state
+    from paper_2608_25203_amd.zk import Solver
+
+    w = WORKLOADS["c3_2048_m5"]
+    eta, psi = jonswap_state(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"], w["kp"], w["steepness"],
+                             w["seed"])
+    dev = torch.device("cuda:0")
+    runs = {}
+    for prec in (64, 32):
+        s = Solver(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"], w["M"], precision=prec, check=False,
+                   device=dev)
+        e = torch.tensor(eta, dtype=torch.float64, device=dev)
+        p = torch.tensor(psi, dtype=torch.float64, device=dev)
+        ew, pw = e.clone(), p.clone()
+        s.step(ew, pw, w["dt"], 2)  # warmup on a copy (uploads the schedule)
+        del ew, pw
+        torch.cuda.synchronize()
+        snaps, t = [], 0.0
+        for k in segments:
+            t0 = time.perf_counter()
+            s.step(e, p, w["dt"], k)
+            torch.cuda.synchronize()
+            t += time.perf_counter() - t0
+            snaps.append((e.clone(), p.clone()) if prec == 64 else (e, p))
+            if prec == 32:
+                e64, p64 = runs[64]["snaps"][len(snaps) - 1]
+                snaps[-1] = (rel_max(e, e64), rel_max(p, p64))
+                e, p = e.clone(), p.clone()
+        runs[prec] = {"snaps": snaps, "time": t}
+        print(f"# precision form: fp{prec} {sum(segments)} steps in {t:.2f} s", file=sys.stderr, flush=True)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    nsteps = sum(segments)
+    npts = w["nx"] * w["ny"]
+    cum = [sum(segments[:i + 1]) for i in range(len(segments))]
+    errs = [{"step": c, "eta_rel_err": round(a, 9), "psi_rel_err": round(b, 9)}
+            for c, (a, b) in zip(cum, runs[32]["snaps"])]
+    v64 = npts * nsteps / runs[64]["time"]
+    v32 = npts * nsteps / runs[32]["time"]
+    worst = max(max(d["eta_rel_err"], d["psi_rel_err"]) for d in errs)
+    return {"workload": f"c3_2048_m5: {w['nx']}x{w['ny']}, 2pi x 2pi, deep, M={w['M']}, RK4 dt={w['dt']}, "
+                        f"JONSWAP steepness {w['steepness']}, {nsteps} steps",
+            "fp64_value": round(v64, 1), "fp32_value": round(v32, 1), "unit": "grid-point-steps/s",
+            "speedup": round(v32 / v64, 3), "errors_vs_fp64": errs, "max_rel_err": worst,
+            "within_1e-4": bool(worst <= 1e-4)}
+
+
+def c2_diagnostics(w, H_before, H_after):
+    """Hamiltonian drift of the timed run and the linear-limit dispersion error
+    (eps = 0, filter off) of single modes on the benchmark grid: measured
+    frequency against omega = sqrt(g k tanh(k h)), beside the closed form
+    arg R(i omega dt) / (omega dt) - 1 of classical RK4."""
+    import numpy as np
+    import torch
+
+    from paper_2608_25203_amd.zk import Solver
+
+    out = {"H_drift_rel": (H_after - H_before) / H_before}
+    dev = torch.device("cuda:0")
+    # the same run with the state filter off separates its damping from the drift
+    from paper_2608_25203_amd.inputs import jonswap_state
+
+    eta0, psi0 = jonswap_state(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"], w["kp"], w["steepness"],
+                               w["seed"])
+    s = Solver(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"], w["M"], filt=False, check=False, device=dev)
+    e = torch.tensor(eta0, dtype=torch.float64, device=dev)
+    p = torch.tensor(psi0, dtype=torch.float64, device=dev)
+    H0 = s.hamiltonian(e, p)
+    s.step(e, p, w["dt"], w["steps"])
+    out["H_drift_rel_filter_off"] = (s.hamiltonian(e, p) - H0) / H0
+    out["H_drift_steps"] = w["steps"]
+    s.close()
+    nx, ny, Lx, h, g, dt = w["nx"], w["ny"], w["Lx"], w["depth"], w["g"], w["dt"]
+    s = Solver(nx, ny, Lx, w["Ly"], h, g, w["M"], eps=0.0, filt=False, check=False, device=dev)
+    x = np.arange(nx) * Lx / nx
+    disp = []
+    for m in (int(round(w["kp"] * Lx / (2 * np.pi))), nx // 2 - 1):
+        k = 2 * np.pi * m / Lx
+        om = math.sqrt(g * k * math.tanh(k * h))
+        th = om * dt
+        K = max(1, int(2.5 / th))
+        eta = np.tile(1e-3 * np.cos(k * x), (ny, 1))
+        psi = np.tile(1e-3 * g / om * np.sin(k * x), (ny, 1))
+        e = torch.tensor(eta, dtype=torch.float64, device=dev)
+        p = torch.tensor(psi, dtype=torch.float64, device=dev)
+        s.step(e, p, dt, K)
+        c0 = np.fft.rfft(eta[0])[m]
+        c1 = np.fft.rfft(e[0].cpu().numpy())[m]
+        om_num = -np.angle(c1 / c0) / (K * dt)
+        z = 1j * th
+        R = 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+        disp.append({"mode": m, "k": k, "omega": om, "steps": K, "measured_rel_err": om_num / om - 1,
+                     "rk4_closed_form": float(np.angle(R) / th - 1)})
+    s.close()
+    out["dispersion"] = disp
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +208,8 @@ def main():
     ap.add_argument("--precision", type=int, default=64, choices=(32, 64))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the precision-form comparison on the 2048^2 M=5 workload")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -135,12 +248,14 @@ def main():
         s.step(e, p, w["dt"], args.warmup)
     torch.cuda.synchronize()
 
+    H_before = s.hamiltonian(e, p)
     # timed region: exactly `steps` RK4 steps in one call, inputs resident in HBM
     t0 = time.perf_counter()
     s.step(e, p, w["dt"], args.steps)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     finite = bool(torch.isfinite(e).all().item() and torch.isfinite(p).all().item())
+    H_after = s.hamiltonian(e, p)
     npts = w["nx"] * w["ny"]
     value = npts * args.steps / t
 
@@ -192,6 +307,10 @@ def main():
         "kernel_ms_per_step": round(step_kernel_ms, 4),
         "finite": finite,
     }
+    if args.workload == "c2_512_m4":
+        out["c2_diagnostics"] = c2_diagnostics(w, H_before, H_after)
+    if not args.no_forms:
+        out["precision_form"] = precision_form()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, eta, psi, args.cpu_steps)
         out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 1)

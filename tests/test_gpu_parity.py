@@ -165,3 +165,27 @@ def test_fp32_transforms_fp64_series(torch, M):
     s.step(e, p, 0.005, 1)
     e0, p0 = m.step(eta, psi, 0.005, 1)
     assert rel(host(e), e0) < 2e-6 and rel(host(p), p0) < 2e-6
+
+
+@pytest.mark.timeout(600)
+def test_c3_shape_parity_fp64_and_fp32(torch):
+    """2048 x 2048, deep water, M = 5, JONSWAP steepness 0.15 (the precision
+    workload): the RHS in FP64 (1e-10) and in the FP32-transform form (2e-5),
+    and H, against one oracle evaluation."""
+    w = WORKLOADS["c3_2048_m5"]
+    eta, psi = jonswap_state(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"], w["kp"], w["steepness"], w["seed"])
+    from oracle.hos import PocketDFT
+
+    m = HOSModel(Grid(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], dft=PocketDFT(workers=16)), w["M"])
+    a0, b0 = m.rhs(eta, psi)
+    H0 = m.hamiltonian(eta, psi)
+    for prec, tol, htol in ((64, 1e-10, 1e-12), (32, 2e-5, 1e-6)):
+        s = solver(torch, w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["M"], precision=prec)
+        e, p = dev(torch, eta), dev(torch, psi)
+        a, b = s.rhs(e, p)
+        print(f"  fp{prec}:", flush=True)
+        assert rel(host(a), a0) < tol and rel(host(b), b0) < tol
+        assert abs(s.hamiltonian(e, p) / H0 - 1) < htol
+        s.close()
+        del s
+        torch.cuda.empty_cache()
