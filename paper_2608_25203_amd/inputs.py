@@ -127,3 +127,21 @@ def workload_state(name, **over):
     eta, psi = jonswap_state(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"],
                              w["kp"], w["steepness"], w["seed"])
     return w, eta, psi
+
+
+def cnn_init_params(seed, channels=(3, 32, 32, 32, 1)):
+    """Seeded initial weights of the closure network: for each layer a
+    (C_out, C_in, 3, 3) weight drawn N(0, 2 / (9 C_in)) (He) and a zero bias
+    (C_out,); the last layer's weights are scaled by 0.1 so the initial
+    prediction is small.  float64 arrays, in parameter order W1, b1, ... ."""
+    rng = np.random.default_rng(seed)
+    out = []
+    nl = len(channels) - 1
+    for l in range(nl):
+        ci, co = channels[l], channels[l + 1]
+        w = rng.standard_normal((co, ci, 3, 3)) * math.sqrt(2.0 / (9 * ci))
+        if l == nl - 1:
+            w *= 0.1
+        out.append(w)
+        out.append(np.zeros(co))
+    return out
