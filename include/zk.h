@@ -138,6 +138,61 @@ int zk_kernel_stats(zk_ctx *ctx, int kind, double *ms, double *bytes, double *fl
  * call on the context. */
 const char *zk_last_error(const zk_ctx *ctx);
 
+/* ---------------------------------------------------------------------------
+ * Learned closure network.
+ *
+ * A reduced-order DtN (the paper's Order-2 model, Sec. 3.2, is its cheapest
+ * truncation; every further order adds a comparable cost, Sec. 8) plus a
+ * small convolutional network that predicts the missing part
+ * r = (G^[6] - G^[2]) psi from eta, psi and G^[2] psi on the grid.  The
+ * network: four 3 x 3 convolutions with circular padding, 3 -> 32 -> 32 -> 32
+ * -> 1 channels, exact-erf GELU after the first three; bf16 weights and
+ * activations, FP32 accumulation (layers 2 and 3 on the matrix cores);
+ * FP32 master weights trained with Adam (beta1 0.9, beta2 0.999, eps 1e-8)
+ * on a masked mean-squared error.
+ *
+ * Parameter vector (ZK_CNN_NPARAMS floats, host memory): W1 b1 W2 b2 W3 b3
+ * W4 b4 with W of shape (C_out, C_in, 3, 3) in C order; convolution is
+ * cross-correlation, y[o](i, j) = b[o] + sum W[o][c][u][v] x[c](i+u-1, j+v-1)
+ * with indices taken modulo the tile.
+ *
+ * Samples (device, float): [B][4][H][W], planes 0..2 the input channels,
+ * plane 3 the target (ignored by zk_cnn_forward).  Outputs y (device,
+ * float): [B][H][W].  Tiles need W % 32 == 0 (W % 64 == 0 for training),
+ * H >= 3 and B*H*W <= max_pixels.  The network owns no device memory: the
+ * caller binds one workspace, as for zk_ctx; every call is asynchronous on
+ * the bound stream unless it returns host data.
+ * ------------------------------------------------------------------------- */
+typedef struct zk_cnn zk_cnn;
+#define ZK_CNN_NPARAMS 19681
+
+/* Network able to run tiles of up to max_pixels pixels (B*H*W).  NULL if
+ * max_pixels is outside [96, 2^28].  Host-side only. */
+zk_cnn *zk_cnn_create(long long max_pixels);
+void zk_cnn_destroy(zk_cnn *net);
+size_t zk_cnn_workspace_bytes(const zk_cnn *net);
+/* Bind a caller-owned device workspace (256-byte aligned) and a stream. */
+int zk_cnn_bind(zk_cnn *net, void *workspace, size_t bytes, void *stream);
+/* Load FP32 parameters from host memory and reset the Adam moments
+ * (synchronises the stream). */
+int zk_cnn_set_params(zk_cnn *net, const float *params_host);
+/* Copy the current FP32 parameters to host memory (synchronises). */
+int zk_cnn_get_params(zk_cnn *net, float *params_host);
+/* y = network(samples planes 0..2). */
+int zk_cnn_forward(zk_cnn *net, const float *samples, float *y, int B, int H, int W);
+/* Loss (mean of (y - target)^2 over the pixels at least `halo` from every
+ * tile edge) and its gradient with respect to every parameter, written to
+ * host memory (ZK_CNN_NPARAMS floats).  With halo >= 4 the circular padding
+ * never reaches a pixel that influences the loss, so a crop trains as a
+ * valid convolution.  Synchronises. */
+int zk_cnn_gradient(zk_cnn *net, const float *samples, int B, int H, int W, int halo, double *loss_host,
+                    float *grad_host);
+/* One Adam step on the masked loss with learning rate lr.  loss_host may be
+ * NULL (then the call stays asynchronous). */
+int zk_cnn_train_step(zk_cnn *net, const float *samples, int B, int H, int W, int halo, double lr,
+                      double *loss_host);
+const char *zk_cnn_last_error(const zk_cnn *net);
+
 #ifdef __cplusplus
 }
 #endif

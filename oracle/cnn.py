@@ -21,9 +21,10 @@ Conventions (shared, by definition, with the GPU kernels):
   * parameter vector order: W1, b1, W2, b2, W3, b3, W4, b4 (flattened C order).
 
 Optional bf16 emulation (`bf16=True`) rounds, at the points where the GPU
-path stores bf16, the conv operands (weights and input activations) to
-bfloat16 (round to nearest even) before an FP64 product, so that the GPU
-training kernels can be compared element by element.
+path stores bf16, the conv operands (weights, input activations and the
+backpropagated pre-activation gradients) to bfloat16 (round to nearest even)
+before an FP64 product, so that the GPU training kernels can be compared
+element by element.  Biases and the loss stay unrounded.
 
 Everything here is numpy (FP64) and written for clarity, not speed: im2col
 with explicit index arithmetic, no blocking.
@@ -154,6 +155,7 @@ class CNN:
             aq, Wq, z = cache[l]
             if l < self.nlayers - 1:
                 d = d * gelu_grad(z)
+            d = self._q(d)  # the GPU path stores pre-activation gradients in bf16
             B, C, H, W = aq.shape
             O = Wq.shape[0]
             dz = d.transpose(0, 2, 3, 1).reshape(-1, O)  # (B*H*W, O)

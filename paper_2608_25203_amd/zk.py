@@ -18,7 +18,10 @@ ZK_KERNEL_ROW_PAD, ZK_KERNEL_ROW_BASE, ZK_KERNEL_COL_PAD, ZK_KERNEL_COL_BASE, ZK
 KERNEL_NAMES = {0: "row_pad", 1: "row_base", 2: "col_pad", 3: "col_base", 4: "reduce"}
 
 EXPORTS = ("zk_create", "zk_destroy", "zk_set_option", "zk_workspace_bytes", "zk_bind", "zk_dtn",
-           "zk_rhs", "zk_step", "zk_hamiltonian", "zk_kernel_stats", "zk_last_error")
+           "zk_rhs", "zk_step", "zk_hamiltonian", "zk_kernel_stats", "zk_last_error",
+           "zk_cnn_create", "zk_cnn_destroy", "zk_cnn_workspace_bytes", "zk_cnn_bind", "zk_cnn_set_params",
+           "zk_cnn_get_params", "zk_cnn_forward", "zk_cnn_gradient", "zk_cnn_train_step", "zk_cnn_last_error")
+ZK_CNN_NPARAMS = 19681
 
 _lib = None
 
@@ -61,6 +64,24 @@ def lib():
     L.zk_kernel_stats.restype = i
     L.zk_last_error.argtypes = [vp]
     L.zk_last_error.restype = ctypes.c_char_p
+    ll, pd, pf = ctypes.c_longlong, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_float)
+    L.zk_cnn_create.argtypes = [ll]
+    L.zk_cnn_create.restype = vp
+    L.zk_cnn_destroy.argtypes = [vp]
+    L.zk_cnn_destroy.restype = None
+    L.zk_cnn_workspace_bytes.argtypes = [vp]
+    L.zk_cnn_workspace_bytes.restype = sz
+    L.zk_cnn_bind.argtypes = [vp, vp, sz, vp]
+    L.zk_cnn_set_params.argtypes = [vp, pf]
+    L.zk_cnn_get_params.argtypes = [vp, pf]
+    L.zk_cnn_forward.argtypes = [vp, vp, vp, i, i, i]
+    L.zk_cnn_gradient.argtypes = [vp, vp, i, i, i, i, pd, pf]
+    L.zk_cnn_train_step.argtypes = [vp, vp, i, i, i, i, d, pd]
+    for f in ("zk_cnn_bind", "zk_cnn_set_params", "zk_cnn_get_params", "zk_cnn_forward", "zk_cnn_gradient",
+              "zk_cnn_train_step"):
+        getattr(L, f).restype = i
+    L.zk_cnn_last_error.argtypes = [vp]
+    L.zk_cnn_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -194,6 +215,99 @@ class Solver:
         if getattr(self, "ctx", None):
             zk_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- closure network ------------------------------------------------------------------
+def _cnn_check(net, rc):
+    if rc != ZK_OK:
+        raise ZKError(rc, lib().zk_cnn_last_error(net).decode())
+    return rc
+
+
+class Net:
+    """The closure network (zk_cnn_*) bound to a torch-owned workspace.
+
+    Samples are float32 CUDA tensors [B, 4, H, W] (planes 0..2 input,
+    plane 3 target); parameters are float32 numpy vectors of ZK_CNN_NPARAMS."""
+
+    def __init__(self, max_pixels, device="cuda"):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.net = lib().zk_cnn_create(int(max_pixels))
+        if not self.net:
+            raise ZKError(ZK_EINVAL, "zk_cnn_create rejected max_pixels")
+        nbytes = int(lib().zk_cnn_workspace_bytes(self.net))
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self.ws.data_ptr()) % 256
+            self.stream = torch.cuda.current_stream(self.device)
+            _cnn_check(self.net, lib().zk_cnn_bind(self.net, self.ws.data_ptr() + off, nbytes,
+                                                   self.stream.cuda_stream))
+
+    @staticmethod
+    def _fp(a):
+        import numpy as np
+
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+    def _samples(self, s):
+        t = self.torch
+        if s.dtype != t.float32 or s.dim() != 4 or s.shape[1] != 4 or not s.is_contiguous():
+            raise ValueError("samples must be a contiguous float32 tensor [B, 4, H, W]")
+        return s
+
+    def set_params(self, params):
+        a, p = self._fp(params)
+        if a.size != ZK_CNN_NPARAMS:
+            raise ValueError("parameter vector has the wrong length")
+        _cnn_check(self.net, lib().zk_cnn_set_params(self.net, p))
+
+    def get_params(self):
+        import numpy as np
+
+        out = np.empty(ZK_CNN_NPARAMS, dtype=np.float32)
+        _cnn_check(self.net, lib().zk_cnn_get_params(self.net, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def forward(self, samples):
+        s = self._samples(samples)
+        B, _, H, W = s.shape
+        y = self.torch.empty((B, H, W), dtype=self.torch.float32, device=self.device)
+        _cnn_check(self.net, lib().zk_cnn_forward(self.net, s.data_ptr(), y.data_ptr(), B, H, W))
+        return y
+
+    def gradient(self, samples, halo):
+        import numpy as np
+
+        s = self._samples(samples)
+        B, _, H, W = s.shape
+        loss = ctypes.c_double(0.0)
+        g = np.empty(ZK_CNN_NPARAMS, dtype=np.float32)
+        _cnn_check(self.net, lib().zk_cnn_gradient(self.net, s.data_ptr(), B, H, W, int(halo), ctypes.byref(loss),
+                                                   g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return loss.value, g
+
+    def train_step(self, samples, halo, lr, want_loss=False):
+        s = self._samples(samples)
+        B, _, H, W = s.shape
+        loss = ctypes.c_double(0.0)
+        _cnn_check(self.net, lib().zk_cnn_train_step(self.net, s.data_ptr(), B, H, W, int(halo), float(lr),
+                                                     ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def close(self):
+        if getattr(self, "net", None):
+            lib().zk_cnn_destroy(self.net)
+            self.net = None
 
     def __del__(self):
         try:
