@@ -193,6 +193,59 @@ int zk_cnn_train_step(zk_cnn *net, const float *samples, int B, int H, int W, in
                       double *loss_host);
 const char *zk_cnn_last_error(const zk_cnn *net);
 
+/* ---------------------------------------------------------------------------
+ * Learned-closure stepper.
+ *
+ * Steps (eta, psi) with classical RK4 on the grid, where every stage uses
+ *   G = P_B( G^[low] psi + r ),  r = out_scale * s * net(x),
+ *   x = ( k0 eta / eta_scale,  k0 psi / s,  G^[low] psi / s ),  s = rms(G^[low] psi),
+ * in place of G^[M] in the Zakharov RHS (Sec. 3.1 eq:zakharov_kin, Sec. 3.2
+ * eq:dyn_truncated with eq:W), P_B the projection onto the band (Nyquist
+ * modes removed), then the state filter A(k) (Sec. 3.4).  The residual is
+ * linear in psi for fixed eta, as the DtN operator is; the psi-scale s makes
+ * the network see that exactly.  The full-order context is the closure's
+ * fallback and the judge of its error: an audit at the first step and every
+ * audit_every steps computes e = ||G_closure - G^[full] psi||_2 /
+ * ||G^[full] psi||_2 on the current state; while e > tol the next
+ * audit_every steps are taken by the full-order context (zk_step), else by
+ * the closure.  low, full and net must be bound to one stream and keep their
+ * binding while the closure is used; full may be NULL when no audit is asked
+ * for (audit_every = 0).  The grid must have nx % 32 == 0 and nx * ny <= the
+ * network's max_pixels.  Workspace: caller-owned, as for zk_ctx.
+ * ------------------------------------------------------------------------- */
+typedef struct zk_closure zk_closure;
+
+/* NULL if an argument is invalid (contexts of different grids, full order not
+ * above low order, network too small, non-positive scales).  Host-only. */
+zk_closure *zk_closure_create(zk_ctx *low, zk_ctx *full, zk_cnn *net, double k0, double eta_scale,
+                              double out_scale);
+void zk_closure_destroy(zk_closure *clo);
+size_t zk_closure_workspace_bytes(const zk_closure *clo);
+/* Bind a workspace; the stream is the one the contexts and the network share. */
+int zk_closure_bind(zk_closure *clo, void *workspace, size_t bytes);
+/* G = P_B(G^[low] psi + r) on the grid (the closure's DtN). */
+int zk_closure_dtn(zk_closure *clo, const double *eta, const double *psi, double *G);
+/* One training sample for the network from a state: samples (device float
+ * [4][ny][nx]) = the three input planes x above and the target
+ * (G^[full] psi - G^[low] psi) / (out_scale * s).  Needs the full context. */
+int zk_closure_features(zk_closure *clo, const double *eta, const double *psi, float *samples);
+/* Periodic crops of a [4][ny][nx] sample: dst[k] = planes at rows
+ * offsets[2k] + (0..h-1) and columns offsets[2k+1] + (0..w-1), indices taken
+ * modulo the grid; dst is device float [ncrop][4][h][w].  ncrop <= 4096;
+ * offsets (host) in [0, ny) x [0, nx).  Synchronises. */
+int zk_closure_crops(zk_closure *clo, const float *samples, const int *offsets_host, int ncrop, int h, int w,
+                     float *dst);
+/* Advance (eta, psi) in place by nsteps RK4 steps of size dt with audits and
+ * fallback as described above (audit_every = 0: closure only, no audit).
+ * Audits synchronise the stream. */
+int zk_closure_step(zk_closure *clo, double *eta, double *psi, double dt, int nsteps, int audit_every,
+                    double tol);
+/* Counters since creation: steps taken by the closure and by the fallback,
+ * audits, the last and the largest audited error.  Any output may be NULL. */
+int zk_closure_stats(const zk_closure *clo, long long *closure_steps, long long *fallback_steps,
+                     long long *audits, double *last_err, double *max_err);
+const char *zk_closure_last_error(const zk_closure *clo);
+
 #ifdef __cplusplus
 }
 #endif

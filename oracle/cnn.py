@@ -223,3 +223,34 @@ def closure_residual(cnn, eta, psi, g2psi, k0, out_scale, eta_scale=0.1):
     x, s = closure_features(eta, psi, g2psi, k0, eta_scale)
     y, _ = cnn.forward(x[None])
     return out_scale * s * y[0, 0]
+
+
+def closure_rhs_spec(model, net, eta_h, psi_h, k0, out_scale, eta_scale=0.1):
+    """Zakharov RHS with the learned closure: the order-M DtN of `model` plus
+    the network's residual, projected onto the band, in place of G^[M]:
+        G = P_B(G^[M] psi + r),  d_t eta = G,  d_t psi = -g eta + N(eta, psi, G)
+    (eq:zakharov_kin, eq:dyn_truncated with eq:W)."""
+    g = model.gr
+    eta, psi = g.phys(eta_h), g.phys(psi_h)
+    g2 = g.phys(model.dtn_spec(eta_h, psi_h))
+    r = closure_residual(net, eta, psi, g2, k0, out_scale, eta_scale)
+    G_h = g.spec(g2 + r)
+    return G_h, -g.g * eta_h + model.bernoulli_spec(eta_h, psi_h, G_h)
+
+
+def closure_step(model, net, eta, psi, dt, nsteps, k0, out_scale, eta_scale=0.1):
+    """Classical RK4 with the closure RHS, then the state filter A(k) after
+    every full step (as HOSModel.step)."""
+    g = model.gr
+    eh, ph = g.spec(eta), g.spec(psi)
+    f = lambda a, b: closure_rhs_spec(model, net, a, b, k0, out_scale, eta_scale)
+    for _ in range(int(nsteps)):
+        k1 = f(eh, ph)
+        k2 = f(eh + 0.5 * dt * k1[0], ph + 0.5 * dt * k1[1])
+        k3 = f(eh + 0.5 * dt * k2[0], ph + 0.5 * dt * k2[1])
+        k4 = f(eh + dt * k3[0], ph + dt * k3[1])
+        eh = eh + dt / 6.0 * (k1[0] + 2 * k2[0] + 2 * k3[0] + k4[0])
+        ph = ph + dt / 6.0 * (k1[1] + 2 * k2[1] + 2 * k3[1] + k4[1])
+        if model.filt:
+            eh, ph = eh * g.filt, ph * g.filt
+    return g.phys(eh), g.phys(ph)

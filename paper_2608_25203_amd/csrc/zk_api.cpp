@@ -12,53 +12,9 @@
 #include "zk.h"
 #include "zk_kernels.hpp"
 #include "zk_plan.hpp"
+#include "zk_ctx_internal.hpp"
 
 using namespace zk;
-
-struct zk_ctx {
-  PlanParams pp{};
-  int precision = 64;
-  int check = 1;
-  std::string err;
-
-  Plan plan;
-  double plan_dt = NAN;
-  bool have_plan = false;
-  bool dirty = true;  // schedules must be (re)uploaded
-
-  // binding
-  char *ws = nullptr;
-  size_t ws_bytes = 0;
-  hipStream_t stream = nullptr;
-  int device = 0;
-  bool bound = false;
-
-  // workspace layout (byte offsets)
-  size_t off_tw[4] = {0, 0, 0, 0};  // row pad, row base, col pad, col base
-  size_t off_ops = 0, off_progs = 0, off_terms = 0, off_outs = 0, off_tasks = 0;
-  size_t off_red = 0, off_cmax = 0, off_sym = 0, off_fx = 0, off_fy = 0, off_base = 0, off_mix = 0, total = 0;
-  long long base_stride = 0, mix_stride = 0;
-  size_t sched_cap[5] = {0, 0, 0, 0, 0};  // capacities (elements) reserved for the schedules
-
-  // optional per-kernel timing (ZK_OPT_PROFILE)
-  struct Rec {
-    int kind;
-    double bytes, flops;
-    hipEvent_t a, b;
-  };
-  bool prof = false;
-  std::vector<Rec> pending;
-  std::vector<hipEvent_t> pool;
-  double st_ms[5] = {0, 0, 0, 0, 0}, st_bytes[5] = {0, 0, 0, 0, 0}, st_flops[5] = {0, 0, 0, 0, 0};
-  long long st_n[5] = {0, 0, 0, 0, 0};
-  ~zk_ctx() {
-    for (auto &r : pending) {
-      hipEventDestroy(r.a);
-      hipEventDestroy(r.b);
-    }
-    for (auto e : pool) hipEventDestroy(e);
-  }
-};
 
 namespace {
 
@@ -244,11 +200,6 @@ int upload(zk_ctx *c, double dt) {
   return ZK_OK;
 }
 
-struct Phys {
-  const double *in0 = nullptr, *in1 = nullptr;
-  double *out0 = nullptr, *out1 = nullptr;
-};
-
 template <typename real>
 int run_seq_t(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
   const int nx = c->pp.nx, ny = c->pp.ny;
@@ -280,6 +231,7 @@ int run_seq_t(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
       a.nx = nx;
       a.pin0 = ph.in0;
       a.pin1 = ph.in1;
+      a.pin2 = ph.in2;
       a.pout0 = ph.out0;
       a.pout1 = ph.out1;
       a.tw = twp(pad ? 0 : 1);
@@ -351,6 +303,18 @@ int check_call(zk_ctx *c) {
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 }  // namespace
+
+namespace zk {
+
+int ctx_prepare(zk_ctx *c) {
+  int rc = check_call(c);
+  if (rc) return rc;
+  return upload(c, c->have_plan ? c->plan_dt : NAN);
+}
+
+int ctx_run(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) { return run_seq(c, seq, ph); }
+
+}  // namespace zk
 
 extern "C" {
 

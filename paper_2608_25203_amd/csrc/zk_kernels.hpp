@@ -33,8 +33,8 @@ struct RowArgs {
   long long mix_stride;  // elements between mixed fields
   int rows;              // rows of the mixed fields of this pass
   int nx;                // base-grid row length (physical fields)
-  const double *pin0, *pin1;
-  double *pout0, *pout1;
+  const double *pin0, *pin1, *pin2;  // OP_LDP slots 0..2
+  double *pout0, *pout1;             // OP_STP slots 0..1
   const cpx<real> *tw;    // exp(-2 pi i j / N), N = row FFT length
   double kx_scale;        // 2 pi / Lx
   const float *colmax;    // [mixed field][nx/2]: per-column max |value| written by the lifts
@@ -303,8 +303,8 @@ __global__ __launch_bounds__(256) void row_kernel(RowArgs<real> a) {
       }
       case OP_LDP: {
         if constexpr (S::PADDED) break;  // caller fields have base-length rows only
-        const double *pa = op.fa == 0 ? a.pin0 : a.pin1;
-        const double *pb = op.fb == 0 ? a.pin0 : a.pin1;
+        const double *pa = op.fa == 0 ? a.pin0 : (op.fa == 1 ? a.pin1 : a.pin2);
+        const double *pb = op.fb == 0 ? a.pin0 : (op.fb == 1 ? a.pin1 : a.pin2);
         const long long off = (long long)row * a.nx;
 #pragma unroll
         for (int e = 0; e < E; ++e) {

@@ -329,6 +329,11 @@ Plan build_plan(const PlanParams &pp, double dt) {
   B.ld2(Fac{mbA, 0}, -1, 0);
   B.op(OP_STP, RS_U, 0, 0, 0, 0, -1, 0, 0.0);
 
+  // entry of a third caller field (slot 2) on the base grid
+  const int entry_g_prog = B.prog_begin();
+  B.op(OP_LDP, 0, 0, 0, 2, 0, -1, 0, 0.0);
+  B.op(OP_ST2, RS_U, RS_V, 0, mbA, 0, -1, 0, 0.0);
+
   auto row_launch = [&](int kind, const std::vector<int> &progs) {
     // programs of one launch must be contiguous
     for (size_t i = 1; i < progs.size(); ++i)
@@ -502,6 +507,46 @@ Plan build_plan(const PlanParams &pp, double dt) {
     P.chk_p[par] = bUP[par];
   }
 
+  // ---- stepping with an external DtN --------------------------------------------
+  // rhs_g: the RHS of (eta, psi) with G supplied on the grid; G is projected
+  // onto the band by its entry transform, eta_t = P_B G.
+  {
+    auto &seq = P.rhs_g;
+    entry(seq);
+    seq.push_back(row_launch(L_ROW_BASE, {entry_g_prog}));
+    TaskSpec tg;
+    tg.fwd = mbA;
+    tg.outs.push_back(B.store(bG, {{-1, 0, 1.0}}));
+    seq.push_back(B.col_launch(L_COL_BASE, {tg}));
+    std::vector<TaskSpec> ts;
+    auto one = [&](OutSpec o) {
+      TaskSpec t;
+      t.outs.push_back(std::move(o));
+      ts.push_back(std::move(t));
+    };
+    one(B.lift(mE, {{bUE[0], 0, kref}}));
+    one(B.lift(mEy, {{bUE[0], SYM_IKY, 1.0}}));
+    one(B.lift(mP, {{bUP[0], 0, 1.0}}));
+    one(B.lift(mPy, {{bUP[0], SYM_IKY, 1.0}}));
+    one(B.lift(mG, {{bG, 0, 1.0}}));
+    seq.push_back(B.col_launch(L_COL_PAD, ts));
+    seq.push_back(row_launch(L_ROW_PAD, {bern_prog}));
+    TaskSpec t = B.fold_task(mN);
+    t.outs.push_back(B.store(bPT, {{bUE[0], 0, -g}, {-1, 0, 1.0}}));
+    seq.push_back(B.col_launch(L_COL_PAD, {t}));
+    exit_seq(seq, bG, bPT);
+  }
+  // filter: A(k) on (eta, psi) (eq:state_filter), identity when the filter is off
+  {
+    auto &seq = P.filter;
+    entry(seq);
+    std::vector<TaskSpec> ts(2);
+    ts[0].outs.push_back(B.lift(mbA, {{bUE[0], FILT, 1.0}}));
+    ts[1].outs.push_back(B.lift(mbB, {{bUP[0], FILT, 1.0}}));
+    seq.push_back(B.col_launch(L_COL_BASE, ts));
+    seq.push_back(row_launch(L_ROW_BASE, {exit2_prog}));
+  }
+
   // ---- algorithmic bytes and FFT flops per launch ------------------------------
   // Every program or task streams its fields through HBM once: a row program
   // reads each mixed field it loads (kx < nx/2 of one row per team) and writes
@@ -558,7 +603,7 @@ Plan build_plan(const PlanParams &pp, double dt) {
       }
     };
     for (auto *seq : {&P.dtn, &P.rhs, &P.ham, &P.step_entry, &P.step_body[0], &P.step_body[1], &P.step_lift[0],
-                      &P.step_lift[1], &P.step_exit[0], &P.step_exit[1]})
+                      &P.step_lift[1], &P.step_exit[0], &P.step_exit[1], &P.rhs_g, &P.filter})
       annotate(*seq);
   }
   return P;
@@ -582,7 +627,7 @@ std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
           if ((o.a == RS_U) != (o.b == RS_V) || o.a == RS_V || o.b == RS_U) return bad("ST2 pairs u with a set");
           break;
         case OP_LDP:
-          if (o.fa < 0 || o.fa > 1 || o.fb > 1) return bad("LDP slot");
+          if (o.fa < 0 || o.fa > 2 || o.fb > 2) return bad("LDP slot");
           break;
         case OP_STP:
           if (o.fa < 0 || o.fa > 1 || o.a > RS_O2) return bad("STP");
@@ -637,7 +682,7 @@ std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
     return "";
   };
   for (auto *seq : {&p.dtn, &p.rhs, &p.ham, &p.step_entry, &p.step_body[0], &p.step_body[1], &p.step_lift[0],
-                    &p.step_lift[1], &p.step_exit[0], &p.step_exit[1]}) {
+                    &p.step_lift[1], &p.step_exit[0], &p.step_exit[1], &p.rhs_g, &p.filter}) {
     std::string e = chk(*seq);
     if (!e.empty()) return e;
   }

@@ -56,6 +56,9 @@ struct Plan {
   std::vector<Launch> step_lift[2];   // lifts of U[p] for the next step's stage 1
   std::vector<Launch> step_exit[2];   // U[p] -> physical
   int chk_e[2], chk_p[2];             // base ids of U[p] (finite check)
+  // Pieces for stepping with an externally supplied DtN (learned closure):
+  std::vector<Launch> rhs_g;   // eta, psi, G (LDP slots 0, 1, 2) -> eta_t = P_B G, psi_t
+  std::vector<Launch> filter;  // eta, psi -> A eta, A psi (the state filter alone)
 };
 
 // Build the full plan (host only; deterministic).  Throws std::runtime_error

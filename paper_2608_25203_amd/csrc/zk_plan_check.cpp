@@ -74,7 +74,9 @@ int main(int argc, char **argv) {
   dump_seq("step_lift0", p.step_lift[0], false);
   dump_seq("step_lift1", p.step_lift[1], false);
   dump_seq("step_exit0", p.step_exit[0], false);
-  dump_seq("step_exit1", p.step_exit[1], true);
+  dump_seq("step_exit1", p.step_exit[1], false);
+  dump_seq("rhs_g", p.rhs_g, false);
+  dump_seq("filter", p.filter, true);
   std::printf("}\n");
   return 0;
 }

@@ -20,7 +20,10 @@ KERNEL_NAMES = {0: "row_pad", 1: "row_base", 2: "col_pad", 3: "col_base", 4: "re
 EXPORTS = ("zk_create", "zk_destroy", "zk_set_option", "zk_workspace_bytes", "zk_bind", "zk_dtn",
            "zk_rhs", "zk_step", "zk_hamiltonian", "zk_kernel_stats", "zk_last_error",
            "zk_cnn_create", "zk_cnn_destroy", "zk_cnn_workspace_bytes", "zk_cnn_bind", "zk_cnn_set_params",
-           "zk_cnn_get_params", "zk_cnn_forward", "zk_cnn_gradient", "zk_cnn_train_step", "zk_cnn_last_error")
+           "zk_cnn_get_params", "zk_cnn_forward", "zk_cnn_gradient", "zk_cnn_train_step", "zk_cnn_last_error",
+           "zk_closure_create", "zk_closure_destroy", "zk_closure_workspace_bytes", "zk_closure_bind",
+           "zk_closure_dtn", "zk_closure_features", "zk_closure_crops", "zk_closure_step", "zk_closure_stats",
+           "zk_closure_last_error")
 ZK_CNN_NPARAMS = 19681
 
 _lib = None
@@ -82,6 +85,24 @@ def lib():
         getattr(L, f).restype = i
     L.zk_cnn_last_error.argtypes = [vp]
     L.zk_cnn_last_error.restype = ctypes.c_char_p
+    pll, pi = ctypes.POINTER(ll), ctypes.POINTER(i)
+    L.zk_closure_create.argtypes = [vp, vp, vp, d, d, d]
+    L.zk_closure_create.restype = vp
+    L.zk_closure_destroy.argtypes = [vp]
+    L.zk_closure_destroy.restype = None
+    L.zk_closure_workspace_bytes.argtypes = [vp]
+    L.zk_closure_workspace_bytes.restype = sz
+    L.zk_closure_bind.argtypes = [vp, vp, sz]
+    L.zk_closure_dtn.argtypes = [vp, vp, vp, vp]
+    L.zk_closure_features.argtypes = [vp, vp, vp, vp]
+    L.zk_closure_crops.argtypes = [vp, vp, pi, i, i, i, vp]
+    L.zk_closure_step.argtypes = [vp, vp, vp, d, i, i, d]
+    L.zk_closure_stats.argtypes = [vp, pll, pll, pll, pd, pd]
+    for f in ("zk_closure_bind", "zk_closure_dtn", "zk_closure_features", "zk_closure_crops", "zk_closure_step",
+              "zk_closure_stats"):
+        getattr(L, f).restype = i
+    L.zk_closure_last_error.argtypes = [vp]
+    L.zk_closure_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -308,6 +329,80 @@ class Net:
         if getattr(self, "net", None):
             lib().zk_cnn_destroy(self.net)
             self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- learned-closure stepper ----------------------------------------------------------
+class Closure:
+    """zk_closure_* over a low-order Solver, an optional full-order Solver
+    (fallback and judge) and a Net, all on one device stream."""
+
+    def __init__(self, low, full, net, k0, eta_scale, out_scale):
+        import torch
+
+        self.torch = torch
+        self.low, self.full, self.net_obj = low, full, net
+        self.c = lib().zk_closure_create(low.ctx, full.ctx if full is not None else None, net.net, float(k0),
+                                         float(eta_scale), float(out_scale))
+        if not self.c:
+            raise ZKError(ZK_EINVAL, "zk_closure_create rejected the arguments")
+        nbytes = int(lib().zk_closure_workspace_bytes(self.c))
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=low.device)
+        off = (-self.ws.data_ptr()) % 256
+        self._check(lib().zk_closure_bind(self.c, self.ws.data_ptr() + off, nbytes))
+
+    def _check(self, rc):
+        if rc != ZK_OK:
+            raise ZKError(rc, lib().zk_closure_last_error(self.c).decode())
+
+    def dtn(self, eta, psi):
+        eta, psi = self.low._field(eta), self.low._field(psi)
+        out = self.torch.empty_like(eta)
+        self._check(lib().zk_closure_dtn(self.c, eta.data_ptr(), psi.data_ptr(), out.data_ptr()))
+        return out
+
+    def features(self, eta, psi):
+        eta, psi = self.low._field(eta), self.low._field(psi)
+        out = self.torch.empty((4, self.low.ny, self.low.nx), dtype=self.torch.float32, device=self.low.device)
+        self._check(lib().zk_closure_features(self.c, eta.data_ptr(), psi.data_ptr(), out.data_ptr()))
+        return out
+
+    def crops(self, samples, offsets, h, w):
+        """samples: float32 [4, ny, nx] device tensor; offsets: int array [n, 2] (row, col)."""
+        import numpy as np
+
+        offs = np.ascontiguousarray(offsets, dtype=np.int32).reshape(-1, 2)
+        out = self.torch.empty((offs.shape[0], 4, h, w), dtype=self.torch.float32, device=self.low.device)
+        self._check(lib().zk_closure_crops(self.c, samples.data_ptr(),
+                                           offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), offs.shape[0],
+                                           int(h), int(w), out.data_ptr()))
+        return out
+
+    def step(self, eta, psi, dt, nsteps, audit_every=0, tol=0.0):
+        """In place on contiguous float64 device tensors."""
+        if eta.dtype != self.torch.float64 or not eta.is_contiguous() or not psi.is_contiguous():
+            raise ValueError("step works in place on contiguous float64 device tensors")
+        self._check(lib().zk_closure_step(self.c, eta.data_ptr(), psi.data_ptr(), float(dt), int(nsteps),
+                                          int(audit_every), float(tol)))
+        return eta, psi
+
+    def stats(self):
+        a, b, n = ctypes.c_longlong(0), ctypes.c_longlong(0), ctypes.c_longlong(0)
+        e1, e2 = ctypes.c_double(0), ctypes.c_double(0)
+        self._check(lib().zk_closure_stats(self.c, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n),
+                                           ctypes.byref(e1), ctypes.byref(e2)))
+        return {"closure_steps": a.value, "fallback_steps": b.value, "audits": n.value, "last_err": e1.value,
+                "max_err": e2.value}
+
+    def close(self):
+        if getattr(self, "c", None):
+            lib().zk_closure_destroy(self.c)
+            self.c = None
 
     def __del__(self):
         try:

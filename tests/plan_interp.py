@@ -124,8 +124,9 @@ class Interp:
                     z = np.fft.ifft(Z, axis=1) * N
                     R[0], R[1] = z.real / sa, z.imag / sb
                 elif code == OP_LDP:
-                    R[0] = np.array(phys[fa], dtype=float)
-                    R[1] = np.array(phys[fb], dtype=float) if fb >= 0 else np.zeros((rows, N))
+                    slot = lambda i: 4 if i == 2 else i  # phys: in0, in1, out0, out1, in2
+                    R[0] = np.array(phys[slot(fa)], dtype=float)
+                    R[1] = np.array(phys[slot(fb)], dtype=float) if fb >= 0 else np.zeros((rows, N))
                 elif code == OP_MOV:
                     R[a] = R[b].copy()
                 elif code == OP_MAC:
@@ -226,6 +227,18 @@ class Interp:
         N = self.nx * self.ny
         dA = self.Lx * self.Ly / N
         return 0.5 * dA * s1 / N + 0.5 * self.g * dA * s2 / N
+
+    def rhs_g(self, eta, psi, G):
+        P = self._plan(self.dt if self.dt is not None else 1.0)
+        phys = [eta, psi, np.zeros_like(eta), np.zeros_like(eta), G]
+        self.run(P["rhs_g"], phys)
+        return phys[2], phys[3]
+
+    def filter(self, eta, psi):
+        P = self._plan(self.dt if self.dt is not None else 1.0)
+        phys = [eta, psi, np.zeros_like(eta), np.zeros_like(eta)]
+        self.run(P["filter"], phys)
+        return phys[2], phys[3]
 
     def step(self, eta, psi, dt, nsteps):
         P = self._plan(dt)

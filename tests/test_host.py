@@ -67,6 +67,26 @@ def test_schedule_algebra_matches_oracle_broadband(M, eps, taper, filt):
     assert rel(s, s0) < 1e-13 and rel(t, t0) < 1e-13
 
 
+@pytest.mark.parametrize("M", [2, 4])
+def test_closure_pieces_match_oracle(M):
+    """rhs_g (the RHS with G supplied on the grid, projected onto the band)
+    and the stand-alone state filter, executed literally, against the
+    oracle's Bernoulli term and filter."""
+    nx, ny = 32, 16
+    eta, psi = random_band_fields(nx, ny, 5, 7, amplitude=0.02)
+    G = np.random.default_rng(6).standard_normal((ny, nx))  # any field, Nyquist content included
+    I = Interp(nx, ny, 3.0, 2.0, 1.5, 9.81, M)
+    m = HOSModel(Grid(nx, ny, 3.0, 2.0, 1.5), M)
+    g = m.gr
+    a, b = I.rhs_g(eta, psi, G)
+    Gh = g.spec(G)
+    eh, ph = g.spec(eta), g.spec(psi)
+    assert rel(a, g.phys(Gh)) < 1e-13
+    assert rel(b, g.phys(-9.81 * eh + m.bernoulli_spec(eh, ph, Gh))) < 1e-13
+    fa, fb = I.filter(eta, psi)
+    assert rel(fa, g.phys(eh * g.filt)) < 1e-13 and rel(fb, g.phys(ph * g.filt)) < 1e-13
+
+
 # ---------------------------------------------------------------- the library
 LIB = os.path.join(ROOT, "paper_2608_25203_amd", "libzk.so")
 
