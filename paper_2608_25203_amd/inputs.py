@@ -114,10 +114,11 @@ WORKLOADS = {
                      dt=0.01, steps=100, kp=4.0, steepness=0.05, seed=0),
     "c2_512_m4": dict(nx=512, ny=512, Lx=200.0, Ly=200.0, depth=20.0, g=9.81, M=4,
                       dt=0.05, steps=1000, kp=2 * np.pi / 12.5, steepness=0.1, seed=1),
+    # peak at kNyq / 16 (32 grid points per peak wavelength), dt = T_p / 50
     "c3_2048_m5": dict(nx=2048, ny=2048, Lx=2 * np.pi, Ly=2 * np.pi, depth=math.inf, g=9.81, M=5,
-                       dt=0.007, steps=500, kp=32.0, steepness=0.15, seed=2),
+                       dt=0.005, steps=500, kp=64.0, steepness=0.15, seed=2),
     "c5_1024_m6": dict(nx=1024, ny=1024, Lx=2 * np.pi, Ly=2 * np.pi, depth=math.inf, g=9.81, M=6,
-                       dt=0.01, steps=1000, kp=16.0, steepness=0.1, seed=42),
+                       dt=0.007, steps=1000, kp=32.0, steepness=0.1, seed=42),
 }
 
 

@@ -1,0 +1,45 @@
+"""What the trained closure gains over order 2 alone, judged by the oracle
+alone (no HIP code): the network's parameters (trained on the GPU, stored
+in the package) are evaluated by the numpy network of oracle/cnn.py on a
+small periodic domain with the training grid spacing (2 pi / 1024) and the
+same physical peak wavenumber, and its DtN is compared with the oracle's
+order-6 DtN.  Sea states here are unseen seeds."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cnn as C
+from oracle.hos import Grid, HOSModel
+from paper_2608_25203_amd.inputs import jonswap_state
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WDIR = os.path.join(ROOT, "paper_2608_25203_amd", "weights")
+
+
+def load():
+    meta = json.load(open(os.path.join(WDIR, "closure_c5.json")))
+    p = np.load(os.path.join(WDIR, "closure_c5.npy"), allow_pickle=False)
+    return meta, C.CNN(C.unflatten(p.astype(np.float64)))
+
+
+@pytest.mark.parametrize("steep,seed", [(0.1, 71), (0.15, 72)])
+def test_trained_closure_reduces_order2_dtn_error(steep, seed):
+    meta, net = load()
+    n = 128
+    L = n * 2 * math.pi / 1024
+    kp = meta["geometry"]["kp"]
+    eta, psi = jonswap_state(n, n, L, L, None, 9.81, kp, steep, seed)
+    grid = Grid(n, n, L, L, None)
+    m6 = HOSModel(grid, 6)
+    eta, psi = m6.step(eta, psi, meta["geometry"]["dt"], 20)
+    g6 = m6.dtn(eta, psi)
+    g2 = HOSModel(grid, 2).dtn(eta, psi)
+    r = C.closure_residual(net, eta, psi, g2, meta["k0"], meta["out_scale"], meta["eta_scale"])
+    gc = grid.phys(grid.spec(g2 + r))
+    e2 = np.linalg.norm(g2 - g6) / np.linalg.norm(g6)
+    ec = np.linalg.norm(gc - g6) / np.linalg.norm(g6)
+    print(f"  steepness {steep}: order 2 {e2:.3e}, closure {ec:.3e}, gain {e2 / ec:.2f}")
+    assert ec < e2 / 3

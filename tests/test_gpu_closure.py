@@ -138,3 +138,47 @@ def test_audit_fallback(torch):
     clo.step(e2, p2, 0.01, 3, audit_every=2, tol=math.inf)
     st = clo.stats()
     assert st["closure_steps"] == 3 and st["audits"] == 4
+
+
+@pytest.mark.timeout(300)
+def test_trained_closure_gain_1024(torch):
+    """The stored network at its training geometry (1024 x 1024, 2 pi, deep,
+    k_p = 32), unseen seed, steepness 0.1: its DtN error against order 6 is
+    several times below order 2's, and 100 closure RK4 steps track the
+    order-6 run more closely than 100 order-2 steps."""
+    import json
+    import os
+
+    from paper_2608_25203_amd.zk import Closure, Net, Solver
+
+    wdir = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2608_25203_amd", "weights")
+    meta = json.load(open(os.path.join(wdir, "closure_c5.json")))
+    p32 = np.load(os.path.join(wdir, "closure_c5.npy"), allow_pickle=False)
+    G = meta["geometry"]
+    n, Ld, dt = G["nx"], G["L"], G["dt"]
+    low = Solver(n, n, Ld, Ld, math.inf, 9.81, 2)
+    full = Solver(n, n, Ld, Ld, math.inf, 9.81, 6)
+    net = Net(n * n)
+    net.set_params(p32)
+    clo = Closure(low, full, net, meta["k0"], meta["eta_scale"], meta["out_scale"])
+    eta, psi = jonswap_state(n, n, Ld, Ld, None, 9.81, G["kp"], 0.1, 44)
+    e, p = dev(torch, eta), dev(torch, psi)
+    full.step(e, p, dt, 50)
+    g6, g2, gc = full.dtn(e, p), low.dtn(e, p), clo.dtn(e, p)
+    n6 = torch.linalg.vector_norm(g6).item()
+    e2 = torch.linalg.vector_norm(g2 - g6).item() / n6
+    ec = torch.linalg.vector_norm(gc - g6).item() / n6
+    print(f"  DtN: order 2 {e2:.3e}, closure {ec:.3e}, gain {e2 / ec:.2f}", flush=True)
+    assert ec < e2 / 5
+    runs = {}
+    for name, adv in (("m6", lambda a, b: full.step(a, b, dt, 100)), ("m2", lambda a, b: low.step(a, b, dt, 100)),
+                      ("closure", lambda a, b: clo.step(a, b, dt, 100))):
+        a, b = e.clone(), p.clone()
+        adv(a, b)
+        runs[name] = a
+    ref = runs["m6"]
+    nr = torch.linalg.vector_norm(ref).item()
+    d2 = torch.linalg.vector_norm(runs["m2"] - ref).item() / nr
+    dc = torch.linalg.vector_norm(runs["closure"] - ref).item() / nr
+    print(f"  eta after 100 steps vs order 6: order 2 {d2:.3e}, closure {dc:.3e}", flush=True)
+    assert dc < d2 / 2
