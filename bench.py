@@ -148,6 +148,75 @@ def precision_form(segments=(1, 9, 90, 400)):
             "within_1e-4": bool(worst <= 1e-4)}
 
 
+def closure_form(nsteps=1000, audit_every=10, tol=1e-4):
+    """Learned closure on its training geometry (1024 x 1024, 2 pi, deep,
+    k_p = 32, dt = 0.007, JONSWAP steepness 0.1, seed 42) against plain
+    order 6 in FP64 over nsteps RK4 steps: grid-point-steps/s and the max
+    relative eta error of order 2 alone, of order 2 + network (low order in
+    FP64 and in FP32), and of the audited closure (audit every `audit_every`
+    steps, fallback to order 6 while the DtN error exceeds `tol`)."""
+    import json as _json
+
+    import numpy as np
+    import torch
+
+    from paper_2608_25203_amd.inputs import WORKLOADS, jonswap_state
+    from paper_2608_25203_amd.zk import Closure, Net, Solver
+
+    wdir = os.path.join(HERE, "paper_2608_25203_amd", "weights")
+    meta = _json.load(open(os.path.join(wdir, "closure_c5.json")))
+    params = np.load(os.path.join(wdir, "closure_c5.npy"), allow_pickle=False)
+    w = WORKLOADS["c5_1024_m6"]
+    n, L, dt = w["nx"], w["Lx"], w["dt"]
+    eta, psi = jonswap_state(n, n, L, L, w["depth"], w["g"], w["kp"], w["steepness"], w["seed"])
+    dev = torch.device("cuda:0")
+    full = Solver(n, n, L, L, w["depth"], w["g"], 6, check=False, device=dev)
+    low64 = Solver(n, n, L, L, w["depth"], w["g"], 2, check=False, device=dev)
+    low32 = Solver(n, n, L, L, w["depth"], w["g"], 2, precision=32, check=False, device=dev)
+    net = Net(n * n, device=dev)
+    net.set_params(params)
+    clo64 = Closure(low64, full, net, meta["k0"], meta["eta_scale"], meta["out_scale"])
+    clo32 = Closure(low32, full, net, meta["k0"], meta["eta_scale"], meta["out_scale"])
+
+    def run(advance, warm=True):
+        if warm:
+            e, p = (torch.tensor(a, dtype=torch.float64, device=dev) for a in (eta, psi))
+            advance(e, p, 2)
+        e, p = (torch.tensor(a, dtype=torch.float64, device=dev) for a in (eta, psi))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        advance(e, p, nsteps)
+        torch.cuda.synchronize()
+        return e, time.perf_counter() - t0
+
+    e6, t6 = run(lambda e, p, k: full.step(e, p, dt, k))
+    out = {"workload": f"c5_1024_m6: {n}x{n}, 2pi x 2pi, deep, k_p={w['kp']:g}, RK4 dt={dt}, JONSWAP steepness "
+                       f"{w['steepness']}, seed {w['seed']}, {nsteps} steps; reference: order 6, FP64",
+           "unit": "grid-point-steps/s", "order6_fp64_value": round(n * n * nsteps / t6, 1)}
+    cases = {"order2_fp64": lambda e, p, k: low64.step(e, p, dt, k),
+             "closure_fp64": lambda e, p, k: clo64.step(e, p, dt, k),
+             "closure_fp32": lambda e, p, k: clo32.step(e, p, dt, k),
+             "closure_audited_fp32": lambda e, p, k: clo32.step(e, p, dt, k, audit_every, tol)}
+    for name, adv in cases.items():
+        if name == "closure_audited_fp32":
+            clo32.close()
+            clo32 = Closure(low32, full, net, meta["k0"], meta["eta_scale"], meta["out_scale"])
+            adv = lambda e, p, k: clo32.step(e, p, dt, k, audit_every, tol)  # noqa: E731
+        e, t = run(adv, warm=name != "closure_audited_fp32")
+        out[name] = {"value": round(n * n * nsteps / t, 1), "speedup_vs_order6": round(t6 / t, 3),
+                     "eta_rel_err_vs_order6": rel_max(e, e6)}
+        print(f"# closure form: {name} {t:.2f} s, eta err {out[name]['eta_rel_err_vs_order6']:.3e}",
+              file=sys.stderr, flush=True)
+    st = clo32.stats()
+    out["closure_audited_fp32"].update({"audit_every": audit_every, "tol": tol, "closure_steps": st["closure_steps"],
+                                        "fallback_steps": st["fallback_steps"], "audits": st["audits"],
+                                        "max_audited_dtn_err": st["max_err"]})
+    for o in (clo64, clo32, net, low64, low32, full):
+        o.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def c2_diagnostics(w, H_before, H_after):
     """Hamiltonian drift of the timed run and the linear-limit dispersion error
     (eps = 0, filter off) of single modes on the benchmark grid: measured
@@ -209,7 +278,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the precision-form comparison on the 2048^2 M=5 workload")
+                    help="skip the precision-form (2048^2 M=5) and closure-form (1024^2) comparisons")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -311,6 +380,7 @@ def main():
         out["c2_diagnostics"] = c2_diagnostics(w, H_before, H_after)
     if not args.no_forms:
         out["precision_form"] = precision_form()
+        out["closure_form"] = closure_form()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, eta, psi, args.cpu_steps)
         out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 1)
