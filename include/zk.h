@@ -246,6 +246,62 @@ int zk_closure_stats(const zk_closure *clo, long long *closure_steps, long long 
                      long long *audits, double *last_err, double *max_err);
 const char *zk_closure_last_error(const zk_closure *clo);
 
+/* ---------------------------------------------------------------------------
+ * Batches of independent tiles.
+ *
+ * Many periodic tiles of different sizes, depths and orders M advanced
+ * together by the same RK4 + filter step as zk_step (each tile's result is
+ * that of its own context).  Each tile keeps its own spectra in a slice of
+ * the batch workspace; the tiles' passes are merged into phases, one
+ * batched launch per phase and tile size (blockIdx.y runs over the tiles'
+ * programs or tasks), and one step's phases are replayed as a HIP graph of
+ * kernel nodes.  The team shape of each pass and size (threads per
+ * transform and first-pass radix) is the default one (min(256, n/2)
+ * threads) until zk_batch_autotune times the compiled alternatives on the
+ * batch itself and keeps the fastest.  Tile sizes follow zk_create's rule.
+ * ------------------------------------------------------------------------- */
+typedef struct zk_tile {
+    int nx, ny;           /* grid points (powers of two in [64, 2048])      */
+    double Lx, Ly, depth; /* domain size and still-water depth (<= 0: deep) */
+    int M;                /* HOS order, 1..8                               */
+} zk_tile;
+typedef struct zk_batch zk_batch;
+
+enum {
+    ZK_BATCH_OPT_GRAPH = 1  /* 1: replay each step as a HIP graph (default);
+                               0: launch the phases one by one           */
+};
+
+/* precision: 64 (FP64 transforms) or 32 (FP32 transforms, FP64 series,
+ * state and symbols), as ZK_OPT_PRECISION.  NULL on invalid tiles or
+ * arguments.  Host-only. */
+zk_batch *zk_batch_create(int ntiles, const zk_tile *tiles, double g, int precision);
+void zk_batch_destroy(zk_batch *batch);
+size_t zk_batch_workspace_bytes(const zk_batch *batch);
+/* Bind a caller-owned workspace (256-byte aligned) and a stream; uploads
+ * every tile's tables (synchronises). */
+int zk_batch_bind(zk_batch *batch, void *workspace, size_t bytes, void *stream);
+/* Register the tiles' fields: host arrays of ntiles device pointers to
+ * [ny][nx] doubles, stepped in place; they must stay valid while used. */
+int zk_batch_set_fields(zk_batch *batch, double *const *eta, double *const *psi);
+int zk_batch_set_option(zk_batch *batch, int key, double value);
+/* Advance every tile by nsteps RK4 steps of size dt (each followed by the
+ * state filter).  Asynchronous on the bound stream; the first call for a dt
+ * builds the merged schedule and the graphs (synchronises). */
+int zk_batch_step(zk_batch *batch, double dt, int nsteps);
+/* Time every compiled team shape of every pass and tile size on one step of
+ * this batch (reps timed repetitions each; the tiles' internal spectra are
+ * overwritten, the registered fields are not) and keep the fastest.
+ * Synchronises. */
+int zk_batch_autotune(zk_batch *batch, double dt, int reps);
+/* Entry `index` of the autotuner's choices: pass kind (row 1 / column 0),
+ * padded (1) or base (0) transform, transform length and the team shape
+ * (T threads, first-pass radix E).  ZK_EINVAL past the last entry. */
+int zk_batch_tuning(const zk_batch *batch, int index, int *row, int *pad, int *n_transform, int *T, int *E);
+/* Phases and batched launches of one step (after the schedule is built). */
+int zk_batch_stats(const zk_batch *batch, long long *phases_per_step, long long *launches_per_step);
+const char *zk_batch_last_error(const zk_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

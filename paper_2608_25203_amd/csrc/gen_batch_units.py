@@ -1,0 +1,19 @@
+"""Writes the batched-kernel instantiation units zk_batch_{row,col}_{f64,f32}.hip
+(one function per unit mapping a team shape (T, E) to its kernel).  Run from
+any directory; the units are committed, this script regenerates them."""
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SHAPES = [(T, E) for T in (32, 64, 128, 256) for E in (2, 3, 4, 6, 8, 12)]
+
+for kind in ("row", "col"):
+    for real, tag in (("double", "f64"), ("float", "f32")):
+        lines = [f"// zk_batch_{kind}_{tag}.hip -- batched {kind}-pass kernel instances ({real} transforms);",
+                 "// written by gen_batch_units.py.",
+                 '#include "zk_kernels.hpp"', "", "namespace zk {", "", "template <>",
+                 f"const void *batch_{kind}_kernel<{real}>(int T, int E) {{"]
+        for T, E in SHAPES:
+            lines.append(f"  if (T == {T} && E == {E}) return reinterpret_cast<const void *>(&{kind}_kernel_batch<{real}, {T}, {E}>);")
+        lines += ["  return nullptr;", "}", "", "}  // namespace zk", ""]
+        with open(os.path.join(HERE, f"zk_batch_{kind}_{tag}.hip"), "w") as f:
+            f.write("\n".join(lines))

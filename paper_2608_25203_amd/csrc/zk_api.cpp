@@ -203,14 +203,8 @@ int upload(zk_ctx *c, double dt) {
 template <typename real>
 int run_seq_t(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
   const int nx = c->pp.nx, ny = c->pp.ny;
-  // team sizes: T = min(256, n/2) threads; first-pass radix E = N / T
-  const int Tx = std::min(256, nx / 2), Ty = std::min(256, ny / 2);
-  const int Ex_pad = 3 * nx / 2 / Tx, Ex_base = nx / Tx, Ey_pad = 3 * ny / 2 / Ty, Ey_base = ny / Ty;
   char *ws = c->ws;
-  auto twp = [&](int i) { return reinterpret_cast<const cpx<real> *>(ws + c->off_tw[i]); };
-  cpx<real> *mix = reinterpret_cast<cpx<real> *>(ws + c->off_mix);
   cpx<double> *base = reinterpret_cast<cpx<double> *>(ws + c->off_base);
-  const double kc = 2.0 / 3.0 * std::min(M_PI * nx / c->pp.Lx, M_PI * ny / c->pp.Ly);
   for (const Launch &l : seq) {
     hipError_t e = hipSuccess;
     zk_ctx::Rec rec{l.kind, l.bytes, l.flops, nullptr, nullptr};
@@ -221,53 +215,14 @@ int run_seq_t(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
     }
     if (l.kind == L_ROW_PAD || l.kind == L_ROW_BASE) {
       const bool pad = l.kind == L_ROW_PAD;
-      RowArgs<real> a{};
-      a.ops = reinterpret_cast<const RowOp *>(ws + c->off_ops);
-      a.progs = reinterpret_cast<const RowProg *>(ws + c->off_progs);
-      a.prog0 = l.first;
-      a.mix = mix;
-      a.mix_stride = c->mix_stride;
-      a.rows = pad ? 3 * ny / 2 : ny;
-      a.nx = nx;
-      a.pin0 = ph.in0;
-      a.pin1 = ph.in1;
-      a.pin2 = ph.in2;
-      a.pout0 = ph.out0;
-      a.pout1 = ph.out1;
-      a.tw = twp(pad ? 0 : 1);
-      a.kx_scale = 2.0 * M_PI / c->pp.Lx;
-      a.colmax = reinterpret_cast<const float *>(ws + c->off_cmax);
-      const int rpb = 256 / Tx;
-      if (a.rows % rpb) return fail(c, ZK_EINVAL, "row blocking");
-      e = launch_row<real>(a, Tx, pad ? Ex_pad : Ex_base, a.rows / rpb, l.count, c->stream);
+      const RowArgs<real> a = ctx_row_args<real>(c, pad, ph, l.first);
+      const TeamShape sh = ctx_team(c, true, pad);
+      e = launch_row<real>(a, sh.T, sh.E, sh.blocks, l.count, c->stream);
     } else if (l.kind == L_COL_PAD || l.kind == L_COL_BASE) {
       const bool pad = l.kind == L_COL_PAD;
-      ColArgs<real> a{};
-      a.tasks = reinterpret_cast<const ColTask *>(ws + c->off_tasks);
-      a.task0 = l.first;
-      a.outs = reinterpret_cast<const ColOut *>(ws + c->off_outs);
-      a.terms = reinterpret_cast<const ColTerm *>(ws + c->off_terms);
-      a.mix = mix;
-      a.mix_stride = c->mix_stride;
-      a.rows = pad ? 3 * ny / 2 : ny;
-      a.base = base;
-      a.base_stride = c->base_stride;
-      a.ny = ny;
-      a.nx = nx;
-      a.tw = twp(pad ? 2 : 3);
-      a.kx_scale = 2.0 * M_PI / c->pp.Lx;
-      a.ky_scale = 2.0 * M_PI / c->pp.Ly;
-      a.depth = c->pp.depth;
-      a.inv_kc = 1.0 / kc;
-      a.taper_on = c->pp.taper ? 1 : 0;
-      a.colmax = reinterpret_cast<float *>(ws + c->off_cmax);
-      a.sym = reinterpret_cast<const SymEl *>(ws + c->off_sym);
-      a.filt_x = reinterpret_cast<const double *>(ws + c->off_fx);
-      a.filt_y = reinterpret_cast<const double *>(ws + c->off_fy);
-      const int cpb = 256 / Ty;
-      const int ncols = nx / 2;
-      if (ncols % cpb) return fail(c, ZK_EINVAL, "column blocking");
-      e = launch_col<real>(a, Ty, pad ? Ey_pad : Ey_base, ncols / cpb, l.count, c->stream);
+      const ColArgs<real> a = ctx_col_args<real>(c, pad, l.first);
+      const TeamShape sh = ctx_team(c, false, pad);
+      e = launch_col<real>(a, sh.T, sh.E, sh.blocks, l.count, c->stream);
     } else if (l.kind == L_PARSEVAL) {
       double *red = reinterpret_cast<double *>(ws + c->off_red);
       e = launch_parseval(base + (long long)l.first * c->base_stride, base + (long long)l.count * c->base_stride,
@@ -305,6 +260,76 @@ bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 }  // namespace
 
 namespace zk {
+
+TeamShape ctx_team(const zk_ctx *c, bool row, bool pad) {
+  // T = min(256, n/2) threads per transform; first-pass radix E = N / T;
+  // a 256-thread block holds 256 / T teams (rows or columns)
+  const int n = row ? c->pp.nx : c->pp.ny;
+  TeamShape sh;
+  sh.T = std::min(256, n / 2);
+  sh.E = (pad ? 3 * n / 2 : n) / sh.T;
+  sh.blocks = row ? (pad ? 3 * c->pp.ny / 2 : c->pp.ny) / (256 / sh.T) : (c->pp.nx / 2) / (256 / sh.T);
+  return sh;
+}
+
+template <typename real>
+RowArgs<real> ctx_row_args(const zk_ctx *c, bool pad, const Phys &ph, int prog0) {
+  char *ws = c->ws;
+  RowArgs<real> a{};
+  a.ops = reinterpret_cast<const RowOp *>(ws + c->off_ops);
+  a.progs = reinterpret_cast<const RowProg *>(ws + c->off_progs);
+  a.prog0 = prog0;
+  a.mix = reinterpret_cast<cpx<real> *>(ws + c->off_mix);
+  a.mix_stride = c->mix_stride;
+  a.rows = pad ? 3 * c->pp.ny / 2 : c->pp.ny;
+  a.nx = c->pp.nx;
+  a.pin0 = ph.in0;
+  a.pin1 = ph.in1;
+  a.pin2 = ph.in2;
+  a.pout0 = ph.out0;
+  a.pout1 = ph.out1;
+  a.tw = reinterpret_cast<const cpx<real> *>(ws + c->off_tw[pad ? 0 : 1]);
+  a.kx_scale = 2.0 * M_PI / c->pp.Lx;
+  a.colmax = reinterpret_cast<const float *>(ws + c->off_cmax);
+  return a;
+}
+
+template <typename real>
+ColArgs<real> ctx_col_args(const zk_ctx *c, bool pad, int task0) {
+  char *ws = c->ws;
+  const int nx = c->pp.nx, ny = c->pp.ny;
+  const double kc = 2.0 / 3.0 * std::min(M_PI * nx / c->pp.Lx, M_PI * ny / c->pp.Ly);
+  ColArgs<real> a{};
+  a.tasks = reinterpret_cast<const ColTask *>(ws + c->off_tasks);
+  a.task0 = task0;
+  a.outs = reinterpret_cast<const ColOut *>(ws + c->off_outs);
+  a.terms = reinterpret_cast<const ColTerm *>(ws + c->off_terms);
+  a.mix = reinterpret_cast<cpx<real> *>(ws + c->off_mix);
+  a.mix_stride = c->mix_stride;
+  a.rows = pad ? 3 * ny / 2 : ny;
+  a.base = reinterpret_cast<cpx<double> *>(ws + c->off_base);
+  a.base_stride = c->base_stride;
+  a.ny = ny;
+  a.nx = nx;
+  a.tw = reinterpret_cast<const cpx<real> *>(ws + c->off_tw[pad ? 2 : 3]);
+  a.kx_scale = 2.0 * M_PI / c->pp.Lx;
+  a.ky_scale = 2.0 * M_PI / c->pp.Ly;
+  a.depth = c->pp.depth;
+  a.inv_kc = 1.0 / kc;
+  a.taper_on = c->pp.taper ? 1 : 0;
+  a.colmax = reinterpret_cast<float *>(ws + c->off_cmax);
+  a.sym = reinterpret_cast<const SymEl *>(ws + c->off_sym);
+  a.filt_x = reinterpret_cast<const double *>(ws + c->off_fx);
+  a.filt_y = reinterpret_cast<const double *>(ws + c->off_fy);
+  return a;
+}
+
+template RowArgs<double> ctx_row_args<double>(const zk_ctx *, bool, const Phys &, int);
+template RowArgs<float> ctx_row_args<float>(const zk_ctx *, bool, const Phys &, int);
+template ColArgs<double> ctx_col_args<double>(const zk_ctx *, bool, int);
+template ColArgs<float> ctx_col_args<float>(const zk_ctx *, bool, int);
+
+int ctx_upload(zk_ctx *c, double dt) { return upload(c, dt); }
 
 int ctx_prepare(zk_ctx *c) {
   int rc = check_call(c);

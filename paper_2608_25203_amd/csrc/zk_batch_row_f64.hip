@@ -1,0 +1,36 @@
+// zk_batch_row_f64.hip -- batched row-pass kernel instances (double transforms);
+// written by gen_batch_units.py.
+#include "zk_kernels.hpp"
+
+namespace zk {
+
+template <>
+const void *batch_row_kernel<double>(int T, int E) {
+  if (T == 32 && E == 2) return reinterpret_cast<const void *>(&row_kernel_batch<double, 32, 2>);
+  if (T == 32 && E == 3) return reinterpret_cast<const void *>(&row_kernel_batch<double, 32, 3>);
+  if (T == 32 && E == 4) return reinterpret_cast<const void *>(&row_kernel_batch<double, 32, 4>);
+  if (T == 32 && E == 6) return reinterpret_cast<const void *>(&row_kernel_batch<double, 32, 6>);
+  if (T == 32 && E == 8) return reinterpret_cast<const void *>(&row_kernel_batch<double, 32, 8>);
+  if (T == 32 && E == 12) return reinterpret_cast<const void *>(&row_kernel_batch<double, 32, 12>);
+  if (T == 64 && E == 2) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 2>);
+  if (T == 64 && E == 3) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 3>);
+  if (T == 64 && E == 4) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 4>);
+  if (T == 64 && E == 6) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 6>);
+  if (T == 64 && E == 8) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 8>);
+  if (T == 64 && E == 12) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 12>);
+  if (T == 128 && E == 2) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 2>);
+  if (T == 128 && E == 3) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 3>);
+  if (T == 128 && E == 4) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 4>);
+  if (T == 128 && E == 6) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 6>);
+  if (T == 128 && E == 8) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 8>);
+  if (T == 128 && E == 12) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 12>);
+  if (T == 256 && E == 2) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 2>);
+  if (T == 256 && E == 3) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 3>);
+  if (T == 256 && E == 4) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 4>);
+  if (T == 256 && E == 6) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 6>);
+  if (T == 256 && E == 8) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 8>);
+  if (T == 256 && E == 12) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 12>);
+  return nullptr;
+}
+
+}  // namespace zk

@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "zk_kernels.hpp"
 #include "zk_plan.hpp"
 
 struct zk_ctx {
@@ -63,6 +64,20 @@ struct Phys {
   const double *in0 = nullptr, *in1 = nullptr, *in2 = nullptr;
   double *out0 = nullptr, *out1 = nullptr;
 };
+
+// Default team shape of a pass: T threads per transform, first-pass radix E,
+// and the number of 256-thread blocks covering the pass's rows or columns.
+struct TeamShape {
+  int T, E, blocks;
+};
+TeamShape ctx_team(const zk_ctx *c, bool row, bool pad);
+// Argument records of the context's passes (pointers into its workspace).
+template <typename real>
+RowArgs<real> ctx_row_args(const zk_ctx *c, bool pad, const Phys &ph, int prog0);
+template <typename real>
+ColArgs<real> ctx_col_args(const zk_ctx *c, bool pad, int task0);
+// Build and upload the plan for step size dt (no-op if current).
+int ctx_upload(zk_ctx *c, double dt);
 
 // Validate the call, bind the device and make sure the schedules are uploaded
 // (dt of the last zk_step, or the default schedule).

@@ -206,10 +206,17 @@ struct Shape {
   }
 };
 
-// Row pass: TPB teams per block, one row each, all running program
-// progs[prog0 + blockIdx.y].
+// One entry of a batched launch: the tile's argument record and the
+// program (row pass) or task (column pass) its blocks run.
+struct BatchItem {
+  int32_t tile;   // index into the launch's argument table
+  int32_t index;  // program or task index in that tile's schedule
+};
+
+// Row pass body: TPB teams per block, one row each (block blk of the
+// pass), all running program progs[prog].
 template <typename real, int T, int E>
-__global__ __launch_bounds__(256) void row_kernel(RowArgs<real> a) {
+__device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int blk) {
   using S = Shape<T, E>;
   constexpr int N = S::N, L = S::L, NB = S::template nbuf<real>();
   constexpr bool TWL = S::template tw_in_lds<real>();
@@ -219,10 +226,10 @@ __global__ __launch_bounds__(256) void row_kernel(RowArgs<real> a) {
   const int team = threadIdx.x / T;
   const int t = threadIdx.x % T;
   // rows y and y+1 share 128-byte lines of the tiled fields
-  const int row = (S::TPB == 1 ? xcd_unit(blockIdx.x, a.rows, 2) : (int)blockIdx.x) * S::TPB + team;
+  const int row = (S::TPB == 1 ? xcd_unit(blk, a.rows, 2) : blk) * S::TPB + team;
   cpx<real> *b0 = smem + team * NB * L;
   cpx<real> *b1 = b0 + (NB - 1) * L;
-  const RowProg pg = a.progs[a.prog0 + blockIdx.y];
+  const RowProg pg = a.progs[prog];
   const cpx<real> *tw = a.tw;
   if constexpr (TWL) {
     for (int i = threadIdx.x; i < N; i += 256) twl[i] = a.tw[i];
@@ -432,11 +439,11 @@ __device__ __forceinline__ cpx<double> symval(uint32_t s, double kk, double g0, 
   return {f, 0.0};
 }
 
-// Column pass: TPB teams per block, one kx column each, all running task
-// tasks[task0 + blockIdx.y].  Thread t owns base-band rows b = t + T q,
-// q < QB (q = KR at t = 0 is the ky Nyquist row, kept zero).
+// Column pass body: TPB teams per block (block blk of the pass), one kx
+// column each, all running task tasks[task].  Thread t owns base-band rows
+// b = t + T q, q < QB (q = KR at t = 0 is the ky Nyquist row, kept zero).
 template <typename real, int T, int E>
-__global__ __launch_bounds__(256) void col_kernel(ColArgs<real> a) {
+__device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index, int blk) {
   using S = Shape<T, E>;
   constexpr int N = S::N, L = S::L, NB = S::template nbuf<real>(), QB = S::QB;
   constexpr bool TWL = S::template tw_in_lds<real>();
@@ -447,10 +454,10 @@ __global__ __launch_bounds__(256) void col_kernel(ColArgs<real> a) {
   const int t = threadIdx.x % T;
   // columns of one tile share 128-byte lines; keep a tile's blocks on one XCD
   constexpr int CBMAX = MixTile<real>::CB > CBB ? MixTile<real>::CB : CBB;
-  const int col = xcd_unit(blockIdx.x, a.nx / 2 / S::TPB, CBMAX / S::TPB) * S::TPB + team;
+  const int col = xcd_unit(blk, a.nx / 2 / S::TPB, CBMAX / S::TPB) * S::TPB + team;
   cpx<real> *b0 = smem + team * NB * L;
   cpx<real> *b1 = b0 + (NB - 1) * L;
-  const ColTask task = a.tasks[a.task0 + blockIdx.y];
+  const ColTask task = a.tasks[task_index];
   const int ny = a.ny;
   const cpx<real> *tw = a.tw;
   if constexpr (TWL) {
@@ -553,6 +560,53 @@ __global__ __launch_bounds__(256) void col_kernel(ColArgs<real> a) {
     }
   }
 }
+
+// Single-grid kernels: the argument record by value, programs or tasks
+// first + blockIdx.y.
+template <typename real, int T, int E>
+__global__ __launch_bounds__(256) void row_kernel(RowArgs<real> a) {
+  row_body<real, T, E>(a, a.prog0 + blockIdx.y, blockIdx.x);
+}
+template <typename real, int T, int E>
+__global__ __launch_bounds__(256) void col_kernel(ColArgs<real> a) {
+  col_body<real, T, E>(a, a.task0 + blockIdx.y, blockIdx.x);
+}
+
+// Batched kernels: blockIdx.y selects an item (tile argument record and
+// program or task); every tile of one launch shares the team shape (T, E),
+// so blockIdx.x spans the same rows or columns for each.
+template <typename real, int T, int E>
+__global__ __launch_bounds__(256) void row_kernel_batch(const RowArgs<real> *__restrict__ args,
+                                                        const BatchItem *__restrict__ items) {
+  const BatchItem it = items[blockIdx.y];
+  const RowArgs<real> a = args[it.tile];
+  row_body<real, T, E>(a, it.index, blockIdx.x);
+}
+template <typename real, int T, int E>
+__global__ __launch_bounds__(256) void col_kernel_batch(const ColArgs<real> *__restrict__ args,
+                                                        const BatchItem *__restrict__ items) {
+  const BatchItem it = items[blockIdx.y];
+  const ColArgs<real> a = args[it.tile];
+  col_body<real, T, E>(a, it.index, blockIdx.x);
+}
+
+// Team shapes (T, E) compiled for the batched kernels: T in {32, 64, 128,
+// 256} threads and E in {2, 3, 4, 6, 8, 12}, so that each power-of-two length
+// n in [64, 2048] has one to three candidate shapes for its padded (3n/2)
+// and base (n) transforms; the autotuner picks among them.  These return the
+// kernel for (T, E), or nullptr if that shape is not built.
+template <typename real>
+const void *batch_row_kernel(int T, int E);
+template <typename real>
+const void *batch_col_kernel(int T, int E);
+template <>
+const void *batch_row_kernel<double>(int T, int E);
+template <>
+const void *batch_row_kernel<float>(int T, int E);
+template <>
+const void *batch_col_kernel<double>(int T, int E);
+template <>
+const void *batch_col_kernel<float>(int T, int E);
 
 // launch wrappers (defined in the per-precision instantiation units)
 template <typename real>

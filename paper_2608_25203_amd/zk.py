@@ -23,7 +23,16 @@ EXPORTS = ("zk_create", "zk_destroy", "zk_set_option", "zk_workspace_bytes", "zk
            "zk_cnn_get_params", "zk_cnn_forward", "zk_cnn_gradient", "zk_cnn_train_step", "zk_cnn_last_error",
            "zk_closure_create", "zk_closure_destroy", "zk_closure_workspace_bytes", "zk_closure_bind",
            "zk_closure_dtn", "zk_closure_features", "zk_closure_crops", "zk_closure_step", "zk_closure_stats",
-           "zk_closure_last_error")
+           "zk_closure_last_error",
+           "zk_batch_create", "zk_batch_destroy", "zk_batch_workspace_bytes", "zk_batch_bind", "zk_batch_set_fields",
+           "zk_batch_set_option", "zk_batch_step", "zk_batch_autotune", "zk_batch_tuning", "zk_batch_stats",
+           "zk_batch_last_error")
+ZK_BATCH_OPT_GRAPH = 1
+
+
+class ZkTile(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("Lx", ctypes.c_double), ("Ly", ctypes.c_double),
+                ("depth", ctypes.c_double), ("M", ctypes.c_int)]
 ZK_CNN_NPARAMS = 19681
 
 _lib = None
@@ -103,6 +112,24 @@ def lib():
         getattr(L, f).restype = i
     L.zk_closure_last_error.argtypes = [vp]
     L.zk_closure_last_error.restype = ctypes.c_char_p
+    L.zk_batch_create.argtypes = [i, ctypes.POINTER(ZkTile), d, i]
+    L.zk_batch_create.restype = vp
+    L.zk_batch_destroy.argtypes = [vp]
+    L.zk_batch_destroy.restype = None
+    L.zk_batch_workspace_bytes.argtypes = [vp]
+    L.zk_batch_workspace_bytes.restype = sz
+    L.zk_batch_bind.argtypes = [vp, vp, sz, vp]
+    L.zk_batch_set_fields.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    L.zk_batch_set_option.argtypes = [vp, i, d]
+    L.zk_batch_step.argtypes = [vp, d, i]
+    L.zk_batch_autotune.argtypes = [vp, d, i]
+    L.zk_batch_tuning.argtypes = [vp, i, pi, pi, pi, pi, pi]
+    L.zk_batch_stats.argtypes = [vp, pll, pll]
+    for f in ("zk_batch_bind", "zk_batch_set_fields", "zk_batch_set_option", "zk_batch_step", "zk_batch_autotune",
+              "zk_batch_tuning", "zk_batch_stats"):
+        getattr(L, f).restype = i
+    L.zk_batch_last_error.argtypes = [vp]
+    L.zk_batch_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -403,6 +430,88 @@ class Closure:
         if getattr(self, "c", None):
             lib().zk_closure_destroy(self.c)
             self.c = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- batches of tiles ------------------------------------------------------------------
+class Batch:
+    """zk_batch_*: tiles given as dicts with nx, ny, Lx, Ly, depth (inf or <= 0:
+    deep) and M; fields are registered once (contiguous float64 device
+    tensors [ny, nx]) and stepped in place."""
+
+    def __init__(self, tiles, g=9.81, precision=32, device="cuda", graph=True):
+        import math
+
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        arr = (ZkTile * len(tiles))()
+        for k, t in enumerate(tiles):
+            dep = t.get("depth", math.inf)
+            arr[k] = ZkTile(int(t["nx"]), int(t["ny"]), float(t["Lx"]), float(t["Ly"]),
+                            float(dep) if dep is not None else math.inf, int(t["M"]))
+        self.tiles = [dict(t) for t in tiles]
+        self.b = lib().zk_batch_create(len(tiles), arr, float(g), int(precision))
+        if not self.b:
+            raise ZKError(ZK_EINVAL, "zk_batch_create rejected the tiles")
+        self._check(lib().zk_batch_set_option(self.b, ZK_BATCH_OPT_GRAPH, 1.0 if graph else 0.0))
+        nbytes = int(lib().zk_batch_workspace_bytes(self.b))
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self.ws.data_ptr()) % 256
+            self.stream = torch.cuda.current_stream(self.device)
+            self._check(lib().zk_batch_bind(self.b, self.ws.data_ptr() + off, nbytes, self.stream.cuda_stream))
+        self.fields = None
+
+    def _check(self, rc):
+        if rc != ZK_OK:
+            raise ZKError(rc, lib().zk_batch_last_error(self.b).decode())
+
+    def set_fields(self, etas, psis):
+        t = self.torch
+        for k, (e, p) in enumerate(zip(etas, psis)):
+            shp = (self.tiles[k]["ny"], self.tiles[k]["nx"])
+            for x in (e, p):
+                if x.dtype != t.float64 or not x.is_contiguous() or tuple(x.shape) != shp:
+                    raise ValueError(f"tile {k}: fields must be contiguous float64 tensors of shape {shp}")
+        self.fields = (list(etas), list(psis))  # keep them alive
+        n = len(etas)
+        pe = (ctypes.c_void_p * n)(*[e.data_ptr() for e in etas])
+        pp = (ctypes.c_void_p * n)(*[p.data_ptr() for p in psis])
+        self._check(lib().zk_batch_set_fields(self.b, pe, pp))
+
+    def step(self, dt, nsteps):
+        self._check(lib().zk_batch_step(self.b, float(dt), int(nsteps)))
+
+    def autotune(self, dt, reps=3):
+        self._check(lib().zk_batch_autotune(self.b, float(dt), int(reps)))
+        return self.tuning()
+
+    def tuning(self):
+        out, k = [], 0
+        while True:
+            v = [ctypes.c_int(0) for _ in range(5)]
+            if lib().zk_batch_tuning(self.b, k, *[ctypes.byref(x) for x in v]) != ZK_OK:
+                return out
+            out.append({"row": bool(v[0].value), "pad": bool(v[1].value), "n": v[2].value, "T": v[3].value,
+                        "E": v[4].value})
+            k += 1
+
+    def stats(self):
+        a, b = ctypes.c_longlong(0), ctypes.c_longlong(0)
+        self._check(lib().zk_batch_stats(self.b, ctypes.byref(a), ctypes.byref(b)))
+        return {"phases_per_step": a.value, "launches_per_step": b.value}
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().zk_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

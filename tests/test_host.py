@@ -127,3 +127,33 @@ def test_library_host_side_argument_checks():
     # calls before zk_bind report a missing workspace without touching a device
     assert L.zk_dtn(ctx, None, None, None) == zk.ZK_ENOWS
     L.zk_destroy(ctx)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libzk.so not built")
+def test_batch_create_host_checks():
+    """zk_batch_create is host-only: it accepts valid tiles (workspace = the
+    tiles' workspaces plus the argument and item tables) and rejects an
+    invalid tile size, order or precision."""
+    from paper_2608_25203_amd import zk
+
+    L = zk.lib()
+    good = (zk.ZkTile * 2)(zk.ZkTile(64, 64, 1.0, 1.0, 0.5, 3), zk.ZkTile(128, 64, 2.0, 1.0, math.inf, 5))
+    b = L.zk_batch_create(2, good, 9.81, 32)
+    assert b
+    ws = L.zk_batch_workspace_bytes(b)
+    c0 = L.zk_create(64, 64, 1.0, 1.0, 0.5, 9.81, 3)
+    c1 = L.zk_create(128, 64, 2.0, 1.0, math.inf, 9.81, 5)
+    for c in (c0, c1):
+        assert L.zk_set_option(c, zk.ZK_OPT_PRECISION, 32) == 0
+    assert ws > L.zk_workspace_bytes(c0) + L.zk_workspace_bytes(c1)
+    L.zk_destroy(c0)
+    L.zk_destroy(c1)
+    L.zk_batch_destroy(b)
+    for bad, prec in (((100, 64, 1.0, 1.0, 0.5, 3), 32), ((64, 64, 1.0, 1.0, 0.5, 9), 32),
+                      ((64, 64, 1.0, 1.0, 0.5, 3), 16)):
+        arr = (zk.ZkTile * 1)(zk.ZkTile(*bad))
+        assert not L.zk_batch_create(1, arr, 9.81, prec)
+    # stepping an unbound batch is an error, not a crash
+    b = L.zk_batch_create(2, good, 9.81, 64)
+    assert L.zk_batch_step(b, 0.01, 1) == zk.ZK_ENOWS
+    L.zk_batch_destroy(b)
