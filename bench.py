@@ -217,6 +217,90 @@ def closure_form(nsteps=1000, audit_every=10, tol=1e-4):
     return out
 
 
+def batch_form(nsteps=100, seq_steps=20, ntiles=256):
+    """Many independent tiles in one batch: 256 tiles drawn from
+    default_rng(4) -- size uniform in {128, 256, 512, 1024}^2 with 1 m
+    spacing, M uniform in 3..6, depth uniform in [10, 200] m, JONSWAP
+    steepness uniform in [0.02, 0.12] (k_p = 2 pi / 16 m, seed 1000 + i) --
+    FP32 transforms with FP64 series and state, RK4 dt = 0.05 s, team shapes
+    autotuned, each step replayed as a HIP graph.  Whole-batch grid-point-
+    steps/s, beside the same tiles stepped one context after another."""
+    import numpy as np
+    import torch
+
+    from paper_2608_25203_amd.inputs import jonswap_state
+    from paper_2608_25203_amd.zk import Batch, Solver
+
+    rng = np.random.default_rng(4)
+    kp, dt, g = 2 * math.pi / 16.0, 0.05, 9.81
+    tiles, states = [], []
+    for i in range(ntiles):
+        n = int(rng.choice([128, 256, 512, 1024]))
+        M = int(rng.integers(3, 7))
+        h = float(rng.uniform(10.0, 200.0))
+        st = float(rng.uniform(0.02, 0.12))
+        tiles.append(dict(nx=n, ny=n, Lx=float(n), Ly=float(n), depth=h, M=M))
+        states.append(jonswap_state(n, n, float(n), float(n), h, g, kp, st, 1000 + i))
+    print(f"# batch form: {ntiles} tiles generated", file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    pts = sum(t["nx"] * t["ny"] for t in tiles)
+    b = Batch(tiles, g=g, precision=32, device=dev)
+    es = [torch.tensor(e, dtype=torch.float64, device=dev) for e, _ in states]
+    ps = [torch.tensor(p, dtype=torch.float64, device=dev) for _, p in states]
+    b.set_fields(es, ps)
+    tuning = b.autotune(dt, reps=2)
+    b.step(dt, 2)  # warm-up: graphs replayed once
+    for k, (e, p) in enumerate(states):  # restore the initial state in the same buffers
+        es[k].copy_(torch.from_numpy(e))
+        ps[k].copy_(torch.from_numpy(p))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(dt, nsteps)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    print(f"# batch form: {nsteps} batched steps in {tb:.2f} s", file=sys.stderr, flush=True)
+    st_b = b.stats()
+    b.close()
+    del b, es, ps
+    torch.cuda.empty_cache()
+    # the same tiles one context after another (seq_steps steps, same start)
+    solvers, es2, ps2 = [], [], []
+    for t, (e, p) in zip(tiles, states):
+        solvers.append(Solver(t["nx"], t["ny"], t["Lx"], t["Ly"], t["depth"], g, t["M"], precision=32, check=False,
+                              device=dev))
+        es2.append(torch.tensor(e, dtype=torch.float64, device=dev))
+        ps2.append(torch.tensor(p, dtype=torch.float64, device=dev))
+    for s, e, p in zip(solvers, es2, ps2):  # warm-up on copies
+        s.step(e.clone(), p.clone(), dt, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, e, p in zip(solvers, es2, ps2):
+        s.step(e, p, dt, seq_steps)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    # the batch's result after seq_steps for the largest-M tile equals its context's
+    bchk = Batch(tiles, g=g, precision=32, device=dev)
+    es3 = [torch.tensor(e, dtype=torch.float64, device=dev) for e, _ in states]
+    ps3 = [torch.tensor(p, dtype=torch.float64, device=dev) for _, p in states]
+    bchk.set_fields(es3, ps3)
+    bchk.step(dt, seq_steps)
+    torch.cuda.synchronize()
+    diff = max(rel_max(es3[k], es2[k]) for k in range(ntiles))
+    bchk.close()
+    for s in solvers:
+        s.close()
+    torch.cuda.empty_cache()
+    sizes = {n: sum(1 for t in tiles if t["nx"] == n) for n in (128, 256, 512, 1024)}
+    return {"workload": f"{ntiles} tiles, sizes {sizes} (1 m spacing), M 3..6, depth 10..200 m, JONSWAP "
+                        f"steepness 0.02..0.12, k_p = 2 pi / 16 m, RK4 dt {dt} s, FP32 transforms",
+            "grid_points": pts, "value": round(pts * nsteps / tb, 1), "unit": "grid-point-steps/s",
+            "steps": nsteps, "ms_per_step": round(1e3 * tb / nsteps, 3),
+            "sequential_value": round(pts * seq_steps / ts, 1), "sequential_steps": seq_steps,
+            "speedup_vs_sequential": round((pts * nsteps / tb) / (pts * seq_steps / ts), 3),
+            "phases_per_step": st_b["phases_per_step"], "launches_per_step": st_b["launches_per_step"],
+            "graph": True, "tuning": tuning, "max_rel_diff_vs_sequential_eta": diff}
+
+
 def c2_diagnostics(w, H_before, H_after):
     """Hamiltonian drift of the timed run and the linear-limit dispersion error
     (eps = 0, filter off) of single modes on the benchmark grid: measured
@@ -277,8 +361,9 @@ def main():
     ap.add_argument("--precision", type=int, default=64, choices=(32, 64))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default team shapes")
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the precision-form (2048^2 M=5) and closure-form (1024^2) comparisons")
+                    help="skip the precision-form (2048^2 M=5), closure-form (1024^2) and batch-form (256 tiles) runs")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -312,6 +397,7 @@ def main():
     e = torch.tensor(eta, dtype=torch.float64, device=dev)
     p = torch.tensor(psi, dtype=torch.float64, device=dev)
 
+    shapes = s.autotune(w["dt"], reps=3) if not args.no_autotune else s.team_shapes()
     # warmup (also uploads the dt-dependent schedule)
     if args.warmup > 0:
         s.step(e, p, w["dt"], args.warmup)
@@ -374,6 +460,7 @@ def main():
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kern.items()},
         "kernel_ms_per_step": round(step_kernel_ms, 4),
+        "team_shapes": {k: {"T": v[0], "E": v[1]} for k, v in shapes.items()},
         "finite": finite,
     }
     if args.workload == "c2_512_m4":
@@ -381,6 +468,7 @@ def main():
     if not args.no_forms:
         out["precision_form"] = precision_form()
         out["closure_form"] = closure_form()
+        out["batch_form"] = batch_form()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, eta, psi, args.cpu_steps)
         out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 1)

@@ -134,6 +134,19 @@ int zk_hamiltonian(zk_ctx *ctx, const double *eta, const double *psi, double *H_
  * then be NULL). */
 int zk_kernel_stats(zk_ctx *ctx, int kind, double *ms, double *bytes, double *flops, long long *launches);
 
+/* Autotuner: for each pass kind (row / column, padded / base transform),
+ * time every compiled team shape (T threads per transform, first-pass radix
+ * E = N / T, T in {32, 64, 128, 256}) on the passes of one RK4 step of this
+ * context (reps timed repetitions each; the context's internal spectra are
+ * overwritten, no caller field is touched) and keep the fastest for later
+ * calls.  Results are identical up to FP64 (or FP32) rounding order.
+ * Synchronises. */
+int zk_autotune(zk_ctx *ctx, double dt, int reps);
+
+/* Team shape in use for a pass kind (row != 0: row pass; pad != 0: padded
+ * transform). */
+int zk_team_shape(const zk_ctx *ctx, int row, int pad, int *T, int *E);
+
 /* Text of the last error on this context ("" if none).  Valid until the next
  * call on the context. */
 const char *zk_last_error(const zk_ctx *ctx);

@@ -92,6 +92,14 @@ void compute_layout(zk_ctx *c) {
   off = align_up(off + c->sched_cap[3] * sizeof(ColOut));
   c->off_tasks = off;
   off = align_up(off + c->sched_cap[4] * sizeof(ColTask));
+  c->off_rargs = off;  // [pad, base] row argument records
+  off = align_up(off + 2 * std::max(sizeof(RowArgs<double>), sizeof(RowArgs<float>)));
+  c->off_cargs = off;  // [pad, base] column argument records
+  off = align_up(off + 2 * std::max(sizeof(ColArgs<double>), sizeof(ColArgs<float>)));
+  c->off_iprog = off;  // items {pad 0 | base 1, program}, pad block then base block
+  off = align_up(off + 2 * c->sched_cap[1] * sizeof(BatchItem));
+  c->off_itask = off;  // items {pad 0 | base 1, task}
+  off = align_up(off + 2 * c->sched_cap[4] * sizeof(BatchItem));
   c->off_red = off;
   off = align_up(off + (2 * kRedBlocks + 8) * sizeof(double));
   c->off_cmax = off;
@@ -193,6 +201,39 @@ int upload(zk_ctx *c, double dt) {
       }
     }
   }
+  {
+    // argument records (field pointers come with each call) and items
+    std::vector<char> rt(2 * std::max(sizeof(RowArgs<double>), sizeof(RowArgs<float>)));
+    std::vector<char> ct(2 * std::max(sizeof(ColArgs<double>), sizeof(ColArgs<float>)));
+    const Phys none;
+    for (int p = 0; p < 2; ++p) {
+      if (c->precision == 32) {
+        const RowArgs<float> r = ctx_row_args<float>(c, p == 0, none, 0);
+        const ColArgs<float> k = ctx_col_args<float>(c, p == 0, 0);
+        std::memcpy(&rt[p * sizeof(r)], &r, sizeof(r));
+        std::memcpy(&ct[p * sizeof(k)], &k, sizeof(k));
+      } else {
+        const RowArgs<double> r = ctx_row_args<double>(c, p == 0, none, 0);
+        const ColArgs<double> k = ctx_col_args<double>(c, p == 0, 0);
+        std::memcpy(&rt[p * sizeof(r)], &r, sizeof(r));
+        std::memcpy(&ct[p * sizeof(k)], &k, sizeof(k));
+      }
+    }
+    std::vector<BatchItem> ip(2 * c->sched_cap[1]), it(2 * c->sched_cap[4]);
+    for (size_t k = 0; k < c->sched_cap[1]; ++k) {
+      ip[k] = BatchItem{0, (int32_t)k};
+      ip[c->sched_cap[1] + k] = BatchItem{1, (int32_t)k};
+    }
+    for (size_t k = 0; k < c->sched_cap[4]; ++k) {
+      it[k] = BatchItem{0, (int32_t)k};
+      it[c->sched_cap[4] + k] = BatchItem{1, (int32_t)k};
+    }
+    HIP_TRY(c, put(c->off_rargs, rt.data(), rt.size()));
+    HIP_TRY(c, put(c->off_cargs, ct.data(), ct.size()));
+    HIP_TRY(c, put(c->off_iprog, ip.data(), ip.size() * sizeof(BatchItem)));
+    HIP_TRY(c, put(c->off_itask, it.data(), it.size() * sizeof(BatchItem)));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
   HIP_TRY(c, hipStreamSynchronize(c->stream));  // host vectors may change after return
   c->plan_dt = dt;
   c->have_plan = true;
@@ -213,17 +254,19 @@ int run_seq_t(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
       HIP_TRY(c, take_event(c, &rec.b));
       HIP_TRY(c, hipEventRecord(rec.a, c->stream));
     }
-    if (l.kind == L_ROW_PAD || l.kind == L_ROW_BASE) {
-      const bool pad = l.kind == L_ROW_PAD;
-      const RowArgs<real> a = ctx_row_args<real>(c, pad, ph, l.first);
-      const TeamShape sh = ctx_team(c, true, pad);
-      e = launch_row<real>(a, sh.T, sh.E, sh.blocks, l.count, c->stream);
-    } else if (l.kind == L_COL_PAD || l.kind == L_COL_BASE) {
-      const bool pad = l.kind == L_COL_PAD;
-      const ColArgs<real> a = ctx_col_args<real>(c, pad, l.first);
-      const TeamShape sh = ctx_team(c, false, pad);
-      e = launch_col<real>(a, sh.T, sh.E, sh.blocks, l.count, c->stream);
-    } else if (l.kind == L_PARSEVAL) {
+    if (l.kind != L_PARSEVAL) {
+      const bool row = l.kind == L_ROW_PAD || l.kind == L_ROW_BASE;
+      const bool pad = l.kind == L_ROW_PAD || l.kind == L_COL_PAD;
+      const TeamShape sh = ctx_team(c, row, pad);
+      const void *fn = row ? batch_row_kernel<real>(sh.T, sh.E) : batch_col_kernel<real>(sh.T, sh.E);
+      if (!fn) return fail(c, ZK_EINVAL, "team shape not built");
+      void *args = ws + (row ? c->off_rargs : c->off_cargs);
+      BatchItem *items = reinterpret_cast<BatchItem *>(ws + (row ? c->off_iprog : c->off_itask)) +
+                         (pad ? 0 : (row ? c->sched_cap[1] : c->sched_cap[4])) + l.first;
+      PhysArgs pa{ph.in0, ph.in1, ph.in2, ph.out0, ph.out1, 1};
+      void *params[] = {&args, &items, &pa};
+      e = hipLaunchKernel(fn, dim3(sh.blocks, l.count), dim3(256), params, 0, c->stream);
+    } else {
       double *red = reinterpret_cast<double *>(ws + c->off_red);
       e = launch_parseval(base + (long long)l.first * c->base_stride, base + (long long)l.count * c->base_stride,
                           base + (long long)l.c2 * c->base_stride, base + (long long)l.d2 * c->base_stride, nx / 2, ny,
@@ -262,11 +305,11 @@ bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 namespace zk {
 
 TeamShape ctx_team(const zk_ctx *c, bool row, bool pad) {
-  // T = min(256, n/2) threads per transform; first-pass radix E = N / T;
-  // a 256-thread block holds 256 / T teams (rows or columns)
+  // default T = min(256, n/2) threads per transform, or the autotuned shape;
+  // first-pass radix E = N / T; a 256-thread block holds 256 / T teams
   const int n = row ? c->pp.nx : c->pp.ny;
   TeamShape sh;
-  sh.T = std::min(256, n / 2);
+  sh.T = c->tuneT[row][pad] ? c->tuneT[row][pad] : std::min(256, n / 2);
   sh.E = (pad ? 3 * n / 2 : n) / sh.T;
   sh.blocks = row ? (pad ? 3 * c->pp.ny / 2 : c->pp.ny) / (256 / sh.T) : (c->pp.nx / 2) / (256 / sh.T);
   return sh;
@@ -524,6 +567,67 @@ int zk_kernel_stats(zk_ctx *c, int kind, double *ms, double *bytes, double *flop
   *bytes = c->st_bytes[kind];
   *flops = c->st_flops[kind];
   *launches = c->st_n[kind];
+  return ZK_OK;
+}
+
+int zk_autotune(zk_ctx *c, double dt, int reps) {
+  int rc = check_call(c);
+  if (rc) return rc;
+  if (!std::isfinite(dt) || reps < 1) return fail(c, ZK_EINVAL, "dt must be finite and reps >= 1");
+  if ((rc = upload(c, dt))) return rc;
+  const bool prof = c->prof;
+  c->prof = false;
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  for (int row = 1; row >= 0; --row)
+    for (int pad = 1; pad >= 0; --pad) {
+      std::vector<Launch> sub;
+      for (const Launch &l : c->plan.step_body[0]) {
+        const bool lr = l.kind == L_ROW_PAD || l.kind == L_ROW_BASE;
+        const bool lp = l.kind == L_ROW_PAD || l.kind == L_COL_PAD;
+        if (l.kind != L_PARSEVAL && lr == (bool)row && lp == (bool)pad) sub.push_back(l);
+      }
+      if (sub.empty()) continue;
+      const int n = row ? c->pp.nx : c->pp.ny;
+      const int N = pad ? 3 * n / 2 : n;
+      float best = 1e30f;
+      int bestT = 0;
+      for (int E : pad ? std::vector<int>{3, 6, 12} : std::vector<int>{2, 4, 8}) {
+        const int T = N / E;
+        if (N % E || !(T == 32 || T == 64 || T == 128 || T == 256)) continue;
+        const void *fn = c->precision == 32 ? (row ? batch_row_kernel<float>(T, E) : batch_col_kernel<float>(T, E))
+                                            : (row ? batch_row_kernel<double>(T, E) : batch_col_kernel<double>(T, E));
+        if (!fn) continue;
+        c->tuneT[row][pad] = T;
+        float tot = 0.f;
+        for (int r = 0; r <= reps; ++r) {  // r = 0 warms up
+          HIP_TRY(c, hipEventRecord(e0, c->stream));
+          if ((rc = run_seq(c, sub, Phys{}))) return rc;
+          HIP_TRY(c, hipEventRecord(e1, c->stream));
+          HIP_TRY(c, hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+          if (r) tot += ms;
+        }
+        if (tot < best) {
+          best = tot;
+          bestT = T;
+        }
+      }
+      c->tuneT[row][pad] = bestT;
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  c->prof = prof;
+  return ZK_OK;
+}
+
+int zk_team_shape(const zk_ctx *c, int row, int pad, int *T, int *E) {
+  if (!c || !T || !E) return ZK_EINVAL;
+  const TeamShape sh = ctx_team(c, row != 0, pad != 0);
+  *T = sh.T;
+  *E = sh.E;
   return ZK_OK;
 }
 

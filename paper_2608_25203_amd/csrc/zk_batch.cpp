@@ -176,7 +176,8 @@ int launch(zk_batch *b, const BL &l) {
   BatchItem *it;
   kernel_params(b, l, &fn, &args, &it);
   if (!fn) return fail(b, ZK_EINVAL, "team shape not built");
-  void *params[] = {&args, &it};
+  PhysArgs ph{};
+  void *params[] = {&args, &it, &ph};
   HIP_TRY(b, hipLaunchKernel(fn, dim3(l.blocks, l.nitems), dim3(256), params, 0, b->stream));
   return ZK_OK;
 }
@@ -201,7 +202,8 @@ int build_graph(zk_batch *b, int s) {
         rc = fail(b, ZK_EINVAL, "team shape not built");
         break;
       }
-      void *params[] = {&args, &it};
+      PhysArgs ph{};
+      void *params[] = {&args, &it, &ph};
       hipKernelNodeParams p{};
       p.func = const_cast<void *>(fn);
       p.gridDim = dim3(l.blocks, l.nitems);

@@ -561,30 +561,35 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   }
 }
 
-// Single-grid kernels: the argument record by value, programs or tasks
-// first + blockIdx.y.
-template <typename real, int T, int E>
-__global__ __launch_bounds__(256) void row_kernel(RowArgs<real> a) {
-  row_body<real, T, E>(a, a.prog0 + blockIdx.y, blockIdx.x);
-}
-template <typename real, int T, int E>
-__global__ __launch_bounds__(256) void col_kernel(ColArgs<real> a) {
-  col_body<real, T, E>(a, a.task0 + blockIdx.y, blockIdx.x);
-}
+// Caller fields of a single-grid call; they replace the argument record's
+// field pointers when use != 0 (batches keep theirs in the record).
+struct PhysArgs {
+  const double *in0, *in1, *in2;
+  double *out0, *out1;
+  int use;
+};
 
-// Batched kernels: blockIdx.y selects an item (tile argument record and
-// program or task); every tile of one launch shares the team shape (T, E),
-// so blockIdx.x spans the same rows or columns for each.
+// The row and column kernels: blockIdx.y selects an item (argument record
+// and program or task); every item of one launch shares the team shape
+// (T, E), so blockIdx.x spans the same rows or columns for each.  A single
+// grid is the batch of one tile.
 template <typename real, int T, int E>
 __global__ __launch_bounds__(256) void row_kernel_batch(const RowArgs<real> *__restrict__ args,
-                                                        const BatchItem *__restrict__ items) {
+                                                        const BatchItem *__restrict__ items, PhysArgs ph) {
   const BatchItem it = items[blockIdx.y];
-  const RowArgs<real> a = args[it.tile];
+  RowArgs<real> a = args[it.tile];
+  if (ph.use) {
+    a.pin0 = ph.in0;
+    a.pin1 = ph.in1;
+    a.pin2 = ph.in2;
+    a.pout0 = ph.out0;
+    a.pout1 = ph.out1;
+  }
   row_body<real, T, E>(a, it.index, blockIdx.x);
 }
 template <typename real, int T, int E>
 __global__ __launch_bounds__(256) void col_kernel_batch(const ColArgs<real> *__restrict__ args,
-                                                        const BatchItem *__restrict__ items) {
+                                                        const BatchItem *__restrict__ items, PhysArgs) {
   const BatchItem it = items[blockIdx.y];
   const ColArgs<real> a = args[it.tile];
   col_body<real, T, E>(a, it.index, blockIdx.x);
@@ -607,20 +612,6 @@ template <>
 const void *batch_col_kernel<double>(int T, int E);
 template <>
 const void *batch_col_kernel<float>(int T, int E);
-
-// launch wrappers (defined in the per-precision instantiation units)
-template <typename real>
-hipError_t launch_row(const RowArgs<real> &a, int T, int E, int nblocks, int nprog, hipStream_t s);
-template <typename real>
-hipError_t launch_col(const ColArgs<real> &a, int T, int E, int nblocks, int ntask, hipStream_t s);
-template <>
-hipError_t launch_row<double>(const RowArgs<double> &a, int T, int E, int nblocks, int nprog, hipStream_t s);
-template <>
-hipError_t launch_row<float>(const RowArgs<float> &a, int T, int E, int nblocks, int nprog, hipStream_t s);
-template <>
-hipError_t launch_col<double>(const ColArgs<double> &a, int T, int E, int nblocks, int ntask, hipStream_t s);
-template <>
-hipError_t launch_col<float>(const ColArgs<float> &a, int T, int E, int nblocks, int ntask, hipStream_t s);
 
 // FP64 reductions over base spectra (zk_reduce.hip).  Writes
 //   out[0] = sum_k w(kx) Re(conj(a) b),  out[1] = sum_k w(kx) Re(conj(c) d)

@@ -18,7 +18,7 @@ ZK_KERNEL_ROW_PAD, ZK_KERNEL_ROW_BASE, ZK_KERNEL_COL_PAD, ZK_KERNEL_COL_BASE, ZK
 KERNEL_NAMES = {0: "row_pad", 1: "row_base", 2: "col_pad", 3: "col_base", 4: "reduce"}
 
 EXPORTS = ("zk_create", "zk_destroy", "zk_set_option", "zk_workspace_bytes", "zk_bind", "zk_dtn",
-           "zk_rhs", "zk_step", "zk_hamiltonian", "zk_kernel_stats", "zk_last_error",
+           "zk_rhs", "zk_step", "zk_hamiltonian", "zk_kernel_stats", "zk_autotune", "zk_team_shape", "zk_last_error",
            "zk_cnn_create", "zk_cnn_destroy", "zk_cnn_workspace_bytes", "zk_cnn_bind", "zk_cnn_set_params",
            "zk_cnn_get_params", "zk_cnn_forward", "zk_cnn_gradient", "zk_cnn_train_step", "zk_cnn_last_error",
            "zk_closure_create", "zk_closure_destroy", "zk_closure_workspace_bytes", "zk_closure_bind",
@@ -74,6 +74,10 @@ def lib():
     L.zk_kernel_stats.argtypes = [vp, i, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d),
                                   ctypes.POINTER(ctypes.c_longlong)]
     L.zk_kernel_stats.restype = i
+    L.zk_autotune.argtypes = [vp, d, i]
+    L.zk_autotune.restype = i
+    L.zk_team_shape.argtypes = [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]
+    L.zk_team_shape.restype = i
     L.zk_last_error.argtypes = [vp]
     L.zk_last_error.restype = ctypes.c_char_p
     ll, pd, pf = ctypes.c_longlong, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_float)
@@ -248,6 +252,20 @@ class Solver:
     def hamiltonian(self, eta, psi):
         eta, psi = self._field(eta), self._field(psi)
         return zk_hamiltonian(self.ctx, eta.data_ptr(), psi.data_ptr())
+
+    def autotune(self, dt, reps=3):
+        """Time the compiled team shapes of every pass kind on one step and keep the fastest."""
+        _check(self.ctx, lib().zk_autotune(self.ctx, float(dt), int(reps)))
+        return self.team_shapes()
+
+    def team_shapes(self):
+        out = {}
+        for row in (1, 0):
+            for pad in (1, 0):
+                T, E = ctypes.c_int(0), ctypes.c_int(0)
+                _check(self.ctx, lib().zk_team_shape(self.ctx, row, pad, ctypes.byref(T), ctypes.byref(E)))
+                out[("row" if row else "col") + ("_pad" if pad else "_base")] = (T.value, E.value)
+        return out
 
     def kernel_stats(self):
         """{kind name: (ms, bytes, flops, launches)} for launches timed so far."""

@@ -189,3 +189,30 @@ def test_c3_shape_parity_fp64_and_fp32(torch):
         s.close()
         del s
         torch.cuda.empty_cache()
+
+
+def test_autotuned_shapes_keep_parity(torch):
+    """After the autotuner picks team shapes (possibly not the default ones),
+    G psi, the RHS and 3 RK4 steps still meet the FP64 bar, on the 512 x 512
+    M = 4 workload and on a non-square grid."""
+    for name, (nx, ny, Lx, Ly, h, M) in {"c2": (512, 512, 200.0, 200.0, 20.0, 4),
+                                          "rect": (128, 256, 3.0, 6.0, 0.8, 5)}.items():
+        if name == "c2":
+            w = WORKLOADS["c2_512_m4"]
+            eta, psi = jonswap_state(nx, ny, Lx, Ly, h, 9.81, w["kp"], w["steepness"], w["seed"])
+            dt = w["dt"]
+        else:
+            kmax = math.hypot(math.pi * nx / Lx, math.pi * ny / Ly)
+            eta, psi = random_band_fields(nx, ny, 77, min(nx, ny) // 2 - 1, amplitude=0.1 / kmax)
+            dt = 0.002
+        s = solver(torch, nx, ny, Lx, Ly, h, M)
+        print(" ", name, s.autotune(dt, reps=1), flush=True)
+        m = HOSModel(Grid(nx, ny, Lx, Ly, h), M)
+        e, p = dev(torch, eta), dev(torch, psi)
+        assert rel(host(s.dtn(e, p)), m.dtn(eta, psi)) < 1e-10
+        a, b = s.rhs(e, p)
+        a0, b0 = m.rhs(eta, psi)
+        assert rel(host(a), a0) < 1e-10 and rel(host(b), b0) < 1e-10
+        s.step(e, p, dt, 3)
+        e0, p0 = m.step(eta, psi, dt, 3)
+        assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
