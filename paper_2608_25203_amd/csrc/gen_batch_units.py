@@ -14,6 +14,15 @@ for kind in ("row", "col"):
                  f"const void *batch_{kind}_kernel<{real}>(int T, int E) {{"]
         for T, E in SHAPES:
             lines.append(f"  if (T == {T} && E == {E}) return reinterpret_cast<const void *>(&{kind}_kernel_batch<{real}, {T}, {E}>);")
-        lines += ["  return nullptr;", "}", "", "}  // namespace zk", ""]
+        lines += ["  return nullptr;", "}", "",
+                  "template <>",
+                  f"hipError_t launch_batch_{kind}<{real}>(int T, int E, dim3 grid, hipStream_t s, const {'RowArgs' if kind == 'row' else 'ColArgs'}<{real}> *args,",
+                  "                                   const BatchItem *items, PhysArgs ph) {"]
+        for T, E in SHAPES:
+            lines.append(f"  if (T == {T} && E == {E}) {{")
+            lines.append(f"    hipLaunchKernelGGL(({kind}_kernel_batch<{real}, {T}, {E}>), grid, dim3(256), 0, s, args, items, ph);")
+            lines.append("    return hipGetLastError();")
+            lines.append("  }")
+        lines += ["  return hipErrorInvalidValue;", "}", "", "}  // namespace zk", ""]
         with open(os.path.join(HERE, f"zk_batch_{kind}_{tag}.hip"), "w") as f:
             f.write("\n".join(lines))

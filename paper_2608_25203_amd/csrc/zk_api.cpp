@@ -258,14 +258,14 @@ int run_seq_t(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
       const bool row = l.kind == L_ROW_PAD || l.kind == L_ROW_BASE;
       const bool pad = l.kind == L_ROW_PAD || l.kind == L_COL_PAD;
       const TeamShape sh = ctx_team(c, row, pad);
-      const void *fn = row ? batch_row_kernel<real>(sh.T, sh.E) : batch_col_kernel<real>(sh.T, sh.E);
-      if (!fn) return fail(c, ZK_EINVAL, "team shape not built");
-      void *args = ws + (row ? c->off_rargs : c->off_cargs);
-      BatchItem *items = reinterpret_cast<BatchItem *>(ws + (row ? c->off_iprog : c->off_itask)) +
-                         (pad ? 0 : (row ? c->sched_cap[1] : c->sched_cap[4])) + l.first;
-      PhysArgs pa{ph.in0, ph.in1, ph.in2, ph.out0, ph.out1, 1};
-      void *params[] = {&args, &items, &pa};
-      e = hipLaunchKernel(fn, dim3(sh.blocks, l.count), dim3(256), params, 0, c->stream);
+      const BatchItem *items = reinterpret_cast<const BatchItem *>(ws + (row ? c->off_iprog : c->off_itask)) +
+                               (pad ? 0 : (row ? c->sched_cap[1] : c->sched_cap[4])) + l.first;
+      const PhysArgs pa{ph.in0, ph.in1, ph.in2, ph.out0, ph.out1, 1};
+      const dim3 grid(sh.blocks, l.count);
+      e = row ? launch_batch_row<real>(sh.T, sh.E, grid, c->stream,
+                                       reinterpret_cast<const RowArgs<real> *>(ws + c->off_rargs), items, pa)
+              : launch_batch_col<real>(sh.T, sh.E, grid, c->stream,
+                                       reinterpret_cast<const ColArgs<real> *>(ws + c->off_cargs), items, pa);
     } else {
       double *red = reinterpret_cast<double *>(ws + c->off_red);
       e = launch_parseval(base + (long long)l.first * c->base_stride, base + (long long)l.count * c->base_stride,

@@ -612,6 +612,21 @@ template <>
 const void *batch_col_kernel<double>(int T, int E);
 template <>
 const void *batch_col_kernel<float>(int T, int E);
+// Launch the kernel of shape (T, E) (hipErrorInvalidValue if not built).
+template <typename real>
+hipError_t launch_batch_row(int T, int E, dim3 grid, hipStream_t s, const RowArgs<real> *args, const BatchItem *items,
+                            PhysArgs ph);
+template <typename real>
+hipError_t launch_batch_col(int T, int E, dim3 grid, hipStream_t s, const ColArgs<real> *args, const BatchItem *items,
+                            PhysArgs ph);
+template <>
+hipError_t launch_batch_row<double>(int, int, dim3, hipStream_t, const RowArgs<double> *, const BatchItem *, PhysArgs);
+template <>
+hipError_t launch_batch_row<float>(int, int, dim3, hipStream_t, const RowArgs<float> *, const BatchItem *, PhysArgs);
+template <>
+hipError_t launch_batch_col<double>(int, int, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *, PhysArgs);
+template <>
+hipError_t launch_batch_col<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *, PhysArgs);
 
 // FP64 reductions over base spectra (zk_reduce.hip).  Writes
 //   out[0] = sum_k w(kx) Re(conj(a) b),  out[1] = sum_k w(kx) Re(conj(c) d)
