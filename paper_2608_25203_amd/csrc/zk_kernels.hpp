@@ -265,39 +265,60 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         // a power of two from its field maximum (published by the lifts that
         // wrote it) so that neither drowns in the rounding of the other, and
         // unscaled exactly afterwards.
-        float ma = 0.f, mb = 0.f;
-        {
-          const float *ca = a.colmax + (long long)op.fa * (S::KR * T);
-          const float *cb = a.colmax + (long long)(has_b ? op.fb : op.fa) * (S::KR * T);
-#pragma unroll
-          for (int q = 0; q < S::KR; ++q) {
-            ma = fmaxf(ma, ca[t + T * q]);
-            mb = fmaxf(mb, cb[t + T * q]);
-          }
-        }
-        const float2 mm = team_max2<T>(ma, mb, red);
-        const float2 pa = pow2_scale(mm.x);
-        const float2 pb = has_b ? pow2_scale(mm.y) : make_float2(1.f, 1.f);
-        const real sa = (real)pa.x, sb = (real)pb.x;
+        // Data loads first; the field maxima (one per column, published by
+        // the lifts) are reduced over all columns by each wavefront on its
+        // own, so no block barrier sits between the loads and their use.
+        cpx<real> zb[E];
 #pragma unroll
         for (int r = 0; r < E; ++r) {
-          cpx<real> za = {0, 0}, zb = {0, 0};
+          cpx<real> za = {0, 0};
+          zb[r] = {0, 0};
           const bool pos = r < S::KR;
           const bool neg = (r > S::NEG0) || (r == S::NEG0 && t > 0);
           if (pos || neg) {
             const int kk = pos ? (t + T * r) : ((E - r) * T - t);
             const int idx = mix_index<real>(kk, row, a.rows);
             za = Fa[idx];
-            if (has_b) zb = Fb[idx];
+            if (has_b) zb[r] = Fb[idx];
+          }
+          z[r] = za;
+        }
+        float ma = 0.f, mb = 0.f;
+        {
+          constexpr int NC = S::KR * T;  // nx / 2 columns
+          const float *ca = a.colmax + (long long)op.fa * NC;
+          const float *cb = a.colmax + (long long)(has_b ? op.fb : op.fa) * NC;
+          const int lane = threadIdx.x & 63;
+#pragma unroll
+          for (int c = lane; c < NC; c += 64) {
+            ma = fmaxf(ma, ca[c]);
+            mb = fmaxf(mb, cb[c]);
+          }
+#pragma unroll
+          for (int o = 32; o > 0; o >>= 1) {
+            ma = fmaxf(ma, __shfl_xor(ma, o, 64));
+            mb = fmaxf(mb, __shfl_xor(mb, o, 64));
+          }
+        }
+        const float2 pa = pow2_scale(ma);
+        const float2 pb = has_b ? pow2_scale(mb) : make_float2(1.f, 1.f);
+        const real sa = (real)pa.x, sb = (real)pb.x;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const bool pos = r < S::KR;
+          const bool neg = (r > S::NEG0) || (r == S::NEG0 && t > 0);
+          cpx<real> za = z[r], zbr = zb[r];
+          if (pos || neg) {
+            const int kk = pos ? (t + T * r) : ((E - r) * T - t);
             const real kxv = (real)(a.kx_scale * kk);
             if (dxa) za = {-kxv * za.y, kxv * za.x};
-            if (dxb) zb = {-kxv * zb.y, kxv * zb.x};
+            if (dxb) zbr = {-kxv * zbr.y, kxv * zbr.x};
             if (neg) {
               za.y = -za.y;
-              zb.y = -zb.y;
+              zbr.y = -zbr.y;
             }
           }
-          z[r] = {za.x * sa - zb.y * sb, za.y * sa + zb.x * sb};
+          z[r] = {za.x * sa - zbr.y * sb, za.y * sa + zbr.x * sb};
         }
         const cpx<real> *res = team_fft<real, N, E, NB, +1>(z, b0, b1, tw, t);
         const real ia = (real)pa.y, ib = (real)pb.y;
@@ -508,13 +529,31 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
     cpx<double> acc[QB];
 #pragma unroll
     for (int q = 0; q < QB; ++q) acc[q] = {0.0, 0.0};
+    // Base-spectrum terms: the next term's spectrum is loaded while the
+    // current one is accumulated (one global latency per term instead of two).
+    cpx<double> nxt[QB];
+    ColTerm ntm = out.nt > 0 ? a.terms[out.t0] : ColTerm{};
+    auto fetch = [&](const ColTerm &tm2) {
+      if (tm2.src >= 0) {
+        const cpx<double> *B = a.base + (long long)tm2.src * a.base_stride;
+#pragma unroll
+        for (int q = 0; q < QB; ++q) nxt[q] = B[base_index(col, t + T * q, ny)];
+      }
+    };
+    fetch(ntm);
     for (int i = 0; i < out.nt; ++i) {
-      const ColTerm tm = a.terms[out.t0 + i];
+      const ColTerm tm = ntm;
+      cpx<double> cur[QB];
+#pragma unroll
+      for (int q = 0; q < QB; ++q) cur[q] = nxt[q];
+      if (i + 1 < out.nt) {
+        ntm = a.terms[out.t0 + i + 1];
+        fetch(ntm);
+      }
       if (tm.src >= 0) {
-        const cpx<double> *B = a.base + (long long)tm.src * a.base_stride;
 #pragma unroll
         for (int q = 0; q < QB; ++q) {
-          const cpx<double> s0 = B[base_index(col, t + T * q, ny)];
+          const cpx<double> s0 = cur[q];
           cpx<double> sv = sym(tm.sym, q);
           sv = {sv.x * tm.coef, sv.y * tm.coef};
           acc[q].x += s0.x * sv.x - s0.y * sv.y;
