@@ -416,3 +416,59 @@ def test_p12_translation_and_reflection_equivariance(M):
 
     a3, b3 = m.rhs(refl(eta), refl(psi))
     assert rel(a3, refl(a)) < 1e-13 and rel(b3, refl(b)) < 1e-13
+
+
+# ---- exact-linear Adams-Bashforth 2 (Sec. 3.4) ----------------------------------------
+def test_if_propagator_equals_matrix_exponential():
+    """One IF step with a forcing held constant is the exact solution of
+    d/dt (eta, psi) = L (eta, psi) + F over dt: per mode, the matrix
+    exponential of the augmented system [[0, G0, Fe], [-g, 0, Fp], [0, 0, 0]]
+    (scipy.linalg.expm), the k = 0 mode included."""
+    from scipy.linalg import expm
+
+    nx, ny, Lx, Ly, h, dt = 8, 4, 2.0, 1.0, 0.3, 0.37
+    m = HOSModel(Grid(nx, ny, Lx, Ly, h), 3)
+    g = m.gr
+    rng = np.random.default_rng(3)
+    e, p, fe, fp = (rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx)) for _ in range(4))
+    e1, p1 = m.if_propagate(e, p, fe, fp, dt)
+    G0 = g.G0
+    for iy in range(ny):
+        for ix in range(nx):
+            A = np.array([[0, G0[iy, ix], fe[iy, ix]], [-g.g, 0, fp[iy, ix]], [0, 0, 0]], dtype=complex)
+            y = expm(A * dt) @ np.array([e[iy, ix], p[iy, ix], 1.0])
+            assert abs(y[0] - e1[iy, ix]) < 1e-13 * max(1, abs(y[0]))
+            assert abs(y[1] - p1[iy, ix]) < 1e-13 * max(1, abs(y[1]))
+
+
+def test_ifab2_linear_waves_exact_for_any_dt():
+    """eps = 0 (no forcing) and no filter: IF-AB2 is the exact rotation of
+    eq:lin_prop, so 40 steps far beyond the RK4 stability limit equal one
+    rotation by the total time."""
+    n, L = 32, TWO_PI
+    eta, psi = random_band_fields(n, n, 5, 12, amplitude=0.1)
+    m = HOSModel(Grid(n, n, L, L, None), 4, eps=0.0, filt=False)
+    dt = 3.0 / np.sqrt(9.81 * np.pi * n / L)  # omega(kNyq) dt = 3
+    e1, p1 = m.step_ifab2(eta, psi, dt, 40)
+    g = m.gr
+    c, a, b, s, u, v = m.if_coefficients(40 * dt)
+    eh, ph = g.spec(eta), g.spec(psi)
+    assert np.max(np.abs(e1 - g.phys(c * eh + a * ph))) < 1e-12
+    assert np.max(np.abs(p1 - g.phys(-b * eh + c * ph))) < 1e-12
+
+
+def test_ifab2_is_second_order():
+    """Global error against a fine-step reference falls by ~4 per halving of
+    dt (the first step is IF-Euler, whose O(dt^2) local error keeps the
+    scheme second order)."""
+    n, L = 32, TWO_PI
+    eta, psi = jonswap_state(n, n, L, L, None, 9.81, 3.0, 0.08, 4)
+    m = HOSModel(Grid(n, n, L, L, None), 3, filt=False)
+    T = 0.4
+    ref = m.step(eta, psi, T / 400, 400)[0]
+    errs = []
+    for k in (10, 20, 40):
+        e1 = m.step_ifab2(eta, psi, T / k, k)[0]
+        errs.append(np.max(np.abs(e1 - ref)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.2 < r1 < 5.0 and 3.2 < r2 < 5.0, errs
