@@ -65,10 +65,28 @@ enum {
     ZK_OPT_CHECK = 5,     /* 1: zk_step checks the result for NaN/Inf, which
                              synchronises the stream (default); 0: no check,
                              zk_step stays fully asynchronous                 */
+    ZK_OPT_INTEGRATOR = 7,/* ZK_INTEGRATOR_RK4 (default) or ZK_INTEGRATOR_IFAB2;
+                             changes the workspace size: set it before zk_bind */
     ZK_OPT_PROFILE = 6    /* 1: bracket every kernel launch with HIP events on
                              the bound stream and accumulate per-kind times for
                              zk_kernel_stats (adds event records between
                              launches); 0: off (default)                      */
+};
+
+/* Integrators of zk_step (ZK_OPT_INTEGRATOR). */
+enum {
+    ZK_INTEGRATOR_RK4 = 0,   /* classical RK4: four right-hand sides per step  */
+    ZK_INTEGRATOR_IFAB2 = 1  /* the paper's exact-linear Adams-Bashforth 2
+                                (Sec. 3.4, eq:split, eq:lin_prop, eq:if_ab2_eta,
+                                eq:if_ab2_psi): the linear part L = [[0, G0],
+                                [-g, 0]] is integrated exactly per mode, the
+                                forcing F = (G^[M] psi - G0 psi, N) enters
+                                through its constant-forcing response with the
+                                extrapolation F* = 3/2 F_n - 1/2 F_{n-1}; one
+                                right-hand side per step.  The first step of
+                                every zk_step call is the integrating-factor
+                                Euler bootstrap F* = F_0 (no history is kept
+                                across calls). */
 };
 
 /* Kernel kinds reported by zk_kernel_stats. */
@@ -114,8 +132,9 @@ int zk_dtn(zk_ctx *ctx, const double *eta, const double *psi, double *G_psi);
  *   W = (G^[M] psi + eps grad eta . grad psi) / (1 + eps^2 |grad eta|^2). */
 int zk_rhs(zk_ctx *ctx, const double *eta, const double *psi, double *eta_t, double *psi_t);
 
-/* Advance (eta, psi) in place by nsteps classical RK4 steps of size dt, each
- * followed by the state filter A(k) when ZK_OPT_FILTER is on (Sec. 3.4,
+/* Advance (eta, psi) in place by nsteps steps of size dt of the selected
+ * integrator (classical RK4 by default, ZK_OPT_INTEGRATOR), each followed by
+ * the state filter A(k) when ZK_OPT_FILTER is on (Sec. 3.4,
  * eq:state_filter).  The state is kept spectral inside the call and
  * transformed in and out once.  Returns ZK_EDIVERGED if the result holds a
  * NaN or Inf (that check synchronises the stream). */

@@ -100,6 +100,11 @@ void compute_layout(zk_ctx *c) {
   off = align_up(off + 2 * c->sched_cap[1] * sizeof(BatchItem));
   c->off_itask = off;  // items {pad 0 | base 1, task}
   off = align_up(off + 2 * c->sched_cap[4] * sizeof(BatchItem));
+  c->off_ifsym = 0;
+  if (c->integrator == ZK_INTEGRATOR_IFAB2) {
+    c->off_ifsym = off;
+    off = align_up(off + (size_t)(nx / 2) * ny * kIfCoefs * sizeof(double));
+  }
   c->off_red = off;
   off = align_up(off + (2 * kRedBlocks + 8) * sizeof(double));
   c->off_cmax = off;
@@ -234,6 +239,43 @@ int upload(zk_ctx *c, double dt) {
     HIP_TRY(c, put(c->off_itask, it.data(), it.size() * sizeof(BatchItem)));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
+  if (c->integrator == ZK_INTEGRATOR_IFAB2 && !std::isnan(dt) && (c->dirty || !(dt == c->ifsym_dt))) {
+    // exact linear flow and its constant-forcing response over dt per band
+    // element (Sec. 3.4), omega^2 = g G0, in long double; k = 0 limits
+    const int nx = c->pp.nx, ny = c->pp.ny;
+    const long double pi = 3.14159265358979323846264338327950288L;
+    const long double kxs = 2 * pi / c->pp.Lx, kys = 2 * pi / c->pp.Ly, g = c->pp.g, h = dt;
+    std::vector<double> tab((size_t)(nx / 2) * ny * kIfCoefs);
+    for (int col = 0; col < nx / 2; ++col)
+      for (int b = 0; b < ny; ++b) {
+        const int my = b < ny / 2 ? b : b - ny;
+        const long double kx = kxs * col, ky = kys * my, kk = sqrtl(kx * kx + ky * ky);
+        const long double G0 = c->pp.depth > 0 ? kk * tanhl(kk * c->pp.depth) : kk;
+        const long double om = sqrtl(g * G0);
+        long double v[kIfCoefs];
+        if (om == 0) {
+          v[0] = 1;
+          v[1] = 0;
+          v[2] = g * h;
+          v[3] = h;
+          v[4] = 0;
+          v[5] = 0.5L * g * h * h;
+        } else {
+          const long double cs = cosl(om * h), sn = sinl(om * h);
+          v[0] = cs;
+          v[1] = G0 * sn / om;
+          v[2] = g * sn / om;
+          v[3] = sn / om;
+          v[4] = (1 - cs) / g;
+          v[5] = (1 - cs) / G0;
+        }
+        const size_t e = ((size_t)(col / CBB) * ny + b) * CBB + col % CBB;
+        for (int k = 0; k < kIfCoefs; ++k) tab[e * kIfCoefs + k] = (double)v[k];
+      }
+    HIP_TRY(c, put(c->off_ifsym, tab.data(), tab.size() * sizeof(double)));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->ifsym_dt = dt;
+  }
   HIP_TRY(c, hipStreamSynchronize(c->stream));  // host vectors may change after return
   c->plan_dt = dt;
   c->have_plan = true;
@@ -364,6 +406,7 @@ ColArgs<real> ctx_col_args(const zk_ctx *c, bool pad, int task0) {
   a.sym = reinterpret_cast<const SymEl *>(ws + c->off_sym);
   a.filt_x = reinterpret_cast<const double *>(ws + c->off_fx);
   a.filt_y = reinterpret_cast<const double *>(ws + c->off_fy);
+  a.ifsym = c->off_ifsym ? reinterpret_cast<const double *>(ws + c->off_ifsym) : nullptr;
   return a;
 }
 
@@ -440,6 +483,12 @@ int zk_set_option(zk_ctx *c, int key, double v) {
     case ZK_OPT_PROFILE:
       c->prof = v != 0.0;
       return ZK_OK;
+    case ZK_OPT_INTEGRATOR:
+      if (v != ZK_INTEGRATOR_RK4 && v != ZK_INTEGRATOR_IFAB2) return fail(c, ZK_EINVAL, "unknown integrator");
+      if (c->bound && (int)v != c->integrator) return fail(c, ZK_EINVAL, "set the integrator before zk_bind");
+      c->integrator = (int)v;
+      compute_layout(c);
+      break;
     default:
       return fail(c, ZK_EINVAL, "unknown option");
   }
@@ -510,9 +559,11 @@ int zk_step(zk_ctx *c, double *eta, double *psi, double dt, int nsteps) {
   ph.out1 = psi;
   const Plan &p = c->plan;
   if ((rc = run_seq(c, p.step_entry, ph))) return rc;
+  const bool ab2 = c->integrator == ZK_INTEGRATOR_IFAB2;
   for (int i = 0; i < nsteps; ++i) {
     const int par = i & 1;
-    if ((rc = run_seq(c, p.step_body[par], ph))) return rc;
+    const std::vector<Launch> &body = ab2 ? (i == 0 ? p.ab2_first[par] : p.ab2_body[par]) : p.step_body[par];
+    if ((rc = run_seq(c, body, ph))) return rc;
     if (i + 1 < nsteps && (rc = run_seq(c, p.step_lift[1 - par], ph))) return rc;
   }
   const int fin = nsteps & 1;

@@ -32,6 +32,9 @@ struct zk_ctx {
   size_t off_tw[4] = {0, 0, 0, 0};  // row pad, row base, col pad, col base
   size_t off_ops = 0, off_progs = 0, off_terms = 0, off_outs = 0, off_tasks = 0;
   size_t off_rargs = 0, off_cargs = 0, off_iprog = 0, off_itask = 0;
+  int integrator = 0;     // ZK_INTEGRATOR_RK4 or ZK_INTEGRATOR_IFAB2
+  size_t off_ifsym = 0;   // IF-AB2 coefficient table (0 when unused)
+  double ifsym_dt = NAN;  // dt the table holds
   int tuneT[2][2] = {{0, 0}, {0, 0}};  // [row][pad] autotuned threads per transform (0: default)
   size_t off_red = 0, off_cmax = 0, off_sym = 0, off_fx = 0, off_fy = 0, off_base = 0, off_mix = 0, total = 0;
   long long base_stride = 0, mix_stride = 0;

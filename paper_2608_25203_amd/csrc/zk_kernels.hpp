@@ -65,6 +65,7 @@ struct ColArgs {
   float *colmax;  // [mixed field][nx/2]: max |value| of each lifted column
   const SymEl *sym;               // symbol table, base-spectrum layout
   const double *filt_x, *filt_y;  // separable state filter factors
+  const double *ifsym;            // kIfCoefs per band element (base layout), or null
 };
 
 // ---- register-set dispatch (keeps every register array statically indexed)
@@ -456,6 +457,7 @@ __device__ __forceinline__ cpx<double> symval(uint32_t s, double kk, double g0, 
   }
   if (s & SYM_FILT) f *= a.filt_x[col] * a.filt_y[b];
   if ((s & SYM_TAPER) && a.taper_on) f *= tp;
+  if (s & SYM_IF) f *= a.ifsym[(long long)base_index(col, b, a.ny) * kIfCoefs + ((s >> SYM_IF_SHIFT) & 7)];
   if (s & SYM_IKY) return {0.0, f * ky};
   return {f, 0.0};
 }

@@ -242,6 +242,11 @@ Plan build_plan(const PlanParams &pp, double dt) {
     bSP[i] = B.base();
   }
   const int bAE = B.base(), bAP = B.base(), bG = B.base(), bPT = B.base();
+  int bFe[2], bFp[2];  // IF-AB2 forcing of the last two steps
+  for (int i = 0; i < 2; ++i) {
+    bFe[i] = B.base();
+    bFp[i] = B.base();
+  }
   int bPHI[kMaxM + 2], bWP[kMaxM + 2], bGX[kMaxM + 2];
   for (int r = 1; r <= M - 1; ++r) {
     bPHI[r] = B.base();
@@ -507,6 +512,36 @@ Plan build_plan(const PlanParams &pp, double dt) {
     P.chk_p[par] = bUP[par];
   }
 
+  // ---- IF-AB2: F = (G^[M] psi - G0 psi, N); U <- A [E(dt) U + D(dt) F*] ----------
+  {
+    auto ifs = [&](int k) { return (uint32_t)(SYM_IF | (k << SYM_IF_SHIFT)) | FILT; };
+    enum { IC = 0, IA = 1, IB = 2, IS = 3, IU = 4, IV = 5 };
+    for (int first = 1; first >= 0; --first)
+      for (int par = 0; par < 2; ++par) {
+        auto &seq = first ? P.ab2_first[par] : P.ab2_body[par];
+        const int e = bUE[par], p = bUP[par];
+        core(seq, e, p, true);
+        seq.push_back(row_launch(L_ROW_PAD, {bern_prog}));
+        TaskSpec t = B.fold_task(mN);  // X = N (folded Bernoulli term)
+        t.outs.push_back(B.store(bFe[par], {{bG, 0, 1.0}, {p, 1u, -1.0}}));
+        t.outs.push_back(B.store(bFp[par], {{-1, 0, 1.0}}));
+        const double w = first ? 1.0 : 1.5;  // F* = 3/2 F_n - 1/2 F_{n-1} (F_0 at the bootstrap)
+        std::vector<TermSpec> te{{e, ifs(IC), 1.0}, {p, ifs(IA), 1.0},  {bG, ifs(IS), w},
+                                 {p, ifs(IS) | 1u, -w}, {-1, ifs(IU), w}};
+        std::vector<TermSpec> tp{{e, ifs(IB), -1.0}, {p, ifs(IC), 1.0}, {bG, ifs(IV), -w},
+                                 {p, ifs(IV) | 1u, w},   {-1, ifs(IS), w}};
+        if (!first) {
+          te.push_back({bFe[1 - par], ifs(IS), -0.5});
+          te.push_back({bFp[1 - par], ifs(IU), -0.5});
+          tp.push_back({bFe[1 - par], ifs(IV), 0.5});
+          tp.push_back({bFp[1 - par], ifs(IS), -0.5});
+        }
+        t.outs.push_back(B.store(bUE[1 - par], te));
+        t.outs.push_back(B.store(bUP[1 - par], tp));
+        seq.push_back(B.col_launch(L_COL_PAD, {t}));
+      }
+  }
+
   // ---- stepping with an external DtN --------------------------------------------
   // rhs_g: the RHS of (eta, psi) with G supplied on the grid; G is projected
   // onto the band by its entry transform, eta_t = P_B G.
@@ -603,7 +638,8 @@ Plan build_plan(const PlanParams &pp, double dt) {
       }
     };
     for (auto *seq : {&P.dtn, &P.rhs, &P.ham, &P.step_entry, &P.step_body[0], &P.step_body[1], &P.step_lift[0],
-                      &P.step_lift[1], &P.step_exit[0], &P.step_exit[1], &P.rhs_g, &P.filter})
+                      &P.step_lift[1], &P.step_exit[0], &P.step_exit[1], &P.rhs_g, &P.filter, &P.ab2_first[0],
+                      &P.ab2_first[1], &P.ab2_body[0], &P.ab2_body[1]})
       annotate(*seq);
   }
   return P;
@@ -682,7 +718,8 @@ std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
     return "";
   };
   for (auto *seq : {&p.dtn, &p.rhs, &p.ham, &p.step_entry, &p.step_body[0], &p.step_body[1], &p.step_lift[0],
-                    &p.step_lift[1], &p.step_exit[0], &p.step_exit[1], &p.rhs_g, &p.filter}) {
+                    &p.step_lift[1], &p.step_exit[0], &p.step_exit[1], &p.rhs_g, &p.filter, &p.ab2_first[0],
+                    &p.ab2_first[1], &p.ab2_body[0], &p.ab2_body[1]}) {
     std::string e = chk(*seq);
     if (!e.empty()) return e;
   }

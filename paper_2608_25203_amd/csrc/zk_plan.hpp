@@ -57,6 +57,10 @@ struct Plan {
   std::vector<Launch> step_exit[2];   // U[p] -> physical
   int chk_e[2], chk_p[2];             // base ids of U[p] (finite check)
   // Pieces for stepping with an externally supplied DtN (learned closure):
+  // Exact-linear Adams-Bashforth 2 (Sec. 3.4): one RHS per step, state U[p] -> U[1-p],
+  // forcing F_n stored in F[p]; the first step of a call is the IF-Euler bootstrap.
+  std::vector<Launch> ab2_first[2];
+  std::vector<Launch> ab2_body[2];
   std::vector<Launch> rhs_g;   // eta, psi, G (LDP slots 0, 1, 2) -> eta_t = P_B G, psi_t
   std::vector<Launch> filter;  // eta, psi -> A eta, A psi (the state filter alone)
 };

@@ -76,7 +76,11 @@ int main(int argc, char **argv) {
   dump_seq("step_exit0", p.step_exit[0], false);
   dump_seq("step_exit1", p.step_exit[1], false);
   dump_seq("rhs_g", p.rhs_g, false);
-  dump_seq("filter", p.filter, true);
+  dump_seq("filter", p.filter, false);
+  dump_seq("ab2_first0", p.ab2_first[0], false);
+  dump_seq("ab2_first1", p.ab2_first[1], false);
+  dump_seq("ab2_body0", p.ab2_body[0], false);
+  dump_seq("ab2_body1", p.ab2_body[1], true);
   std::printf("}\n");
   return 0;
 }

@@ -54,8 +54,14 @@ enum SymBits : uint32_t {
   SYM_LMASK = 0xF,   // L_l(k) = |k|^l (tanh(|k| d) if l odd), l = bits & 0xF
   SYM_IKY = 0x10,    // i * ky
   SYM_FILT = 0x20,   // state filter A(k)
-  SYM_TAPER = 0x40   // taper exp(-(|k|/kc)^8) (only if the taper option is on)
+  SYM_TAPER = 0x40,  // taper exp(-(|k|/kc)^8) (only if the taper option is on)
+  SYM_IF = 0x80      // coefficient (bits >> SYM_IF_SHIFT) & 7 of the exact linear flow
+                     // and its constant-forcing response (Sec. 3.4, eq:lin_prop,
+                     // eq:if_ab2_eta, eq:if_ab2_psi): 0 cos(w dt), 1 G0 sin(w dt)/w,
+                     // 2 g sin(w dt)/w, 3 sin(w dt)/w, 4 (1-cos(w dt))/g, 5 (1-cos(w dt))/G0
 };
+constexpr int SYM_IF_SHIFT = 8;
+constexpr int kIfCoefs = 6;
 
 struct ColTerm {
   int32_t src;   // base-spectrum id, or -1 = result of the task's forward FFT

@@ -14,6 +14,8 @@ LIB_PATH = os.path.join(HERE, "libzk.so")
 
 ZK_OK, ZK_EINVAL, ZK_ENOWS, ZK_EDEVICE, ZK_EDIVERGED = 0, -1, -2, -3, -4
 ZK_OPT_EPS, ZK_OPT_TAPER, ZK_OPT_FILTER, ZK_OPT_PRECISION, ZK_OPT_CHECK, ZK_OPT_PROFILE = 1, 2, 3, 4, 5, 6
+ZK_OPT_INTEGRATOR = 7
+ZK_INTEGRATOR_RK4, ZK_INTEGRATOR_IFAB2 = 0, 1
 ZK_KERNEL_ROW_PAD, ZK_KERNEL_ROW_BASE, ZK_KERNEL_COL_PAD, ZK_KERNEL_COL_BASE, ZK_KERNEL_REDUCE = 0, 1, 2, 3, 4
 KERNEL_NAMES = {0: "row_pad", 1: "row_base", 2: "col_pad", 3: "col_base", 4: "reduce"}
 
@@ -204,7 +206,7 @@ class Solver:
     Fields are float64 CUDA tensors of shape (ny, nx), contiguous."""
 
     def __init__(self, nx, ny, Lx, Ly, depth, g, M, eps=1.0, taper=True, filt=True, precision=64,
-                 check=True, device="cuda"):
+                 check=True, device="cuda", integrator="rk4"):
         import torch
 
         self.torch = torch
@@ -212,6 +214,7 @@ class Solver:
         self.device = torch.device(device)
         self.ctx = zk_create(nx, ny, Lx, Ly, depth, g, M)
         zk_set_option(self.ctx, ZK_OPT_PRECISION, precision)
+        zk_set_option(self.ctx, ZK_OPT_INTEGRATOR, {"rk4": ZK_INTEGRATOR_RK4, "ifab2": ZK_INTEGRATOR_IFAB2}[integrator])
         zk_set_option(self.ctx, ZK_OPT_EPS, eps)
         zk_set_option(self.ctx, ZK_OPT_TAPER, 1.0 if taper else 0.0)
         zk_set_option(self.ctx, ZK_OPT_FILTER, 1.0 if filt else 0.0)

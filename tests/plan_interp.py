@@ -19,7 +19,7 @@ EXE = os.path.join(ROOT, "_build", "zk_plan_check")
 
 OP_LD2, OP_LDP, OP_MOV, OP_MAC, OP_ZERO, OP_BERN, OP_ST2, OP_STP = range(1, 9)
 RS_NONE = 255
-SYM_IKY, SYM_FILT, SYM_TAPER = 0x10, 0x20, 0x40
+SYM_IKY, SYM_FILT, SYM_TAPER, SYM_IF = 0x10, 0x20, 0x40, 0x80
 L_ROW_PAD, L_ROW_BASE, L_COL_PAD, L_COL_BASE, L_PARSEVAL = range(5)
 
 
@@ -90,9 +90,23 @@ class Interp:
             f = f * self.filt_sym
         if (s & SYM_TAPER) and self.taper:
             f = f * self.taper_sym
+        if s & SYM_IF:
+            f = f * self._ifcoef()[(s >> 8) & 7]
         if s & SYM_IKY:
             return 1j * self.ky * f
         return f.astype(complex)
+
+    def _ifcoef(self):
+        """Exact linear flow and constant-forcing response over self.dt per
+        mode, omega^2 = g G0 (k = 0: the limits)."""
+        dt, g = self.dt, self.g
+        G0 = self.kk * self.th
+        om = np.sqrt(g * G0)
+        z = om == 0
+        o = np.where(z, 1.0, om)
+        c, sn = np.cos(om * dt), np.sin(om * dt)
+        return [c, np.where(z, 0.0, G0 * sn / o), np.where(z, g * dt, g * sn / o), np.where(z, dt, sn / o),
+                (1 - c) / g, np.where(z, 0.5 * g * dt * dt, (1 - c) / np.where(z, 1.0, G0))]
 
     # ---- row pass ----------------------------------------------------------------
     def row(self, launch, phys):
@@ -238,6 +252,18 @@ class Interp:
         P = self._plan(self.dt if self.dt is not None else 1.0)
         phys = [eta, psi, np.zeros_like(eta), np.zeros_like(eta)]
         self.run(P["filter"], phys)
+        return phys[2], phys[3]
+
+    def step_ab2(self, eta, psi, dt, nsteps):
+        P = self._plan(dt)
+        phys = [eta, psi, np.zeros_like(eta), np.zeros_like(eta)]
+        self.run(P["step_entry"], phys)
+        for i in range(nsteps):
+            par = i & 1
+            self.run(P[("ab2_first%d" if i == 0 else "ab2_body%d") % par], phys)
+            if i + 1 < nsteps:
+                self.run(P["step_lift%d" % (1 - par)], phys)
+        self.run(P["step_exit%d" % (nsteps & 1)], phys)
         return phys[2], phys[3]
 
     def step(self, eta, psi, dt, nsteps):

@@ -216,3 +216,47 @@ def test_autotuned_shapes_keep_parity(torch):
         s.step(e, p, dt, 3)
         e0, p0 = m.step(eta, psi, dt, 3)
         assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
+
+
+@pytest.mark.parametrize("M,filt,eps", [(3, True, 1.0), (4, False, 0.6), (5, True, 1.0)])
+def test_ifab2_parity(torch, M, filt, eps):
+    """The paper's exact-linear Adams-Bashforth 2 (Sec. 3.4) against the
+    oracle's step_ifab2: 20 steps in one call (bootstrap + 19 AB2 steps),
+    then 3 + 4 steps in two calls (each call bootstraps), FP64 bar."""
+    n, L = 64, TWO_PI
+    eta, psi = jonswap_state(n, n, L, L, 1.5, 9.81, 4.0, 0.08, 11)
+    s = solver(torch, n, n, L, L, 1.5, M, eps=eps, filt=filt, integrator="ifab2")
+    m = HOSModel(Grid(n, n, L, L, 1.5), M, eps=eps, filt=filt)
+    e, p = dev(torch, eta), dev(torch, psi)
+    s.step(e, p, 0.01, 20)
+    e0, p0 = m.step_ifab2(eta, psi, 0.01, 20)
+    assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
+    e, p = dev(torch, eta), dev(torch, psi)
+    s.step(e, p, 0.01, 3)
+    s.step(e, p, 0.01, 4)
+    e0, p0 = m.step_ifab2(*m.step_ifab2(eta, psi, 0.01, 3), 0.01, 4)
+    assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
+
+
+def test_ifab2_c2_shape_and_linear_exactness(torch):
+    """512 x 512, M = 4, dt = 0.05 s: 5 IF-AB2 steps against the oracle; and
+    with eps = 0, no filter, steps 10x beyond the RK4 limit stay the exact
+    rotation (eq:lin_prop)."""
+    w = WORKLOADS["c2_512_m4"]
+    eta, psi = jonswap_state(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"], w["kp"], w["steepness"], w["seed"])
+    s = solver(torch, w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["M"], integrator="ifab2")
+    m = HOSModel(Grid(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"]), w["M"])
+    e, p = dev(torch, eta), dev(torch, psi)
+    s.step(e, p, w["dt"], 5)
+    e0, p0 = m.step_ifab2(eta, psi, w["dt"], 5)
+    assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
+    s0 = solver(torch, 128, 128, 50.0, 50.0, 5.0, 4, eps=0.0, filt=False, integrator="ifab2")
+    m0 = HOSModel(Grid(128, 128, 50.0, 50.0, 5.0), 4, eps=0.0, filt=False)
+    et, pt = jonswap_state(128, 128, 50.0, 50.0, 5.0, 9.81, 1.0, 0.05, 12)
+    dt = 2.0  # omega(kNyq) dt ~ 18
+    e, p = dev(torch, et), dev(torch, pt)
+    s0.step(e, p, dt, 30)
+    g = m0.gr
+    c, a, b, _, _, _ = m0.if_coefficients(30 * dt)
+    eh, ph = g.spec(et), g.spec(pt)
+    assert rel(host(e), g.phys(c * eh + a * ph)) < 1e-11 and rel(host(p), g.phys(-b * eh + c * ph)) < 1e-11

@@ -87,6 +87,20 @@ def test_closure_pieces_match_oracle(M):
     assert rel(fa, g.phys(eh * g.filt)) < 1e-13 and rel(fb, g.phys(ph * g.filt)) < 1e-13
 
 
+@pytest.mark.parametrize("M,filt", [(1, True), (3, True), (4, False)])
+def test_ab2_schedule_matches_oracle(M, filt):
+    """The IF-AB2 schedules (bootstrap step, AB2 steps, ping-pong forcing),
+    executed literally, give the oracle's step_ifab2 (Sec. 3.4)."""
+    nx, ny = 32, 16
+    eta, psi = random_band_fields(nx, ny, 9, 7, amplitude=0.02)
+    I = Interp(nx, ny, 3.0, 2.0, 1.5, 9.81, M, filt=filt)
+    m = HOSModel(Grid(nx, ny, 3.0, 2.0, 1.5), M, filt=filt)
+    for n in (1, 2, 5):
+        s, t = I.step_ab2(eta, psi, 0.02, n)
+        s0, t0 = m.step_ifab2(eta, psi, 0.02, n)
+        assert rel(s, s0) < 1e-13 and rel(t, t0) < 1e-13
+
+
 # ---------------------------------------------------------------- the library
 LIB = os.path.join(ROOT, "paper_2608_25203_amd", "libzk.so")
 
