@@ -420,6 +420,52 @@ class HOSModel:
         return self.hamiltonian_spec(g.spec(eta), g.spec(psi))
 
 
+# ---- reflecting walls by even extension (Sec. "Boundary conditions via even extension") ----
+def even_extend(f):
+    """Mirror an (ny, nx) field across each wall of the rectangle onto the
+    doubled (2 ny, 2 nx) periodic grid (eq:even_ext).  Reading: samples are
+    cell centred, so the reflection is half-sample symmetric,
+    f~(2n - 1 - i) = f(i), which makes every odd derivative vanish on the
+    walls (the Neumann condition)."""
+    f = np.asarray(f, dtype=float)
+    g = np.concatenate([f, f[::-1, :]], axis=0)
+    return np.concatenate([g, g[:, ::-1]], axis=1)
+
+
+def crop(f):
+    """The physical quarter of a doubled field."""
+    ny, nx = f.shape
+    return np.array(f[: ny // 2, : nx // 2])
+
+
+class ReflectingModel:
+    """A tank of nx x ny cells of size Lx x Ly with reflecting walls: the
+    periodic model on the doubled grid applied to the even extension, the
+    result cropped back.  The Hamiltonian of the tank is a quarter of the
+    doubled domain's."""
+
+    def __init__(self, nx, ny, Lx, Ly, depth, M, g=9.81, **kw):
+        self.m = HOSModel(Grid(2 * nx, 2 * ny, 2 * Lx, 2 * Ly, depth, g=g), M, **kw)
+
+    def dtn(self, eta, psi):
+        return crop(self.m.dtn(even_extend(eta), even_extend(psi)))
+
+    def rhs(self, eta, psi):
+        a, b = self.m.rhs(even_extend(eta), even_extend(psi))
+        return crop(a), crop(b)
+
+    def step(self, eta, psi, dt, nsteps=1):
+        a, b = self.m.step(even_extend(eta), even_extend(psi), dt, nsteps)
+        return crop(a), crop(b)
+
+    def step_ifab2(self, eta, psi, dt, nsteps=1):
+        a, b = self.m.step_ifab2(even_extend(eta), even_extend(psi), dt, nsteps)
+        return crop(a), crop(b)
+
+    def hamiltonian(self, eta, psi):
+        return 0.25 * self.m.hamiltonian(even_extend(eta), even_extend(psi))
+
+
 def truncated_convolution(grid, A, B, taper=True):
     """Brute-force definition of the dealiased product on tiny grids:
     T(k) * sum_{p, q in B, p + q = k} A(p) B(q) / N for k in B (an exact

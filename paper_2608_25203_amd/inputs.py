@@ -130,6 +130,18 @@ def workload_state(name, **over):
     return w, eta, psi
 
 
+def tank_bump(nx, ny, Lx, Ly, A, sigma=1.0, R=6.0):
+    """The wave-propagation tank's initial state: a Gaussian bump
+    A exp(-r^2 / (2 sigma^2)) for r < R (zero outside), r measured from the
+    tank centre, on cell-centred samples ((i + 1/2) Lx / nx, ...); the
+    surface at rest, psi = 0.  float64 arrays [ny][nx]."""
+    x = (np.arange(nx) + 0.5) * Lx / nx - 0.5 * Lx
+    y = (np.arange(ny) + 0.5) * Ly / ny - 0.5 * Ly
+    r2 = x[None, :] ** 2 + y[:, None] ** 2
+    eta = np.where(r2 < R * R, A * np.exp(-r2 / (2.0 * sigma * sigma)), 0.0)
+    return eta, np.zeros_like(eta)
+
+
 def cnn_init_params(seed, channels=(3, 32, 32, 32, 1)):
     """Seeded initial weights of the closure network: for each layer a
     (C_out, C_in, 3, 3) weight drawn N(0, 2 / (9 C_in)) (He) and a zero bias

@@ -472,3 +472,48 @@ def test_ifab2_is_second_order():
         errs.append(np.max(np.abs(e1 - ref)))
     r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
     assert 3.2 < r1 < 5.0 and 3.2 < r2 < 5.0, errs
+
+
+# ---- reflecting walls (even extension) ---------------------------------------------------
+def test_reflecting_tank_standing_wave_closed_form():
+    """Linear sloshing (eps = 0, no filter): the tank mode
+    cos(m pi x / Lx) cos(n pi y / Ly) on cell centres oscillates at
+    omega = sqrt(g k tanh(k d)), k = pi sqrt((m/Lx)^2 + (n/Ly)^2): after 25
+    IF-AB2 steps eta = cos(omega t) times the mode, psi = -(g/omega) sin(omega t)
+    times it (textbook standing wave)."""
+    from oracle.hos import ReflectingModel
+
+    nx, ny, Lx, Ly, d, g = 24, 16, 3.0, 2.0, 0.4, 9.81
+    x = (np.arange(nx) + 0.5) * Lx / nx
+    y = (np.arange(ny) + 0.5) * Ly / ny
+    m, n = 3, 2
+    mode = np.cos(m * np.pi * x / Lx)[None, :] * np.cos(n * np.pi * y / Ly)[:, None]
+    k = np.pi * np.hypot(m / Lx, n / Ly)
+    om = np.sqrt(g * k * np.tanh(k * d))
+    rm = ReflectingModel(nx, ny, Lx, Ly, d, 3, eps=0.0, filt=False)
+    dt, N = 0.013, 25
+    e, p = rm.step_ifab2(0.01 * mode, np.zeros_like(mode), dt, N)
+    t = N * dt
+    assert np.max(np.abs(e - 0.01 * np.cos(om * t) * mode)) < 1e-13
+    assert np.max(np.abs(p + 0.01 * g / om * np.sin(om * t) * mode)) < 1e-13
+
+
+def test_reflecting_extension_symmetry_and_walls():
+    """A nonlinear step keeps the doubled state mirror-symmetric (the
+    dynamics commute with the reflection), the spectral normal derivative
+    vanishes on the walls, and the tank's mean elevation is conserved."""
+    from oracle.hos import ReflectingModel, crop, even_extend
+    from paper_2608_25203_amd.inputs import tank_bump
+
+    nx, ny, L = 32, 32, 20.0
+    eta, psi = tank_bump(nx, ny, L, L, 0.3, sigma=2.0)
+    rm = ReflectingModel(nx, ny, L, L, 20.0, 3)
+    m = rm.m
+    E, P = m.step(even_extend(eta), even_extend(psi), 0.05, 4)
+    assert np.max(np.abs(E - even_extend(crop(E)))) < 1e-10 * np.max(np.abs(E))
+    assert np.max(np.abs(P - even_extend(crop(P)))) < 1e-10 * np.max(np.abs(P))
+    # d/dx of the extension at the wall x = 0 (half a cell left of sample 0): shift by half a cell spectrally
+    g = m.gr
+    dEx = g.phys(1j * g.kx * g.spec(E) * np.exp(-0.5j * g.kx * (2 * L) / (2 * nx)))
+    assert np.max(np.abs(dEx[:, 0])) < 1e-11 * np.max(np.abs(dEx))
+    assert abs(np.mean(crop(E)) - np.mean(eta)) < 1e-8 * np.max(np.abs(eta))  # nested truncation at the band edge
