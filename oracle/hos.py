@@ -23,7 +23,7 @@ What it computes, and where each step comes from in the paper
 * Time stepping: classical RK4 on the spectral state (the paper's own
   integrator, IF-AB2 of Sec. 3.4, is not used on this path).
 
-Readings taken where the paper is silent (each is listed in the design doc):
+Readings taken where the paper is silent:
   R1  order M keeps G_0..G_{M-1};  R2  G_j for j >= 3 from the Phi^(m)
   recursion;  R3  higher powers of eta are nested dealiased pairwise products
   eta^<l> = P(eta, eta^<l-1>);  R4  the taper sits inside every product P,
