@@ -333,6 +333,43 @@ def ifab2_form(w, warmup, nsteps, rk4_value, rk4_eta):
             "H_after": H, "steps": nsteps}
 
 
+PAPER_TANK_MS = {2: 6.352, 3: 13.52}  # Order 2 / Order 3, deep water, RTX 4090 (tab:wave_prop_time_comp)
+
+
+def paper_tank(nsteps=2000):
+    """The paper's wave-propagation timing workload (Sec. 8, tab:wave_prop_time_comp):
+    20 m x 20 m tank, 128 x 128 cells, reflecting walls on all sides (even
+    extension to 256 x 256), depth 20 m, Gaussian bump A = 2 m, sigma = 1 m,
+    R = 6 m, at rest, eps = 1, IF-AB2 with dt = 0.01 s, 2000 steps, at Orders 2
+    and 3 (M = 2, 3); ms per step beside the paper's RTX 4090 figures."""
+    import torch
+
+    from paper_2608_25203_amd.inputs import tank_bump
+    from paper_2608_25203_amd.zk import Solver
+
+    n, L, dt = 128, 20.0, 0.01
+    eta, psi = tank_bump(n, n, L, L, 2.0)
+    dev = torch.device("cuda:0")
+    out = {"workload": "20 m tank, 128^2 cells, reflecting walls (256^2 extended), depth 20 m, Gaussian bump "
+                       "A = 2 m sigma = 1 m, at rest, eps = 1, IF-AB2 dt = 0.01 s, FP64",
+           "steps": nsteps}
+    for M in (2, 3):
+        s = Solver(n, n, L, L, 20.0, 9.81, M, check=False, device=dev, integrator="ifab2", boundary="reflect")
+        e, p = (torch.tensor(a, dtype=torch.float64, device=dev) for a in (eta, psi))
+        s.step(e.clone(), p.clone(), dt, 10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(e, p, dt, nsteps)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / nsteps
+        out[f"order{M}"] = {"ms_per_step": round(ms, 4), "paper_ms_per_step_rtx4090": PAPER_TANK_MS[M],
+                            "speedup_vs_paper": round(PAPER_TANK_MS[M] / ms, 1),
+                            "finite": bool(torch.isfinite(e).all().item()),
+                            "max_eta": float(e.abs().max().item())}
+        s.close()
+    return out
+
+
 def c2_diagnostics(w, H_before, H_after):
     """Hamiltonian drift of the timed run and the linear-limit dispersion error
     (eps = 0, filter off) of single modes on the benchmark grid: measured
@@ -500,6 +537,7 @@ def main():
         out["c2_diagnostics"] = c2_diagnostics(w, H_before, H_after)
         out["c2_diagnostics"]["H_before"] = H_before
         out["ifab2_form"] = ifab2_form(w, args.warmup, args.steps, value, e_timed)
+        out["paper_tank"] = paper_tank()
     if not args.no_forms:
         out["precision_form"] = precision_form()
         out["closure_form"] = closure_form()

@@ -67,6 +67,8 @@ enum {
                              zk_step stays fully asynchronous                 */
     ZK_OPT_INTEGRATOR = 7,/* ZK_INTEGRATOR_RK4 (default) or ZK_INTEGRATOR_IFAB2;
                              changes the workspace size: set it before zk_bind */
+    ZK_OPT_BOUNDARY = 8,  /* ZK_BC_PERIODIC (default) or ZK_BC_REFLECT; set
+                             before zk_bind                                   */
     ZK_OPT_PROFILE = 6    /* 1: bracket every kernel launch with HIP events on
                              the bound stream and accumulate per-kind times for
                              zk_kernel_stats (adds event records between
@@ -87,6 +89,20 @@ enum {
                                 every zk_step call is the integrating-factor
                                 Euler bootstrap F* = F_0 (no history is kept
                                 across calls). */
+};
+
+/* Boundaries (ZK_OPT_BOUNDARY). */
+enum {
+    ZK_BC_PERIODIC = 0,  /* periodic rectangle                              */
+    ZK_BC_REFLECT = 1    /* reflecting walls on all four sides by the even
+                            extension of Sec. "Boundary conditions via even
+                            extension" (eq:even_ext): the nx x ny cell-centred
+                            fields are mirrored (half-sample symmetric) onto a
+                            2nx x 2ny periodic grid of 2Lx x 2Ly, every
+                            operator runs there, and results are cropped back;
+                            normal derivatives vanish on the walls.  Needs
+                            nx, ny <= 1024.  The Hamiltonian is the tank's.
+                            Not for closures or batches. */
 };
 
 /* Kernel kinds reported by zk_kernel_stats. */

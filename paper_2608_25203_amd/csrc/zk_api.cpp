@@ -105,6 +105,11 @@ void compute_layout(zk_ctx *c) {
     c->off_ifsym = off;
     off = align_up(off + (size_t)(nx / 2) * ny * kIfCoefs * sizeof(double));
   }
+  c->off_ext = 0;
+  if (c->bc == ZK_BC_REFLECT) {
+    c->off_ext = off;
+    off = align_up(off + 4 * (size_t)nx * ny * sizeof(double));
+  }
   c->off_red = off;
   off = align_up(off + (2 * kRedBlocks + 8) * sizeof(double));
   c->off_cmax = off;
@@ -342,6 +347,20 @@ int check_call(zk_ctx *c) {
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+// Reflecting walls: the caller's fields are mirrored into doubled workspace
+// fields ext(k) before a sequence and its outputs cropped back after.
+double *ext(zk_ctx *c, int k) {
+  return reinterpret_cast<double *>(c->ws + c->off_ext) + (size_t)k * c->pp.nx * c->pp.ny;
+}
+int mirror_in(zk_ctx *c, const double *a, int k) {
+  HIP_TRY(c, launch_mirror(a, c->unx, c->uny, ext(c, k), c->stream));
+  return ZK_OK;
+}
+int crop_out(zk_ctx *c, int k, double *a) {
+  HIP_TRY(c, launch_crop(ext(c, k), c->unx, c->uny, a, c->stream));
+  return ZK_OK;
+}
+
 }  // namespace
 
 namespace zk {
@@ -445,6 +464,10 @@ zk_ctx *zk_create(int nx, int ny, double Lx, double Ly, double depth, double g, 
   c->pp.taper = true;
   c->pp.filt = true;
   c->pp.real_bytes = 8;
+  c->unx = nx;
+  c->uny = ny;
+  c->uLx = Lx;
+  c->uLy = Ly;
   try {
     compute_layout(c);
   } catch (...) {
@@ -483,6 +506,18 @@ int zk_set_option(zk_ctx *c, int key, double v) {
     case ZK_OPT_PROFILE:
       c->prof = v != 0.0;
       return ZK_OK;
+    case ZK_OPT_BOUNDARY:
+      if (v != ZK_BC_PERIODIC && v != ZK_BC_REFLECT) return fail(c, ZK_EINVAL, "unknown boundary");
+      if (c->bound && (int)v != c->bc) return fail(c, ZK_EINVAL, "set the boundary before zk_bind");
+      if (v == ZK_BC_REFLECT && (2 * c->unx > 2048 || 2 * c->uny > 2048))
+        return fail(c, ZK_EINVAL, "reflecting walls need nx, ny <= 1024 (the grid is doubled)");
+      c->bc = (int)v;
+      c->pp.nx = c->bc ? 2 * c->unx : c->unx;
+      c->pp.ny = c->bc ? 2 * c->uny : c->uny;
+      c->pp.Lx = c->bc ? 2 * c->uLx : c->uLx;
+      c->pp.Ly = c->bc ? 2 * c->uLy : c->uLy;
+      compute_layout(c);
+      break;
     case ZK_OPT_INTEGRATOR:
       if (v != ZK_INTEGRATOR_RK4 && v != ZK_INTEGRATOR_IFAB2) return fail(c, ZK_EINVAL, "unknown integrator");
       if (c->bound && (int)v != c->integrator) return fail(c, ZK_EINVAL, "set the integrator before zk_bind");
@@ -524,6 +559,14 @@ int zk_dtn(zk_ctx *c, const double *eta, const double *psi, double *G) {
     return fail(c, ZK_EINVAL, "null or misaligned field pointer");
   if ((rc = upload(c, c->have_plan ? c->plan_dt : NAN))) return rc;
   Phys ph;
+  if (c->bc) {
+    if ((rc = mirror_in(c, eta, 0)) || (rc = mirror_in(c, psi, 1))) return rc;
+    ph.in0 = ext(c, 0);
+    ph.in1 = ext(c, 1);
+    ph.out0 = ext(c, 2);
+    if ((rc = run_seq(c, c->plan.dtn, ph))) return rc;
+    return crop_out(c, 2, G);
+  }
   ph.in0 = eta;
   ph.in1 = psi;
   ph.out0 = G;
@@ -538,6 +581,16 @@ int zk_rhs(zk_ctx *c, const double *eta, const double *psi, double *eta_t, doubl
     return fail(c, ZK_EINVAL, "null or misaligned field pointer");
   if ((rc = upload(c, c->have_plan ? c->plan_dt : NAN))) return rc;
   Phys ph;
+  if (c->bc) {
+    if ((rc = mirror_in(c, eta, 0)) || (rc = mirror_in(c, psi, 1))) return rc;
+    ph.in0 = ext(c, 0);
+    ph.in1 = ext(c, 1);
+    ph.out0 = ext(c, 2);
+    ph.out1 = ext(c, 3);
+    if ((rc = run_seq(c, c->plan.rhs, ph))) return rc;
+    if ((rc = crop_out(c, 2, eta_t))) return rc;
+    return crop_out(c, 3, psi_t);
+  }
   ph.in0 = eta;
   ph.in1 = psi;
   ph.out0 = eta_t;
@@ -557,6 +610,11 @@ int zk_step(zk_ctx *c, double *eta, double *psi, double dt, int nsteps) {
   ph.in1 = psi;
   ph.out0 = eta;
   ph.out1 = psi;
+  if (c->bc) {
+    if ((rc = mirror_in(c, eta, 0)) || (rc = mirror_in(c, psi, 1))) return rc;
+    ph.in0 = ph.out0 = ext(c, 0);
+    ph.in1 = ph.out1 = ext(c, 1);
+  }
   const Plan &p = c->plan;
   if ((rc = run_seq(c, p.step_entry, ph))) return rc;
   const bool ab2 = c->integrator == ZK_INTEGRATOR_IFAB2;
@@ -568,6 +626,7 @@ int zk_step(zk_ctx *c, double *eta, double *psi, double dt, int nsteps) {
   }
   const int fin = nsteps & 1;
   if ((rc = run_seq(c, p.step_exit[fin], ph))) return rc;
+  if (c->bc && ((rc = crop_out(c, 0, eta)) || (rc = crop_out(c, 1, psi)))) return rc;
   if (c->check) {
     std::vector<Launch> chk{Launch{L_PARSEVAL, p.chk_e[fin], p.chk_e[fin], p.chk_p[fin], p.chk_p[fin], 0.0, 0.0}};
     if ((rc = run_seq(c, chk, ph))) return rc;
@@ -588,6 +647,11 @@ int zk_hamiltonian(zk_ctx *c, const double *eta, const double *psi, double *H) {
   Phys ph;
   ph.in0 = eta;
   ph.in1 = psi;
+  if (c->bc) {
+    if ((rc = mirror_in(c, eta, 0)) || (rc = mirror_in(c, psi, 1))) return rc;
+    ph.in0 = ext(c, 0);
+    ph.in1 = ext(c, 1);
+  }
   if ((rc = run_seq(c, c->plan.ham, ph))) return rc;
   double h[2] = {0, 0};
   HIP_TRY(c, hipMemcpyAsync(h, c->ws + c->off_red + 2 * kRedBlocks * sizeof(double), sizeof(h),
@@ -596,6 +660,7 @@ int zk_hamiltonian(zk_ctx *c, const double *eta, const double *psi, double *H) {
   const double N = (double)c->pp.nx * c->pp.ny;
   const double dA = c->pp.Lx * c->pp.Ly / N;
   *H = 0.5 * dA * h[0] / N + 0.5 * c->pp.g * dA * h[1] / N;
+  if (c->bc) *H *= 0.25;  // the tank is a quarter of the doubled domain
   return ZK_OK;
 }
 

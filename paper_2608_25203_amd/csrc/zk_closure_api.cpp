@@ -153,6 +153,7 @@ extern "C" {
 zk_closure *zk_closure_create(zk_ctx *low, zk_ctx *full, zk_cnn *net, double k0, double eta_scale,
                               double out_scale) {
   if (!low || !net || !(k0 > 0) || !(eta_scale > 0) || !(out_scale > 0)) return nullptr;
+  if (low->bc || (full && full->bc)) return nullptr;  // periodic grids only
   const PlanParams &a = low->pp;
   if (full) {
     const PlanParams &b = full->pp;

@@ -33,6 +33,10 @@ struct zk_ctx {
   size_t off_ops = 0, off_progs = 0, off_terms = 0, off_outs = 0, off_tasks = 0;
   size_t off_rargs = 0, off_cargs = 0, off_iprog = 0, off_itask = 0;
   int integrator = 0;     // ZK_INTEGRATOR_RK4 or ZK_INTEGRATOR_IFAB2
+  int bc = 0;             // ZK_BC_PERIODIC or ZK_BC_REFLECT
+  int unx = 0, uny = 0;   // caller's grid (the internal grid is doubled for walls)
+  double uLx = 0, uLy = 0;
+  size_t off_ext = 0;     // four doubled fields (walls only)
   size_t off_ifsym = 0;   // IF-AB2 coefficient table (0 when unused)
   double ifsym_dt = NAN;  // dt the table holds
   int tuneT[2][2] = {{0, 0}, {0, 0}};  // [row][pad] autotuned threads per transform (0: default)

@@ -669,6 +669,11 @@ hipError_t launch_batch_col<double>(int, int, dim3, hipStream_t, const ColArgs<d
 template <>
 hipError_t launch_batch_col<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *, PhysArgs);
 
+// Reflecting walls (zk_bc.hip): dst [2ny][2nx] = even extension of src
+// [ny][nx]; crop: dst [ny][nx] = the physical quarter of src [2ny][2nx].
+hipError_t launch_mirror(const double *src, int nx, int ny, double *dst, hipStream_t s);
+hipError_t launch_crop(const double *src, int nx, int ny, double *dst, hipStream_t s);
+
 // FP64 reductions over base spectra (zk_reduce.hip).  Writes
 //   out[0] = sum_k w(kx) Re(conj(a) b),  out[1] = sum_k w(kx) Re(conj(c) d)
 // over the stored half spectrum (w = 1 at kx = 0, 2 elsewhere: the full

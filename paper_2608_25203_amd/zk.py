@@ -16,6 +16,8 @@ ZK_OK, ZK_EINVAL, ZK_ENOWS, ZK_EDEVICE, ZK_EDIVERGED = 0, -1, -2, -3, -4
 ZK_OPT_EPS, ZK_OPT_TAPER, ZK_OPT_FILTER, ZK_OPT_PRECISION, ZK_OPT_CHECK, ZK_OPT_PROFILE = 1, 2, 3, 4, 5, 6
 ZK_OPT_INTEGRATOR = 7
 ZK_INTEGRATOR_RK4, ZK_INTEGRATOR_IFAB2 = 0, 1
+ZK_OPT_BOUNDARY = 8
+ZK_BC_PERIODIC, ZK_BC_REFLECT = 0, 1
 ZK_KERNEL_ROW_PAD, ZK_KERNEL_ROW_BASE, ZK_KERNEL_COL_PAD, ZK_KERNEL_COL_BASE, ZK_KERNEL_REDUCE = 0, 1, 2, 3, 4
 KERNEL_NAMES = {0: "row_pad", 1: "row_base", 2: "col_pad", 3: "col_base", 4: "reduce"}
 
@@ -206,13 +208,14 @@ class Solver:
     Fields are float64 CUDA tensors of shape (ny, nx), contiguous."""
 
     def __init__(self, nx, ny, Lx, Ly, depth, g, M, eps=1.0, taper=True, filt=True, precision=64,
-                 check=True, device="cuda", integrator="rk4"):
+                 check=True, device="cuda", integrator="rk4", boundary="periodic"):
         import torch
 
         self.torch = torch
         self.nx, self.ny = int(nx), int(ny)
         self.device = torch.device(device)
         self.ctx = zk_create(nx, ny, Lx, Ly, depth, g, M)
+        zk_set_option(self.ctx, ZK_OPT_BOUNDARY, {"periodic": ZK_BC_PERIODIC, "reflect": ZK_BC_REFLECT}[boundary])
         zk_set_option(self.ctx, ZK_OPT_PRECISION, precision)
         zk_set_option(self.ctx, ZK_OPT_INTEGRATOR, {"rk4": ZK_INTEGRATOR_RK4, "ifab2": ZK_INTEGRATOR_IFAB2}[integrator])
         zk_set_option(self.ctx, ZK_OPT_EPS, eps)
