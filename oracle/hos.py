@@ -389,6 +389,23 @@ class HOSModel:
         a, b = self.step_ifab2_spec(g.spec(eta), g.spec(psi), dt, nsteps)
         return g.phys(a), g.phys(b)
 
+    # -- inverse DNO map (Sec. 3.5, eq:psi_inverse) -----------------------------------
+    def inverse_dtn_spec(self, eta_h, v_h, iters=8):
+        """psi from (eta, v = G^[M](eta) psi) by the fixed-point iteration
+        psi <- G0^{-1} (v - (G^[M] - G0) psi), seeded with G0^{-1} v.
+        Reading: G0^{-1} is 1/G0 off k = 0 and 0 at k = 0 (the mean of psi
+        enters no operator)."""
+        G0 = self.gr.G0
+        inv = np.where(G0 > 0, 1.0 / np.where(G0 > 0, G0, 1.0), 0.0)
+        psi_h = inv * v_h
+        for _ in range(int(iters)):
+            psi_h = inv * (v_h - (self.dtn_spec(eta_h, psi_h) - G0 * psi_h))
+        return psi_h
+
+    def inverse_dtn(self, eta, v, iters=8):
+        g = self.gr
+        return g.phys(self.inverse_dtn_spec(g.spec(eta), g.spec(v), iters))
+
     # -- Hamiltonian ----------------------------------------------------------------
     def hamiltonian_spec(self, eta_h, psi_h):
         """H = 1/2 dA sum_x psi G psi + 1/2 g dA sum_x eta^2 (eq:hamiltonian),

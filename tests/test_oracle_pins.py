@@ -517,3 +517,32 @@ def test_reflecting_extension_symmetry_and_walls():
     dEx = g.phys(1j * g.kx * g.spec(E) * np.exp(-0.5j * g.kx * (2 * L) / (2 * nx)))
     assert np.max(np.abs(dEx[:, 0])) < 1e-11 * np.max(np.abs(dEx))
     assert abs(np.mean(crop(E)) - np.mean(eta)) < 1e-8 * np.max(np.abs(eta))  # nested truncation at the band edge
+
+
+# ---- inverse DNO map (eq:psi_inverse) ---------------------------------------------------
+def test_inverse_dtn_flat_surface_is_exact():
+    """eta = 0: G = G0, so the seed G0^{-1} v is already the answer (zero-mean v)."""
+    n, L, h = 32, TWO_PI, 0.7
+    m = HOSModel(Grid(n, n, L, L, h), 4)
+    _, psi = random_band_fields(n, n, 3, 10, amplitude=1.0)
+    psi = psi - psi.mean()
+    v = m.dtn(np.zeros_like(psi), psi)
+    assert np.max(np.abs(m.inverse_dtn(np.zeros_like(psi), v) - psi)) < 1e-13 * np.max(np.abs(psi))
+
+
+@pytest.mark.parametrize("M", [2, 3, 5])
+def test_inverse_dtn_inverts_the_forward_map(M):
+    """For a gentle sea the iteration contracts (factor ~ |k eta|): eight
+    iterations recover psi (mean removed) from (eta, G^[M] psi) to 1e-9, the
+    residual G^[M] psi* - v shrinks geometrically with the iteration count."""
+    n, L = 64, TWO_PI
+    eta, psi = jonswap_state(n, n, L, L, None, 9.81, 4.0, 0.05, 6)
+    psi = psi - psi.mean()
+    m = HOSModel(Grid(n, n, L, L, None), M)
+    v = m.dtn(eta, psi)
+    res = []
+    for it in (2, 4, 8):
+        p = m.inverse_dtn(eta, v, it)
+        res.append(np.max(np.abs(m.dtn(eta, p) - v)) / np.max(np.abs(v)))
+    assert np.max(np.abs(p - psi)) < 1e-9 * np.max(np.abs(psi))
+    assert res[1] < res[0] / 10 and res[2] < res[1] / 10
