@@ -406,6 +406,39 @@ class HOSModel:
         g = self.gr
         return g.phys(self.inverse_dtn_spec(g.spec(eta), g.spec(v), iters))
 
+    # -- bulk velocity at depth layers (Alg. ComputeVolumeVelFrom2D) -------------------
+    def depth_velocity(self, eta, psi, ys):
+        """Velocities at depths y_i below the flat reference plane, [L][3][ny][nx]
+        as (u, v, w) = (x velocity, upward velocity, y velocity):
+          Phi|0 = psi - eps P(eta, G0 psi)                    (eq:phi1, first order)
+          Phi|0 <- Phi|0 * prod_a exp(-(|k_a| / (kNyq_a / 2))^8)   (coupling taper)
+          u_i = i kx C_i Phi|0, w_i = i ky C_i Phi|0, v_i = S_i Phi|0  (eq:ui, eq:wi, eq:vi)
+        with C_i = cosh(|k|(d - y_i)) / cosh(|k| d), S_i = |k| sinh(|k|(d - y_i)) / cosh(|k| d)
+        (eq:Ci, eq:Si; deep water: exp(-|k| y_i) and |k| exp(-|k| y_i)), C = 1, S = 0 at k = 0.
+        The quotients are evaluated as exp(-|k| y) (1 +- exp(-2|k|(d - y))) / (1 + exp(-2|k|d)),
+        the same functions without overflow."""
+        g = self.gr
+        eh, ph = g.spec(eta), g.spec(psi)
+        phi0 = ph - self.eps * self.P(eh, g.G0 * ph)
+        knx, kny = np.pi * g.nx / g.Lx, np.pi * g.ny / g.Ly
+        phi0 = phi0 * np.exp(-(np.abs(g.kx) / (0.5 * knx)) ** 8 - (np.abs(g.ky) / (0.5 * kny)) ** 8)
+        k = g.kk
+        out = np.empty((len(ys), 3, g.ny, g.nx))
+        for i, y in enumerate(ys):
+            e1 = np.exp(-k * y)
+            if g.deep:
+                C, S = e1, k * e1
+            else:
+                e2 = np.exp(-2.0 * k * (g.h - y))
+                den = 1.0 + np.exp(-2.0 * k * g.h)
+                C, S = e1 * (1.0 + e2) / den, k * e1 * (1.0 - e2) / den
+            C = np.where(k == 0, 1.0, C)
+            S = np.where(k == 0, 0.0, S)
+            out[i, 0] = g.phys(1j * g.kx * C * phi0)
+            out[i, 1] = g.phys(S * phi0)
+            out[i, 2] = g.phys(1j * g.ky * C * phi0)
+        return out
+
     # -- Hamiltonian ----------------------------------------------------------------
     def hamiltonian_spec(self, eta_h, psi_h):
         """H = 1/2 dA sum_x psi G psi + 1/2 g dA sum_x eta^2 (eq:hamiltonian),

@@ -546,3 +546,43 @@ def test_inverse_dtn_inverts_the_forward_map(M):
         res.append(np.max(np.abs(m.dtn(eta, p) - v)) / np.max(np.abs(v)))
     assert np.max(np.abs(p - psi)) < 1e-9 * np.max(np.abs(psi))
     assert res[1] < res[0] / 10 and res[2] < res[1] / 10
+
+
+# ---- bulk velocity at depth layers ----------------------------------------------------------
+def test_depth_velocity_harmonic_field():
+    """The layered velocities are the gradient of a harmonic potential:
+    divergence-free and irrotational (central differences between layers
+    h apart, O(h^2)); upward velocity zero on the bottom; and on a flat
+    surface the surface layer's upward velocity is G0 psi times the coupling
+    taper (the kinematic condition)."""
+    nx, ny, Lx, Ly, d = 32, 32, 4.0, 4.0, 0.8
+    eta, psi = random_band_fields(nx, ny, 17, 5, amplitude=0.02)
+    m = HOSModel(Grid(nx, ny, Lx, Ly, d), 3)
+    g = m.gr
+    h = 1e-4
+    y0 = 0.3
+    V = m.depth_velocity(eta, psi, [y0 - h, y0, y0 + h, d])
+    u, v, w = V[1]
+    dvdY = (V[0, 1] - V[2, 1]) / (2 * h)  # Y upward, y downward
+    dudx = g.phys(1j * g.kx * g.spec(u))
+    dwdy = g.phys(1j * g.ky * g.spec(w))
+    scale = np.max(np.abs(dudx))
+    assert np.max(np.abs(dudx + dwdy + dvdY)) < 1e-6 * scale
+    dudY = (V[0, 0] - V[2, 0]) / (2 * h)
+    dvdx = g.phys(1j * g.kx * g.spec(v))
+    assert np.max(np.abs(dudY - dvdx)) < 1e-6 * scale
+    assert np.max(np.abs(V[3, 1])) < 1e-14 * np.max(np.abs(v))
+    V0 = m.depth_velocity(np.zeros_like(eta), psi, [0.0])
+    taper = np.exp(-(np.abs(g.kx) / (0.5 * np.pi * nx / Lx)) ** 8 - (np.abs(g.ky) / (0.5 * np.pi * ny / Ly)) ** 8)
+    assert np.max(np.abs(V0[0, 1] - g.phys(g.G0 * taper * g.spec(psi)))) < 1e-13 * np.max(np.abs(V0[0, 1]))
+
+
+def test_depth_velocity_deep_limit():
+    """Deep water: C_i and S_i reduce to exp(-|k| y_i) and |k| exp(-|k| y_i),
+    the limit of the finite-depth kernels for |k| d -> infinity (checked at
+    d = 200 against the deep model)."""
+    n, L = 32, 2.0
+    eta, psi = random_band_fields(n, n, 19, 6, amplitude=0.01)
+    a = HOSModel(Grid(n, n, L, L, None), 2).depth_velocity(eta, psi, [0.0, 0.1, 0.4])
+    b = HOSModel(Grid(n, n, L, L, 200.0), 2).depth_velocity(eta, psi, [0.0, 0.1, 0.4])
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
