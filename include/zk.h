@@ -141,6 +141,32 @@ int zk_bind(zk_ctx *ctx, void *workspace, size_t bytes, void *stream);
  * the forward DNO map v = G(eta) psi (Sec. 3.5, eq:v_forward). */
 int zk_dtn(zk_ctx *ctx, const double *eta, const double *psi, double *G_psi);
 
+/* Inverse DNO map (Sec. 3.5, eq:psi_inverse): psi from the pair (eta, v),
+ * v = G^[M](eta) psi, by the fixed-point iteration
+ *   psi <- G0^{-1} (v - (G^[M](eta) - G0) psi),  seeded with psi = G0^{-1} v,
+ * iters iterations (the paper uses eight).  G0^{-1} is 1/G0 off k = 0 and 0
+ * at k = 0, so psi comes out with zero mean.  The iteration contracts when
+ * |k| |eta| is small across the band. */
+int zk_inverse_dtn(zk_ctx *ctx, const double *eta, const double *v, double *psi, int iters);
+
+/* Bulk velocity at depth layers (Alg. ComputeVolumeVelFrom2D; eq:phi1,
+ * eq:Ci, eq:Si, eq:CiSi_stable, eq:ui, eq:vi, eq:wi) from the surface state.
+ * The first-order potential on the flat plane z = 0,
+ *   Phi|0 = psi - eps P(eta, G0 psi),
+ * is multiplied by the coupling taper prod_a exp(-(|k_a| / (kNyq_a / 2))^8)
+ * and lifted to each depth y_i (measured downward from z = 0) with
+ *   C_i = cosh(|k| (h - y_i)) / cosh(|k| h),  S_i = |k| sinh(|k| (h - y_i)) / cosh(|k| h)
+ * (deep water: exp(-|k| y_i), |k| exp(-|k| y_i); C = 1, S = 0 at k = 0),
+ * evaluated in exponential form without overflow.
+ *   eta, psi : device, [ny][nx] row-major doubles (the context's grid)
+ *   ys       : host, nlayers depths, each in [0, h] (>= 0 in deep water)
+ *   uvw      : device, [nlayers][3][ny][nx]: per layer u = d_x Phi (x velocity),
+ *              v = S_i Phi|0 (vertical velocity), w = d_y Phi (y velocity)
+ * 1 <= nlayers <= 4096.  With reflecting walls the fields are the tank's and
+ * the lift runs on the even extension.  Returns ZK_EINVAL for bad pointers,
+ * counts or depths (nothing is launched then). */
+int zk_depth_velocity(zk_ctx *ctx, const double *eta, const double *psi, int nlayers, const double *ys, double *uvw);
+
 /* Zakharov right-hand side (Sec. 3.1 eq:zakharov_kin; Sec. 3.2
  * eq:dyn_truncated with eq:W):
  *   eta_t = G^[M](eta) psi,

@@ -105,6 +105,8 @@ void compute_layout(zk_ctx *c) {
     c->off_ifsym = off;
     off = align_up(off + (size_t)(nx / 2) * ny * kIfCoefs * sizeof(double));
   }
+  c->off_layer = off;
+  off = align_up(off + (size_t)(nx / 2) * ny * 2 * sizeof(double));
   c->off_ext = 0;
   if (c->bc == ZK_BC_REFLECT) {
     c->off_ext = off;
@@ -426,6 +428,7 @@ ColArgs<real> ctx_col_args(const zk_ctx *c, bool pad, int task0) {
   a.filt_x = reinterpret_cast<const double *>(ws + c->off_fx);
   a.filt_y = reinterpret_cast<const double *>(ws + c->off_fy);
   a.ifsym = c->off_ifsym ? reinterpret_cast<const double *>(ws + c->off_ifsym) : nullptr;
+  a.layer = reinterpret_cast<const double *>(ws + c->off_layer);
   return a;
 }
 
@@ -683,6 +686,67 @@ int zk_kernel_stats(zk_ctx *c, int kind, double *ms, double *bytes, double *flop
   *bytes = c->st_bytes[kind];
   *flops = c->st_flops[kind];
   *launches = c->st_n[kind];
+  return ZK_OK;
+}
+
+int zk_inverse_dtn(zk_ctx *c, const double *eta, const double *v, double *psi, int iters) {
+  int rc = check_call(c);
+  if (rc) return rc;
+  if (!eta || !v || !psi || !aligned16(eta) || !aligned16(v) || !aligned16(psi))
+    return fail(c, ZK_EINVAL, "null or misaligned field pointer");
+  if (iters < 0 || iters > 1000) return fail(c, ZK_EINVAL, "iters must be in [0, 1000]");
+  if ((rc = upload(c, c->have_plan ? c->plan_dt : NAN))) return rc;
+  Phys ph;
+  ph.in0 = eta;
+  ph.in1 = v;
+  ph.out0 = psi;
+  if (c->bc) {
+    if ((rc = mirror_in(c, eta, 0)) || (rc = mirror_in(c, v, 1))) return rc;
+    ph.in0 = ext(c, 0);
+    ph.in1 = ext(c, 1);
+    ph.out0 = ext(c, 2);
+  }
+  if ((rc = run_seq(c, c->plan.inv_entry, ph))) return rc;
+  for (int i = 0; i < iters; ++i)
+    if ((rc = run_seq(c, c->plan.inv_iter, ph))) return rc;
+  if ((rc = run_seq(c, c->plan.inv_exit, ph))) return rc;
+  return c->bc ? crop_out(c, 2, psi) : ZK_OK;
+}
+
+int zk_depth_velocity(zk_ctx *c, const double *eta, const double *psi, int nlayers, const double *ys, double *uvw) {
+  int rc = check_call(c);
+  if (rc) return rc;
+  if (!eta || !psi || !uvw || !aligned16(eta) || !aligned16(psi) || !aligned16(uvw))
+    return fail(c, ZK_EINVAL, "null or misaligned field pointer");
+  if (nlayers < 1 || nlayers > 4096 || !ys) return fail(c, ZK_EINVAL, "nlayers must be in [1, 4096] with depths");
+  for (int i = 0; i < nlayers; ++i)
+    if (!std::isfinite(ys[i]) || ys[i] < 0.0 || (c->pp.depth > 0 && ys[i] > c->pp.depth))
+      return fail(c, ZK_EINVAL, "layer depths must lie in [0, depth]");
+  if ((rc = upload(c, c->have_plan ? c->plan_dt : NAN))) return rc;
+  Phys ph;
+  ph.in0 = eta;
+  ph.in1 = psi;
+  if (c->bc) {
+    if ((rc = mirror_in(c, eta, 0)) || (rc = mirror_in(c, psi, 1))) return rc;
+    ph.in0 = ext(c, 0);
+    ph.in1 = ext(c, 1);
+  }
+  if ((rc = run_seq(c, c->plan.lift_phi, ph))) return rc;
+  const size_t plane = (size_t)c->unx * c->uny;
+  double *layer = reinterpret_cast<double *>(c->ws + c->off_layer);
+  for (int i = 0; i < nlayers; ++i) {
+    double *u = uvw + (3 * (size_t)i + 0) * plane, *v = uvw + (3 * (size_t)i + 1) * plane,
+           *w = uvw + (3 * (size_t)i + 2) * plane;
+    HIP_TRY(c, launch_fill_layer(layer, c->pp.nx, c->pp.ny, 2.0 * M_PI / c->pp.Lx, 2.0 * M_PI / c->pp.Ly,
+                                 c->pp.depth, ys[i], c->stream));
+    ph.out0 = c->bc ? ext(c, 2) : u;
+    ph.out1 = c->bc ? ext(c, 3) : w;
+    if ((rc = run_seq(c, c->plan.layer_uw, ph))) return rc;
+    if (c->bc && ((rc = crop_out(c, 2, u)) || (rc = crop_out(c, 3, w)))) return rc;
+    ph.out0 = c->bc ? ext(c, 2) : v;
+    if ((rc = run_seq(c, c->plan.layer_v, ph))) return rc;
+    if (c->bc && (rc = crop_out(c, 2, v))) return rc;
+  }
   return ZK_OK;
 }
 

@@ -38,6 +38,7 @@ struct zk_ctx {
   double uLx = 0, uLy = 0;
   size_t off_ext = 0;     // four doubled fields (walls only)
   size_t off_ifsym = 0;   // IF-AB2 coefficient table (0 when unused)
+  size_t off_layer = 0;   // (C, S) of one depth layer per band element
   double ifsym_dt = NAN;  // dt the table holds
   int tuneT[2][2] = {{0, 0}, {0, 0}};  // [row][pad] autotuned threads per transform (0: default)
   size_t off_red = 0, off_cmax = 0, off_sym = 0, off_fx = 0, off_fy = 0, off_base = 0, off_mix = 0, total = 0;

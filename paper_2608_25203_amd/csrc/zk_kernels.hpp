@@ -66,6 +66,7 @@ struct ColArgs {
   const SymEl *sym;               // symbol table, base-spectrum layout
   const double *filt_x, *filt_y;  // separable state filter factors
   const double *ifsym;            // kIfCoefs per band element (base layout), or null
+  const double *layer;            // (C_i, S_i) of the current depth layer per band element
 };
 
 // ---- register-set dispatch (keeps every register array statically indexed)
@@ -458,6 +459,15 @@ __device__ __forceinline__ cpx<double> symval(uint32_t s, double kk, double g0, 
   if (s & SYM_FILT) f *= a.filt_x[col] * a.filt_y[b];
   if ((s & SYM_TAPER) && a.taper_on) f *= tp;
   if (s & SYM_IF) f *= a.ifsym[(long long)base_index(col, b, a.ny) * kIfCoefs + ((s >> SYM_IF_SHIFT) & 7)];
+  if (s & SYM_INVG0) f = g0 > 0.0 ? f / g0 : 0.0;
+  if (s & SYM_COUPLE) {
+    const int my = b < a.ny / 2 ? b : b - a.ny;
+    const double rx = 4.0 * col / a.nx, ry = 4.0 * (my < 0 ? -my : my) / a.ny;  // |k_a| / (kNyq_a / 2)
+    const double rx2 = rx * rx, ry2 = ry * ry, rx4 = rx2 * rx2, ry4 = ry2 * ry2;
+    f *= exp(-(rx4 * rx4) - (ry4 * ry4));
+  }
+  if (s & (SYM_LAYER_C | SYM_LAYER_S))
+    f *= a.layer[(long long)base_index(col, b, a.ny) * 2 + ((s & SYM_LAYER_S) ? 1 : 0)];
   if (s & SYM_IKY) return {0.0, f * ky};
   return {f, 0.0};
 }
@@ -673,6 +683,10 @@ hipError_t launch_batch_col<float>(int, int, dim3, hipStream_t, const ColArgs<fl
 // [ny][nx]; crop: dst [ny][nx] = the physical quarter of src [2ny][2nx].
 hipError_t launch_mirror(const double *src, int nx, int ny, double *dst, hipStream_t s);
 hipError_t launch_crop(const double *src, int nx, int ny, double *dst, hipStream_t s);
+// Depth-layer kernels (zk_bc.hip): tab[base_index(col, b) * 2 + {0, 1}] = (C, S)
+// at depth y below the flat reference, depth <= 0: deep water.
+hipError_t launch_fill_layer(double *tab, int nx, int ny, double kx_scale, double ky_scale, double depth, double y,
+                             hipStream_t s);
 
 // FP64 reductions over base spectra (zk_reduce.hip).  Writes
 //   out[0] = sum_k w(kx) Re(conj(a) b),  out[1] = sum_k w(kx) Re(conj(c) d)

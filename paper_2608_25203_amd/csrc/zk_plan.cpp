@@ -241,7 +241,7 @@ Plan build_plan(const PlanParams &pp, double dt) {
     bSE[i] = B.base();
     bSP[i] = B.base();
   }
-  const int bAE = B.base(), bAP = B.base(), bG = B.base(), bPT = B.base();
+  const int bAE = B.base(), bAP = B.base(), bG = B.base(), bPT = B.base(), bV = B.base(), bPhi0 = B.base();
   int bFe[2], bFp[2];  // IF-AB2 forcing of the last two steps
   for (int i = 0; i < 2; ++i) {
     bFe[i] = B.base();
@@ -542,6 +542,52 @@ Plan build_plan(const PlanParams &pp, double dt) {
       }
   }
 
+  // ---- inverse DNO map ------------------------------------------------------------
+  {
+    P.inv_entry.push_back(row_launch(L_ROW_BASE, {entry_prog}));
+    std::vector<TaskSpec> ts(2);
+    ts[0].fwd = mbA;
+    ts[0].outs.push_back(B.store(bUE[0], {{-1, 0, 1.0}}));
+    ts[1].fwd = mbB;
+    ts[1].outs.push_back(B.store(bV, {{-1, 0, 1.0}}));
+    ts[1].outs.push_back(B.store(bUP[0], {{-1, SYM_INVG0, 1.0}}));
+    P.inv_entry.push_back(B.col_launch(L_COL_BASE, ts));
+    P.inv_entry.push_back(B.col_launch(L_COL_PAD, l0_tasks(bUE[0], bUP[0], false)));
+    core(P.inv_iter, bUE[0], bUP[0], false);
+    TaskSpec t;
+    t.outs.push_back(B.store(bUP[0], {{bUP[0], 0, 1.0}, {bV, SYM_INVG0, 1.0}, {bG, SYM_INVG0, -1.0}}));
+    P.inv_iter.push_back(B.col_launch(L_COL_PAD, {t}));
+    P.inv_iter.push_back(B.col_launch(L_COL_PAD, l0_tasks(bUE[0], bUP[0], false)));
+    exit_seq(P.inv_exit, bUP[0], -1);
+  }
+
+  // ---- bulk velocity at depth layers ----------------------------------------------
+  {
+    entry(P.lift_phi);
+    std::vector<TaskSpec> ts(2);
+    ts[0].outs.push_back(B.lift(mE, {{bUE[0], 0, kref}}));
+    ts[1].outs.push_back(B.lift(mL[1], {{bUP[0], 1u, 1.0 / kpow(1)}}));
+    P.lift_phi.push_back(B.col_launch(L_COL_PAD, ts));
+    const int prod = B.product_program({{Fac{mE, 0}, Fac{mL[1], 0}, 0, 1.0}}, {oPHI});
+    P.lift_phi.push_back(row_launch(L_ROW_PAD, {prod}));
+    TaskSpec t = B.fold_task(oPHI);  // X = P(eta, G0 psi)
+    t.outs.push_back(B.store(bPhi0, {{bUP[0], SYM_COUPLE, 1.0}, {-1, SYM_COUPLE, -eps}}));
+    P.lift_phi.push_back(B.col_launch(L_COL_PAD, {t}));
+    const int exit_dx = B.prog_begin();
+    B.ld2(Fac{mbA, FL_DX}, mbB, 0);
+    B.op(OP_STP, RS_U, 0, 0, 0, 0, -1, 0, 0.0);
+    B.op(OP_STP, RS_V, 0, 0, 1, 0, -1, 0, 0.0);
+    std::vector<TaskSpec> tu(2);
+    tu[0].outs.push_back(B.lift(mbA, {{bPhi0, SYM_LAYER_C, 1.0}}));
+    tu[1].outs.push_back(B.lift(mbB, {{bPhi0, SYM_LAYER_C | SYM_IKY, 1.0}}));
+    P.layer_uw.push_back(B.col_launch(L_COL_BASE, tu));
+    P.layer_uw.push_back(row_launch(L_ROW_BASE, {exit_dx}));
+    std::vector<TaskSpec> tv(1);
+    tv[0].outs.push_back(B.lift(mbA, {{bPhi0, SYM_LAYER_S, 1.0}}));
+    P.layer_v.push_back(B.col_launch(L_COL_BASE, tv));
+    P.layer_v.push_back(row_launch(L_ROW_BASE, {exit1_prog}));
+  }
+
   // ---- stepping with an external DtN --------------------------------------------
   // rhs_g: the RHS of (eta, psi) with G supplied on the grid; G is projected
   // onto the band by its entry transform, eta_t = P_B G.
@@ -639,7 +685,7 @@ Plan build_plan(const PlanParams &pp, double dt) {
     };
     for (auto *seq : {&P.dtn, &P.rhs, &P.ham, &P.step_entry, &P.step_body[0], &P.step_body[1], &P.step_lift[0],
                       &P.step_lift[1], &P.step_exit[0], &P.step_exit[1], &P.rhs_g, &P.filter, &P.ab2_first[0],
-                      &P.ab2_first[1], &P.ab2_body[0], &P.ab2_body[1]})
+                      &P.ab2_first[1], &P.ab2_body[0], &P.ab2_body[1], &P.inv_entry, &P.inv_iter, &P.inv_exit, &P.lift_phi, &P.layer_uw, &P.layer_v})
       annotate(*seq);
   }
   return P;
@@ -719,7 +765,7 @@ std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
   };
   for (auto *seq : {&p.dtn, &p.rhs, &p.ham, &p.step_entry, &p.step_body[0], &p.step_body[1], &p.step_lift[0],
                     &p.step_lift[1], &p.step_exit[0], &p.step_exit[1], &p.rhs_g, &p.filter, &p.ab2_first[0],
-                    &p.ab2_first[1], &p.ab2_body[0], &p.ab2_body[1]}) {
+                    &p.ab2_first[1], &p.ab2_body[0], &p.ab2_body[1], &p.inv_entry, &p.inv_iter, &p.inv_exit, &p.lift_phi, &p.layer_uw, &p.layer_v}) {
     std::string e = chk(*seq);
     if (!e.empty()) return e;
   }

@@ -61,6 +61,13 @@ struct Plan {
   // forcing F_n stored in F[p]; the first step of a call is the IF-Euler bootstrap.
   std::vector<Launch> ab2_first[2];
   std::vector<Launch> ab2_body[2];
+  // Inverse DNO map (eq:psi_inverse): (eta, v) -> psi; entry seeds psi = G0^{-1} v,
+  // each iteration psi <- psi + G0^{-1} (v - G^[M] psi), exit writes psi.
+  std::vector<Launch> inv_entry, inv_iter, inv_exit;
+  // Bulk velocity (Alg. ComputeVolumeVelFrom2D): lift_phi stores the tapered
+  // first-order potential on the flat plane; per layer (its (C, S) table filled
+  // first) layer_uw writes u, w (output slots 0, 1) and layer_v writes v (slot 0).
+  std::vector<Launch> lift_phi, layer_uw, layer_v;
   std::vector<Launch> rhs_g;   // eta, psi, G (LDP slots 0, 1, 2) -> eta_t = P_B G, psi_t
   std::vector<Launch> filter;  // eta, psi -> A eta, A psi (the state filter alone)
 };

@@ -80,7 +80,13 @@ int main(int argc, char **argv) {
   dump_seq("ab2_first0", p.ab2_first[0], false);
   dump_seq("ab2_first1", p.ab2_first[1], false);
   dump_seq("ab2_body0", p.ab2_body[0], false);
-  dump_seq("ab2_body1", p.ab2_body[1], true);
+  dump_seq("ab2_body1", p.ab2_body[1], false);
+  dump_seq("inv_entry", p.inv_entry, false);
+  dump_seq("inv_iter", p.inv_iter, false);
+  dump_seq("inv_exit", p.inv_exit, false);
+  dump_seq("lift_phi", p.lift_phi, false);
+  dump_seq("layer_uw", p.layer_uw, false);
+  dump_seq("layer_v", p.layer_v, true);
   std::printf("}\n");
   return 0;
 }

@@ -61,6 +61,11 @@ enum SymBits : uint32_t {
                      // 2 g sin(w dt)/w, 3 sin(w dt)/w, 4 (1-cos(w dt))/g, 5 (1-cos(w dt))/G0
 };
 constexpr int SYM_IF_SHIFT = 8;
+constexpr uint32_t SYM_INVG0 = 0x800;  // 1 / G0 off k = 0, 0 at k = 0 (inverse DNO seed and update)
+// Bulk velocity at a depth layer (Sec. on finite-depth kernels and coupling taper):
+constexpr uint32_t SYM_COUPLE = 0x1000;   // prod_a exp(-(|k_a| / (kNyq_a / 2))^8)
+constexpr uint32_t SYM_LAYER_C = 0x2000;  // C_i of the current layer (eq:Ci, eq:CiSi_stable)
+constexpr uint32_t SYM_LAYER_S = 0x4000;  // S_i of the current layer (eq:Si, eq:CiSi_stable)
 constexpr int kIfCoefs = 6;
 
 struct ColTerm {

@@ -22,7 +22,8 @@ ZK_KERNEL_ROW_PAD, ZK_KERNEL_ROW_BASE, ZK_KERNEL_COL_PAD, ZK_KERNEL_COL_BASE, ZK
 KERNEL_NAMES = {0: "row_pad", 1: "row_base", 2: "col_pad", 3: "col_base", 4: "reduce"}
 
 EXPORTS = ("zk_create", "zk_destroy", "zk_set_option", "zk_workspace_bytes", "zk_bind", "zk_dtn",
-           "zk_rhs", "zk_step", "zk_hamiltonian", "zk_kernel_stats", "zk_autotune", "zk_team_shape", "zk_last_error",
+           "zk_rhs", "zk_step", "zk_hamiltonian", "zk_kernel_stats", "zk_autotune", "zk_team_shape", "zk_inverse_dtn",
+           "zk_depth_velocity", "zk_last_error",
            "zk_cnn_create", "zk_cnn_destroy", "zk_cnn_workspace_bytes", "zk_cnn_bind", "zk_cnn_set_params",
            "zk_cnn_get_params", "zk_cnn_forward", "zk_cnn_gradient", "zk_cnn_train_step", "zk_cnn_last_error",
            "zk_closure_create", "zk_closure_destroy", "zk_closure_workspace_bytes", "zk_closure_bind",
@@ -78,6 +79,10 @@ def lib():
     L.zk_kernel_stats.argtypes = [vp, i, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d),
                                   ctypes.POINTER(ctypes.c_longlong)]
     L.zk_kernel_stats.restype = i
+    L.zk_inverse_dtn.argtypes = [vp, vp, vp, vp, i]
+    L.zk_inverse_dtn.restype = i
+    L.zk_depth_velocity.argtypes = [vp, vp, vp, i, ctypes.POINTER(d), vp]
+    L.zk_depth_velocity.restype = i
     L.zk_autotune.argtypes = [vp, d, i]
     L.zk_autotune.restype = i
     L.zk_team_shape.argtypes = [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]
@@ -240,6 +245,24 @@ class Solver:
         eta, psi = self._field(eta), self._field(psi)
         out = self.torch.empty_like(eta)
         zk_dtn(self.ctx, eta.data_ptr(), psi.data_ptr(), out.data_ptr())
+        return out
+
+    def inverse_dtn(self, eta, v, iters=8):
+        """psi from (eta, v = G(eta) psi): eight fixed-point iterations by default."""
+        eta, v = self._field(eta), self._field(v)
+        out = self.torch.empty_like(eta)
+        _check(self.ctx, lib().zk_inverse_dtn(self.ctx, eta.data_ptr(), v.data_ptr(), out.data_ptr(), int(iters)))
+        return out
+
+    def depth_velocity(self, eta, psi, ys):
+        """(u, v, w) at the depths ys below the flat reference plane, a
+        [len(ys)][3][ny][nx] device tensor (x, vertical and y velocity)."""
+        eta, psi = self._field(eta), self._field(psi)
+        ys = [float(y) for y in ys]
+        out = self.torch.empty((len(ys), 3) + tuple(eta.shape), dtype=eta.dtype, device=eta.device)
+        arr = (ctypes.c_double * max(len(ys), 1))(*ys)
+        _check(self.ctx, lib().zk_depth_velocity(self.ctx, eta.data_ptr(), psi.data_ptr(), len(ys), arr,
+                                                  out.data_ptr()))
         return out
 
     def rhs(self, eta, psi):

@@ -92,6 +92,15 @@ class Interp:
             f = f * self.taper_sym
         if s & SYM_IF:
             f = f * self._ifcoef()[(s >> 8) & 7]
+        if s & 0x800:  # 1 / G0, 0 at k = 0
+            G0 = self.kk * self.th
+            f = np.where(G0 > 0, f / np.where(G0 > 0, G0, 1.0), 0.0)
+        if s & 0x1000:  # coupling taper of the depth lift
+            rx = np.abs(self.kx) / (0.5 * np.pi * self.nx / self.Lx)
+            ry = np.abs(self.ky) / (0.5 * np.pi * self.ny / self.Ly)
+            f = f * np.exp(-rx ** 8 - ry ** 8)
+        if s & 0x6000:  # C or S of the current depth layer
+            f = f * self.layer[1 if s & 0x4000 else 0]
         if s & SYM_IKY:
             return 1j * self.ky * f
         return f.astype(complex)
@@ -253,6 +262,38 @@ class Interp:
         phys = [eta, psi, np.zeros_like(eta), np.zeros_like(eta)]
         self.run(P["filter"], phys)
         return phys[2], phys[3]
+
+    def inverse_dtn(self, eta, v, iters):
+        P = self._plan(self.dt if self.dt is not None else 1.0)
+        phys = [eta, v, np.zeros_like(eta), np.zeros_like(eta)]
+        self.run(P["inv_entry"], phys)
+        for _ in range(iters):
+            self.run(P["inv_iter"], phys)
+        self.run(P["inv_exit"], phys)
+        return phys[2]
+
+    def depth_velocity(self, eta, psi, ys):
+        """(u, v, w) at depths ys, [L][3][ny][nx]; the layer kernels C, S in
+        the numerically stable exponential form, C = 1, S = 0 at k = 0."""
+        P = self._plan(self.dt if self.dt is not None else 1.0)
+        out = np.zeros((len(ys), 3, self.ny, self.nx))
+        phys = [eta, psi, None, None]
+        self.run(P["lift_phi"], phys)
+        k = self.kk
+        for i, y in enumerate(ys):
+            e1 = np.exp(-k * y)
+            if self.depth > 0:
+                e2 = np.exp(-2 * k * (self.depth - y))
+                den = 1 + np.exp(-2 * k * self.depth)
+                C, S = e1 * (1 + e2) / den, k * e1 * (1 - e2) / den
+            else:
+                C, S = e1, k * e1
+            self.layer = (np.where(k == 0, 1.0, C), np.where(k == 0, 0.0, S))
+            phys = [eta, psi, out[i, 0], out[i, 2]]
+            self.run(P["layer_uw"], phys)
+            phys = [eta, psi, out[i, 1], None]
+            self.run(P["layer_v"], phys)
+        return out
 
     def step_ab2(self, eta, psi, dt, nsteps):
         P = self._plan(dt)

@@ -306,3 +306,61 @@ def test_paper_tank_workload_parity(torch, M):
     s.step(e, p, 0.01, 10)
     e0, p0 = ReflectingModel(n, n, L, L, 20.0, M).step_ifab2(eta, psi, 0.01, 10)
     assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
+
+
+@pytest.mark.parametrize("M,boundary", [(3, "periodic"), (5, "periodic"), (2, "reflect")])
+def test_inverse_dtn_parity(torch, M, boundary):
+    """Inverse DNO map (eq:psi_inverse) against the oracle's iteration after
+    0, 1 and 8 iterations (FP64 bar), and 8 iterations recover psi from
+    (eta, G psi) for a gentle sea."""
+    from oracle.hos import ReflectingModel, crop, even_extend
+
+    n, L = 64, TWO_PI
+    eta, psi = jonswap_state(n, n, L, L, 1.0, 9.81, 4.0, 0.05, 21)
+    psi = psi - psi.mean()
+    s = solver(torch, n, n, L, L, 1.0, M, boundary=boundary)
+    if boundary == "reflect":
+        rm = ReflectingModel(n, n, L, L, 1.0, M)
+        fwd = rm.dtn
+        inv = lambda e, v, it: crop(rm.m.inverse_dtn(even_extend(e), even_extend(v), it))  # noqa: E731
+    else:
+        m = HOSModel(Grid(n, n, L, L, 1.0), M)
+        fwd, inv = m.dtn, m.inverse_dtn
+    v = fwd(eta, psi)
+    e, vv = dev(torch, eta), dev(torch, v)
+    for it in (0, 1, 8):
+        assert rel(host(s.inverse_dtn(e, vv, it)), inv(eta, v, it)) < 1e-10
+    if boundary == "periodic":
+        assert rel(host(s.inverse_dtn(e, vv, 8)), psi) < 1e-8
+
+
+@pytest.mark.parametrize("nx,ny,Lx,Ly,depth,boundary,ys", [
+    (128, 128, TWO_PI, TWO_PI, None, "periodic", [0.0, 0.1, 0.5, 2.0]),
+    (128, 64, 4.0, 2.0, 1.0, "periodic", [0.0, 0.3, 1.0]),
+    (64, 64, 20.0, 20.0, 20.0, "reflect", [0.0, 2.0, 10.0, 20.0]),
+])
+def test_depth_velocity_parity(torch, nx, ny, Lx, Ly, depth, boundary, ys):
+    """Bulk velocity at depth layers (Alg. ComputeVolumeVelFrom2D) against
+    the oracle, each layer to the FP64 bar relative to that layer's largest
+    velocity component (the vertical velocity vanishes at a flat bottom)."""
+    from oracle.hos import ReflectingModel, crop, even_extend
+    from paper_2608_25203_amd.inputs import tank_bump
+
+    M = 3
+    if boundary == "reflect":
+        eta, _ = tank_bump(nx, ny, Lx, Ly, 0.5, sigma=1.5)
+        psi = 0.1 * np.sqrt(9.81 / depth) * np.roll(eta, 5, axis=1)
+        rm = ReflectingModel(nx, ny, Lx, Ly, depth, M)
+        full = rm.m.depth_velocity(even_extend(eta), even_extend(psi), ys)
+        ref = np.array([[crop(full[i, c]) for c in range(3)] for i in range(len(ys))])
+    else:
+        kp = 4.0 * TWO_PI / Lx
+        eta, psi = jonswap_state(nx, ny, Lx, Ly, depth, 9.81, kp, 0.08, 31)
+        ref = HOSModel(Grid(nx, ny, Lx, Ly, depth), M).depth_velocity(eta, psi, ys)
+    s = solver(torch, nx, ny, Lx, Ly, math.inf if depth is None else depth, M, boundary=boundary)
+    got = host(s.depth_velocity(dev(torch, eta), dev(torch, psi), ys))
+    assert got.shape == ref.shape
+    for i in range(len(ys)):
+        err = np.max(np.abs(got[i] - ref[i])) / np.max(np.abs(ref[i]))
+        print(f"  layer y = {ys[i]}: rel err {err:.3e}", flush=True)
+        assert err < 1e-10

@@ -101,6 +101,35 @@ def test_ab2_schedule_matches_oracle(M, filt):
         assert rel(s, s0) < 1e-13 and rel(t, t0) < 1e-13
 
 
+@pytest.mark.parametrize("M", [1, 3, 4])
+def test_inverse_dtn_schedule_matches_oracle(M):
+    """The inverse-DNO schedules (seed, iterations, exit) executed literally
+    equal the oracle's fixed-point iteration for 0, 1 and 8 iterations."""
+    nx, ny = 32, 16
+    eta, psi = random_band_fields(nx, ny, 13, 7, amplitude=0.02)
+    I = Interp(nx, ny, 3.0, 2.0, 1.5, 9.81, M)
+    m = HOSModel(Grid(nx, ny, 3.0, 2.0, 1.5), M)
+    v = m.dtn(eta, psi)
+    for it in (0, 1, 8):
+        assert rel(I.inverse_dtn(eta, v, it), m.inverse_dtn(eta, v, it)) < 1e-13
+
+
+@pytest.mark.parametrize("depth", [None, 1.5, 0.4])
+def test_depth_velocity_schedule_matches_oracle(depth):
+    """The depth-lift schedules (potential on the flat plane, then per layer
+    the u, w and v lifts) executed literally equal the oracle's bulk
+    velocity at the surface plane, mid-depth and the bottom (or 1.5 deep)."""
+    nx, ny, Lx, Ly = 32, 16, 3.0, 2.0
+    eta, psi = random_band_fields(nx, ny, 17, 7, amplitude=0.02)
+    I = Interp(nx, ny, Lx, Ly, depth, 9.81, 3)
+    m = HOSModel(Grid(nx, ny, Lx, Ly, depth), 3)
+    ys = [0.0, 0.2, depth if depth else 1.5]
+    got, ref = I.depth_velocity(eta, psi, ys), m.depth_velocity(eta, psi, ys)
+    for i in range(len(ys)):
+        for c in range(3):
+            assert rel(got[i, c], ref[i, c]) < 1e-13, (i, c)
+
+
 # ---------------------------------------------------------------- the library
 LIB = os.path.join(ROOT, "paper_2608_25203_amd", "libzk.so")
 
@@ -140,6 +169,8 @@ def test_library_host_side_argument_checks():
     assert b"eps" in L.zk_last_error(ctx) or b"option" in L.zk_last_error(ctx)
     # calls before zk_bind report a missing workspace without touching a device
     assert L.zk_dtn(ctx, None, None, None) == zk.ZK_ENOWS
+    assert L.zk_inverse_dtn(ctx, None, None, None, 8) == zk.ZK_ENOWS
+    assert L.zk_depth_velocity(ctx, None, None, 1, None, None) == zk.ZK_ENOWS
     L.zk_destroy(ctx)
 
 
