@@ -333,6 +333,87 @@ def ifab2_form(w, warmup, nsteps, rk4_value, rk4_eta):
             "H_after": H, "steps": nsteps}
 
 
+def _kernel_table(s, ncalls):
+    st = s.kernel_stats()
+    return {k: {"launches_per_call": v[3] / ncalls, "avg_us": round(1e3 * v[0] / v[3], 3),
+                "GB_per_s": round(v[1] / (v[0] * 1e-3) / 1e9, 1)}
+            for k, v in st.items() if v[3]}
+
+
+def inverse_dno_form(w, ncalls=20, iters=8):
+    """The inverse DNO map (eq:psi_inverse, eight fixed-point iterations) on
+    the benchmark grid: v = G(eta) psi of the benchmark state, then psi back
+    from (eta, v); ms per map, maps/s, and the recovery error of the
+    zero-mean potential."""
+    import torch
+
+    from paper_2608_25203_amd.inputs import jonswap_state
+    from paper_2608_25203_amd.zk import ZK_OPT_PROFILE, Solver
+
+    eta, psi = jonswap_state(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"], w["kp"], w["steepness"],
+                             w["seed"])
+    dev = torch.device("cuda:0")
+    s = Solver(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"], w["M"], check=False, device=dev)
+    e, p = (torch.tensor(a, dtype=torch.float64, device=dev) for a in (eta, psi))
+    p = p - p.mean()
+    v = s.dtn(e, p)
+    out = s.inverse_dtn(e, v, iters)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(ncalls):
+        out = s.inverse_dtn(e, v, iters)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / ncalls
+    s.set_option(ZK_OPT_PROFILE, 1)
+    s.reset_stats()
+    s.inverse_dtn(e, v, iters)
+    torch.cuda.synchronize()
+    kern = _kernel_table(s, 1)
+    s.close()
+    return {"workload": f"{w['nx']}x{w['ny']}, M={w['M']}, {iters} iterations, FP64", "ms_per_map": round(1e3 * t, 4),
+            "maps_per_s": round(1 / t, 1), "grid_points_per_s": round(w["nx"] * w["ny"] / t, 1),
+            "psi_recovery_rel_err": rel_max(out, p), "kernels": kern}
+
+
+def depth_velocity_form(w, nlayers=32, ncalls=10):
+    """Bulk velocity at depth layers (Alg. ComputeVolumeVelFrom2D) of the
+    benchmark state: nlayers depths evenly spaced from the surface plane to
+    the bottom; ms per call, layer-points/s (one layer-point = the three
+    velocity components at one grid point of one layer) and the per-kernel
+    rates of the layer lifts."""
+    import numpy as np
+    import torch
+
+    from paper_2608_25203_amd.inputs import jonswap_state
+    from paper_2608_25203_amd.zk import ZK_OPT_PROFILE, Solver
+
+    eta, psi = jonswap_state(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"], w["kp"], w["steepness"],
+                             w["seed"])
+    dev = torch.device("cuda:0")
+    s = Solver(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"], w["M"], check=False, device=dev)
+    e, p = (torch.tensor(a, dtype=torch.float64, device=dev) for a in (eta, psi))
+    ys = list(np.linspace(0.0, w["depth"], nlayers))
+    out = s.depth_velocity(e, p, ys)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(ncalls):
+        out = s.depth_velocity(e, p, ys)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / ncalls
+    s.set_option(ZK_OPT_PROFILE, 1)
+    s.reset_stats()
+    s.depth_velocity(e, p, ys)
+    torch.cuda.synchronize()
+    kern = _kernel_table(s, 1)
+    finite = bool(torch.isfinite(out).all().item())
+    s.close()
+    return {"workload": f"{w['nx']}x{w['ny']}, depth {w['depth']:g} m, {nlayers} layers in [0, depth], FP64",
+            "ms_per_call": round(1e3 * t, 4), "us_per_layer": round(1e6 * t / nlayers, 2),
+            "layer_points_per_s": round(w["nx"] * w["ny"] * nlayers / t, 1),
+            "output_GB_per_s": round(3 * 8 * w["nx"] * w["ny"] * nlayers / t / 1e9, 1), "finite": finite,
+            "kernels": kern}
+
+
 PAPER_TANK_MS = {2: 6.352, 3: 13.52}  # Order 2 / Order 3, deep water, RTX 4090 (tab:wave_prop_time_comp)
 
 
@@ -538,6 +619,8 @@ def main():
         out["c2_diagnostics"]["H_before"] = H_before
         out["ifab2_form"] = ifab2_form(w, args.warmup, args.steps, value, e_timed)
         out["paper_tank"] = paper_tank()
+        out["inverse_dno_form"] = inverse_dno_form(w)
+        out["depth_velocity_form"] = depth_velocity_form(w)
     if not args.no_forms:
         out["precision_form"] = precision_form()
         out["closure_form"] = closure_form()

@@ -23,6 +23,19 @@ for kind in ("row", "col"):
             lines.append(f"    hipLaunchKernelGGL(({kind}_kernel_batch<{real}, {T}, {E}>), grid, dim3(256), 0, s, args, items, ph);")
             lines.append("    return hipGetLastError();")
             lines.append("  }")
-        lines += ["  return hipErrorInvalidValue;", "}", "", "}  // namespace zk", ""]
+        lines += ["  return hipErrorInvalidValue;", "}", ""]
+        if kind == "col":  # the lift_sym variant, base-length shapes only
+            lines += ["template <>",
+                      f"hipError_t launch_batch_col_lift<{real}>(int T, int E, dim3 grid, hipStream_t s, const ColArgs<{real}> *args,",
+                      "                                        const BatchItem *items, PhysArgs ph) {"]
+            for T, E in SHAPES:
+                if E % 3 == 0:
+                    continue
+                lines.append(f"  if (T == {T} && E == {E}) {{")
+                lines.append(f"    hipLaunchKernelGGL((col_kernel_batch<{real}, {T}, {E}, true>), grid, dim3(256), 0, s, args, items, ph);")
+                lines.append("    return hipGetLastError();")
+                lines.append("  }")
+            lines += ["  return hipErrorInvalidValue;", "}", ""]
+        lines += ["}  // namespace zk", ""]
         with open(os.path.join(HERE, f"zk_batch_{kind}_{tag}.hip"), "w") as f:
             f.write("\n".join(lines))

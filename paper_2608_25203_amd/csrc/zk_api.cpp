@@ -105,8 +105,8 @@ void compute_layout(zk_ctx *c) {
     c->off_ifsym = off;
     off = align_up(off + (size_t)(nx / 2) * ny * kIfCoefs * sizeof(double));
   }
-  c->off_layer = off;
-  off = align_up(off + (size_t)(nx / 2) * ny * 2 * sizeof(double));
+  c->off_layer = off;  // depths of one chunk of layers
+  off = align_up(off + kMaxChunkLayers * sizeof(double));
   c->off_ext = 0;
   if (c->bc == ZK_BC_REFLECT) {
     c->off_ext = off;
@@ -313,6 +313,8 @@ int run_seq_t(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
       const dim3 grid(sh.blocks, l.count);
       e = row ? launch_batch_row<real>(sh.T, sh.E, grid, c->stream,
                                        reinterpret_cast<const RowArgs<real> *>(ws + c->off_rargs), items, pa)
+          : l.c2 == 1 ? launch_batch_col_lift<real>(sh.T, sh.E, grid, c->stream,
+                                                    reinterpret_cast<const ColArgs<real> *>(ws + c->off_cargs), items, pa)
               : launch_batch_col<real>(sh.T, sh.E, grid, c->stream,
                                        reinterpret_cast<const ColArgs<real> *>(ws + c->off_cargs), items, pa);
     } else {
@@ -428,7 +430,7 @@ ColArgs<real> ctx_col_args(const zk_ctx *c, bool pad, int task0) {
   a.filt_x = reinterpret_cast<const double *>(ws + c->off_fx);
   a.filt_y = reinterpret_cast<const double *>(ws + c->off_fy);
   a.ifsym = c->off_ifsym ? reinterpret_cast<const double *>(ws + c->off_ifsym) : nullptr;
-  a.layer = reinterpret_cast<const double *>(ws + c->off_layer);
+  a.layer_y = reinterpret_cast<const double *>(ws + c->off_layer);
   return a;
 }
 
@@ -732,20 +734,21 @@ int zk_depth_velocity(zk_ctx *c, const double *eta, const double *psi, int nlaye
     ph.in1 = ext(c, 1);
   }
   if ((rc = run_seq(c, c->plan.lift_phi, ph))) return rc;
+  // chunks of layers, one column and one row launch each; with walls one
+  // layer at a time through the doubled fields ext(0..2), cropped
   const size_t plane = (size_t)c->unx * c->uny;
-  double *layer = reinterpret_cast<double *>(c->ws + c->off_layer);
-  for (int i = 0; i < nlayers; ++i) {
-    double *u = uvw + (3 * (size_t)i + 0) * plane, *v = uvw + (3 * (size_t)i + 1) * plane,
-           *w = uvw + (3 * (size_t)i + 2) * plane;
-    HIP_TRY(c, launch_fill_layer(layer, c->pp.nx, c->pp.ny, 2.0 * M_PI / c->pp.Lx, 2.0 * M_PI / c->pp.Ly,
-                                 c->pp.depth, ys[i], c->stream));
-    ph.out0 = c->bc ? ext(c, 2) : u;
-    ph.out1 = c->bc ? ext(c, 3) : w;
-    if ((rc = run_seq(c, c->plan.layer_uw, ph))) return rc;
-    if (c->bc && ((rc = crop_out(c, 2, u)) || (rc = crop_out(c, 3, w)))) return rc;
-    ph.out0 = c->bc ? ext(c, 2) : v;
-    if ((rc = run_seq(c, c->plan.layer_v, ph))) return rc;
-    if (c->bc && (rc = crop_out(c, 2, v))) return rc;
+  const int lc = c->bc ? 1 : c->plan.depth_chunk_max;
+  double *ydev = reinterpret_cast<double *>(c->ws + c->off_layer);
+  for (int i0 = 0; i0 < nlayers; i0 += lc) {
+    const int r = std::min(lc, nlayers - i0);
+    LayerDepths y{};
+    for (int i = 0; i < r; ++i) y.v[i] = ys[i0 + i];
+    HIP_TRY(c, launch_set_layer_depths(ydev, y, c->stream));
+    ph.out0 = c->bc ? ext(c, 0) : uvw + 3 * (size_t)i0 * plane;
+    if ((rc = run_seq(c, c->plan.depth_chunk[r], ph))) return rc;
+    if (c->bc)
+      for (int k = 0; k < 3; ++k)
+        if ((rc = crop_out(c, k, uvw + (3 * (size_t)i0 + k) * plane))) return rc;
   }
   return ZK_OK;
 }

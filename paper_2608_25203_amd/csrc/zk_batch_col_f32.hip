@@ -135,4 +135,58 @@ hipError_t launch_batch_col<float>(int T, int E, dim3 grid, hipStream_t s, const
   return hipErrorInvalidValue;
 }
 
+template <>
+hipError_t launch_batch_col_lift<float>(int T, int E, dim3 grid, hipStream_t s, const ColArgs<float> *args,
+                                        const BatchItem *items, PhysArgs ph) {
+  if (T == 32 && E == 2) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 32, 2, true>), grid, dim3(256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 32 && E == 4) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 32, 4, true>), grid, dim3(256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 32 && E == 8) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 32, 8, true>), grid, dim3(256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 64 && E == 2) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 64, 2, true>), grid, dim3(256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 64 && E == 4) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 64, 4, true>), grid, dim3(256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 64 && E == 8) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 64, 8, true>), grid, dim3(256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 2) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 128, 2, true>), grid, dim3(256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 4) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 128, 4, true>), grid, dim3(256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 8) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 128, 8, true>), grid, dim3(256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 256 && E == 2) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 256, 2, true>), grid, dim3(256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 256 && E == 4) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 256, 4, true>), grid, dim3(256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 256 && E == 8) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 256, 8, true>), grid, dim3(256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace zk

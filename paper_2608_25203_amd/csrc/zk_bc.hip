@@ -1,5 +1,5 @@
 // zk_bc.hip -- even extension and crop of caller fields for reflecting walls, and
-// the per-layer kernels of the bulk velocity lift
+// the depths of a chunk of layers of the bulk velocity lift
 // (Sec. "Boundary conditions via even extension", eq:even_ext).  The tank's
 // nx x ny cell-centred field is mirrored across each wall onto the doubled
 // 2nx x 2ny periodic grid, half-sample symmetric: f~(2n - 1 - i) = f(i).
@@ -29,39 +29,15 @@ __global__ __launch_bounds__(256) void crop_kernel(const double *__restrict__ sr
   dst[i] = src[(long long)y * (2 * nx) + x];
 }
 
-// (C, S) of one depth layer per band element, in the stable exponential
-// form of eq:CiSi_stable; C = 1, S = 0 at k = 0.
-__global__ __launch_bounds__(256) void fill_layer_kernel(double *__restrict__ tab, int nx, int ny, double kxs,
-                                                         double kys, double depth, double y) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= (nx / 2) * ny) return;
-  const int col = i / ny, b = i % ny;
-  const int my = b < ny / 2 ? b : b - ny;
-  const double kx = kxs * col, ky = kys * my, k = sqrt(kx * kx + ky * ky);
-  double C = 1.0, S = 0.0;
-  if (k > 0.0) {
-    const double e1 = exp(-k * y);
-    if (depth > 0.0) {
-      const double e2 = exp(-2.0 * k * (depth - y)), den = 1.0 + exp(-2.0 * k * depth);
-      C = e1 * (1.0 + e2) / den;
-      S = k * e1 * (1.0 - e2) / den;
-    } else {
-      C = e1;
-      S = k * e1;
-    }
-  }
-  const long long e = ((long long)(col / CBB) * ny + b) * CBB + col % CBB;
-  tab[2 * e] = C;
-  tab[2 * e + 1] = S;
+__global__ void set_layer_depths_kernel(double *__restrict__ dst, LayerDepths y) {
+  const int i = threadIdx.x;
+  if (i < kMaxChunkLayers) dst[i] = y.v[i];
 }
 
 }  // namespace
 
-hipError_t launch_fill_layer(double *tab, int nx, int ny, double kx_scale, double ky_scale, double depth, double y,
-                             hipStream_t s) {
-  const int total = (nx / 2) * ny;
-  hipLaunchKernelGGL(fill_layer_kernel, dim3((total + 255) / 256), dim3(256), 0, s, tab, nx, ny, kx_scale, ky_scale,
-                     depth, y);
+hipError_t launch_set_layer_depths(double *dst, LayerDepths y, hipStream_t s) {
+  hipLaunchKernelGGL(set_layer_depths_kernel, dim3(1), dim3(64), 0, s, dst, y);
   return hipGetLastError();
 }
 

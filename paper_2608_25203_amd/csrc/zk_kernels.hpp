@@ -66,7 +66,7 @@ struct ColArgs {
   const SymEl *sym;               // symbol table, base-spectrum layout
   const double *filt_x, *filt_y;  // separable state filter factors
   const double *ifsym;            // kIfCoefs per band element (base layout), or null
-  const double *layer;            // (C_i, S_i) of the current depth layer per band element
+  const double *layer_y;          // depths of the current chunk of layers (kMaxChunkLayers)
 };
 
 // ---- register-set dispatch (keeps every register array statically indexed)
@@ -173,9 +173,12 @@ __device__ __forceinline__ float2 team_max2(float a, float b, float *red) {
   return make_float2(a, b);
 }
 
-// Power-of-two scale s bringing a magnitude m to [1, 2), and 1/s (both
-// exact; 1 for m == 0).
+// Power-of-two scale s bringing a magnitude m to [1, 2), and 1/s, both exact:
+// (2^-e, 2^e) with m in [2^e, 2^(e+1)).  For m = 0 the field is zero (below
+// FP32's smallest magnitude) and the pair is (1, 0), so its half of a paired
+// transform comes out exactly zero instead of carrying its partner's rounding.
 __device__ __forceinline__ float2 pow2_scale(float m) {
+  if (m == 0.f) return make_float2(1.0f, 0.0f);
   if (!(m > 0.f && m < 3.0e38f)) return make_float2(1.0f, 1.0f);
   const int e = ilogbf(m);
   return make_float2(ldexpf(1.0f, -e), ldexpf(1.0f, e));
@@ -429,7 +432,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
       case OP_STP: {
         if constexpr (S::PADDED) break;
         double *po = op.fa == 0 ? a.pout0 : a.pout1;
-        const long long off = (long long)row * a.nx;
+        const long long off = ((long long)(op.fb > 0 ? op.fb : 0) * a.rows + row) * a.nx;
         with_any(op.a, [&](auto X) {
 #pragma unroll
           for (int e = 0; e < E; ++e) po[off + t + T * e] = (double)reg(X, e);
@@ -440,6 +443,41 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         break;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Factors of the bulk velocity lift, applied at the lift stage of a column
+// task (one site, after the terms are summed, so the exponentials do not
+// raise the register peak of the pass).  COUPLE: prod_a exp(-(|k_a| / (kNyq_a / 2))^8).  LAYER_C / _S:
+// C = cosh(k (d - y)) / cosh(k d), S = k sinh(k (d - y)) / cosh(k d) at the
+// chunk's layer depth y, as exp(-k y) (1 +- exp(-2 k (d - y))) / (1 + exp(-2 k d));
+// deep water: exp(-k y) and k exp(-k y); C = 1, S = 0 at k = 0.
+__device__ __forceinline__ double lift_factor(uint32_t s, double kk, int col, int b, int nx, int ny, double depth,
+                                           const double *layer_y) {
+  double f = 1.0;
+  if (s & SYM_COUPLE) {
+    const int my = b < ny / 2 ? b : b - ny;
+    const double rx = 4.0 * col / nx, ry = 4.0 * (my < 0 ? -my : my) / ny;  // |k_a| / (kNyq_a / 2)
+    const double rx2 = rx * rx, ry2 = ry * ry, rx4 = rx2 * rx2, ry4 = ry2 * ry2;
+    f *= exp(-(rx4 * rx4) - (ry4 * ry4));
+  }
+  if (s & (SYM_LAYER_C | SYM_LAYER_S)) {
+    const double y = layer_y[(s >> SYM_LAYER_SHIFT) & 15];
+    double c = 1.0, sn = 0.0;
+    if (kk > 0.0) {
+      const double e1 = exp(-kk * y);
+      if (depth > 0.0) {
+        const double e2 = exp(-2.0 * kk * (depth - y)), den = 1.0 + exp(-2.0 * kk * depth);
+        c = e1 * (1.0 + e2) / den;
+        sn = kk * e1 * (1.0 - e2) / den;
+      } else {
+        c = e1;
+        sn = kk * e1;
+      }
+    }
+    f *= (s & SYM_LAYER_S) ? sn : c;
+  }
+  return f;
 }
 
 // ---------------------------------------------------------------------------
@@ -460,14 +498,6 @@ __device__ __forceinline__ cpx<double> symval(uint32_t s, double kk, double g0, 
   if ((s & SYM_TAPER) && a.taper_on) f *= tp;
   if (s & SYM_IF) f *= a.ifsym[(long long)base_index(col, b, a.ny) * kIfCoefs + ((s >> SYM_IF_SHIFT) & 7)];
   if (s & SYM_INVG0) f = g0 > 0.0 ? f / g0 : 0.0;
-  if (s & SYM_COUPLE) {
-    const int my = b < a.ny / 2 ? b : b - a.ny;
-    const double rx = 4.0 * col / a.nx, ry = 4.0 * (my < 0 ? -my : my) / a.ny;  // |k_a| / (kNyq_a / 2)
-    const double rx2 = rx * rx, ry2 = ry * ry, rx4 = rx2 * rx2, ry4 = ry2 * ry2;
-    f *= exp(-(rx4 * rx4) - (ry4 * ry4));
-  }
-  if (s & (SYM_LAYER_C | SYM_LAYER_S))
-    f *= a.layer[(long long)base_index(col, b, a.ny) * 2 + ((s & SYM_LAYER_S) ? 1 : 0)];
   if (s & SYM_IKY) return {0.0, f * ky};
   return {f, 0.0};
 }
@@ -475,7 +505,7 @@ __device__ __forceinline__ cpx<double> symval(uint32_t s, double kk, double g0, 
 // Column pass body: TPB teams per block (block blk of the pass), one kx
 // column each, all running task tasks[task].  Thread t owns base-band rows
 // b = t + T q, q < QB (q = KR at t = 0 is the ky Nyquist row, kept zero).
-template <typename real, int T, int E>
+template <typename real, int T, int E, bool LIFTSYM = false>
 __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index, int blk) {
   using S = Shape<T, E>;
   constexpr int N = S::N, L = S::L, NB = S::template nbuf<real>(), QB = S::QB;
@@ -595,7 +625,10 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
 #pragma unroll
       for (int q = 0; q < QB; ++q) {
         const int r = q < S::KR ? q : q + (S::PADDED ? E / 3 : 0);
-        z[r] = {(real)(acc[q].x * lc), (real)(acc[q].y * lc)};
+        double f = lc;
+        if constexpr (LIFTSYM)
+          if (out.lift_sym) f *= lift_factor(out.lift_sym, skk[q], col, t + T * q, a.nx, ny, a.depth, a.layer_y);
+        z[r] = {(real)(acc[q].x * f), (real)(acc[q].y * f)};
       }
       const cpx<real> *res = team_fft<real, N, E, NB, +1>(z, b0, b1, tw, t);
       cpx<real> *F = a.mix + (long long)out.dst_mixed * a.mix_stride;
@@ -638,12 +671,14 @@ __global__ __launch_bounds__(256) void row_kernel_batch(const RowArgs<real> *__r
   }
   row_body<real, T, E>(a, it.index, blockIdx.x);
 }
-template <typename real, int T, int E>
+// LIFTSYM: the variant that applies ColOut.lift_sym (the bulk velocity
+// lift's column launches); the plain passes never carry its exponentials.
+template <typename real, int T, int E, bool LIFTSYM = false>
 __global__ __launch_bounds__(256) void col_kernel_batch(const ColArgs<real> *__restrict__ args,
                                                         const BatchItem *__restrict__ items, PhysArgs) {
   const BatchItem it = items[blockIdx.y];
   const ColArgs<real> a = args[it.tile];
-  col_body<real, T, E>(a, it.index, blockIdx.x);
+  col_body<real, T, E, LIFTSYM>(a, it.index, blockIdx.x);
 }
 
 // Team shapes (T, E) compiled for the batched kernels: T in {32, 64, 128,
@@ -678,15 +713,26 @@ template <>
 hipError_t launch_batch_col<double>(int, int, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *, PhysArgs);
 template <>
 hipError_t launch_batch_col<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *, PhysArgs);
+// The lift_sym variant of the base-length column kernel (E in {2, 4, 8}).
+template <typename real>
+hipError_t launch_batch_col_lift(int T, int E, dim3 grid, hipStream_t s, const ColArgs<real> *args,
+                                 const BatchItem *items, PhysArgs ph);
+template <>
+hipError_t launch_batch_col_lift<double>(int, int, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *,
+                                         PhysArgs);
+template <>
+hipError_t launch_batch_col_lift<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *,
+                                        PhysArgs);
 
 // Reflecting walls (zk_bc.hip): dst [2ny][2nx] = even extension of src
 // [ny][nx]; crop: dst [ny][nx] = the physical quarter of src [2ny][2nx].
 hipError_t launch_mirror(const double *src, int nx, int ny, double *dst, hipStream_t s);
 hipError_t launch_crop(const double *src, int nx, int ny, double *dst, hipStream_t s);
-// Depth-layer kernels (zk_bc.hip): tab[base_index(col, b) * 2 + {0, 1}] = (C, S)
-// at depth y below the flat reference, depth <= 0: deep water.
-hipError_t launch_fill_layer(double *tab, int nx, int ny, double kx_scale, double ky_scale, double depth, double y,
-                             hipStream_t s);
+// Depths of one chunk of layers (zk_bc.hip): dst[i] = y.v[i] for i < kMaxChunkLayers.
+struct LayerDepths {
+  double v[kMaxChunkLayers];
+};
+hipError_t launch_set_layer_depths(double *dst, LayerDepths y, hipStream_t s);
 
 // FP64 reductions over base spectra (zk_reduce.hip).  Writes
 //   out[0] = sum_k w(kx) Re(conj(a) b),  out[1] = sum_k w(kx) Re(conj(c) d)

@@ -35,6 +35,7 @@ struct OutSpec {
   int dst_base = -1, dst_mixed = -1;
   std::vector<TermSpec> terms;
   double lift_coef = 1.0;
+  uint32_t lift_sym = 0;
 };
 
 struct TaskSpec {
@@ -159,6 +160,7 @@ class Builder {
         co.t0 = (int32_t)P.terms.size();
         co.nt = (int32_t)o.terms.size();
         co.lift_coef = o.lift_coef;
+        co.lift_sym = o.lift_sym;
         for (auto &tm : o.terms) P.terms.push_back({tm.src, tm.sym, tm.coef});
         P.outs.push_back(co);
       }
@@ -170,11 +172,12 @@ class Builder {
     add_tasks(ts);
     return l;
   }
-  OutSpec lift(int dst_mixed, std::vector<TermSpec> terms) {
+  OutSpec lift(int dst_mixed, std::vector<TermSpec> terms, uint32_t lift_sym = 0) {
     OutSpec o;
     o.dst_mixed = dst_mixed;
     o.terms = std::move(terms);
     o.lift_coef = inv_n;
+    o.lift_sym = lift_sym;
     return o;
   }
   OutSpec store(int dst_base, std::vector<TermSpec> terms) {
@@ -571,21 +574,37 @@ Plan build_plan(const PlanParams &pp, double dt) {
     const int prod = B.product_program({{Fac{mE, 0}, Fac{mL[1], 0}, 0, 1.0}}, {oPHI});
     P.lift_phi.push_back(row_launch(L_ROW_PAD, {prod}));
     TaskSpec t = B.fold_task(oPHI);  // X = P(eta, G0 psi)
-    t.outs.push_back(B.store(bPhi0, {{bUP[0], SYM_COUPLE, 1.0}, {-1, SYM_COUPLE, -eps}}));
+    t.outs.push_back(B.store(bPhi0, {{bUP[0], 0, 1.0}, {-1, 0, -eps}}));  // the taper comes with each layer
     P.lift_phi.push_back(B.col_launch(L_COL_PAD, {t}));
-    const int exit_dx = B.prog_begin();
-    B.ld2(Fac{mbA, FL_DX}, mbB, 0);
-    B.op(OP_STP, RS_U, 0, 0, 0, 0, -1, 0, 0.0);
-    B.op(OP_STP, RS_V, 0, 0, 1, 0, -1, 0, 0.0);
-    std::vector<TaskSpec> tu(2);
-    tu[0].outs.push_back(B.lift(mbA, {{bPhi0, SYM_LAYER_C, 1.0}}));
-    tu[1].outs.push_back(B.lift(mbB, {{bPhi0, SYM_LAYER_C | SYM_IKY, 1.0}}));
-    P.layer_uw.push_back(B.col_launch(L_COL_BASE, tu));
-    P.layer_uw.push_back(row_launch(L_ROW_BASE, {exit_dx}));
-    std::vector<TaskSpec> tv(1);
-    tv[0].outs.push_back(B.lift(mbA, {{bPhi0, SYM_LAYER_S, 1.0}}));
-    P.layer_v.push_back(B.col_launch(L_COL_BASE, tv));
-    P.layer_v.push_back(row_launch(L_ROW_BASE, {exit1_prog}));
+    // Chunks: every mixed field is free once Phi|0 is stored, three per layer.
+    const int lc = std::min(kMaxChunkLayers, P.nmix / 3);
+    P.depth_chunk_max = lc;
+    for (int r = 1; r <= lc; ++r) {
+      std::vector<TaskSpec> ts(r);
+      for (int i = 0; i < r; ++i) {
+        const uint32_t li = SYM_COUPLE | ((uint32_t)i << SYM_LAYER_SHIFT);
+        ts[i].outs.push_back(B.lift(3 * i, {{bPhi0, 0, 1.0}}, SYM_LAYER_C | li));            // C Phi (d_x in the row pass)
+        ts[i].outs.push_back(B.lift(3 * i + 1, {{bPhi0, 0, 1.0}}, SYM_LAYER_S | li));        // v = S Phi
+        ts[i].outs.push_back(B.lift(3 * i + 2, {{bPhi0, SYM_IKY, 1.0}}, SYM_LAYER_C | li));  // w = i ky C Phi
+      }
+      Launch cl = B.col_launch(L_COL_BASE, ts);
+      cl.c2 = 1;  // the lift_sym kernel variant
+      P.depth_chunk[r].push_back(cl);
+      std::vector<int> progs;
+      for (int i = 0; i < r; i += 2) {
+        progs.push_back(B.prog_begin());
+        const int n2 = std::min(2, r - i);
+        for (int j = i; j < i + n2; ++j) {
+          B.ld2(Fac{3 * j, FL_DX}, 3 * j + 2, 0);
+          B.op(OP_STP, RS_U, 0, 0, 0, 0, 3 * j, 0, 0.0);
+          B.op(OP_STP, RS_V, 0, 0, 0, 0, 3 * j + 2, 0, 0.0);
+        }
+        B.ld2(Fac{3 * i + 1, 0}, n2 == 2 ? 3 * i + 4 : -1, 0);
+        B.op(OP_STP, RS_U, 0, 0, 0, 0, 3 * i + 1, 0, 0.0);
+        if (n2 == 2) B.op(OP_STP, RS_V, 0, 0, 0, 0, 3 * i + 4, 0, 0.0);
+      }
+      P.depth_chunk[r].push_back(row_launch(L_ROW_BASE, progs));
+    }
   }
 
   // ---- stepping with an external DtN --------------------------------------------
@@ -683,12 +702,19 @@ Plan build_plan(const PlanParams &pp, double dt) {
         }
       }
     };
-    for (auto *seq : {&P.dtn, &P.rhs, &P.ham, &P.step_entry, &P.step_body[0], &P.step_body[1], &P.step_lift[0],
-                      &P.step_lift[1], &P.step_exit[0], &P.step_exit[1], &P.rhs_g, &P.filter, &P.ab2_first[0],
-                      &P.ab2_first[1], &P.ab2_body[0], &P.ab2_body[1], &P.inv_entry, &P.inv_iter, &P.inv_exit, &P.lift_phi, &P.layer_uw, &P.layer_v})
-      annotate(*seq);
+    for (auto *seq : plan_sequences(P)) annotate(*seq);
   }
   return P;
+}
+
+std::vector<std::vector<Launch> *> plan_sequences(Plan &p) {
+  std::vector<std::vector<Launch> *> v = {&p.dtn,          &p.rhs,          &p.ham,          &p.step_entry,
+                                          &p.step_body[0], &p.step_body[1], &p.step_lift[0], &p.step_lift[1],
+                                          &p.step_exit[0], &p.step_exit[1], &p.rhs_g,        &p.filter,
+                                          &p.ab2_first[0], &p.ab2_first[1], &p.ab2_body[0],  &p.ab2_body[1],
+                                          &p.inv_entry,    &p.inv_iter,     &p.inv_exit,     &p.lift_phi};
+  for (int r = 1; r <= p.depth_chunk_max; ++r) v.push_back(&p.depth_chunk[r]);
+  return v;
 }
 
 std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
@@ -712,7 +738,7 @@ std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
           if (o.fa < 0 || o.fa > 2 || o.fb > 2) return bad("LDP slot");
           break;
         case OP_STP:
-          if (o.fa < 0 || o.fa > 1 || o.a > RS_O2) return bad("STP");
+          if (o.fa < 0 || o.fa > 1 || o.a > RS_O2 || o.fb >= 3 * kMaxChunkLayers) return bad("STP");
           break;
         case OP_MAC:
           if (o.a < RS_O0 || o.a > RS_O2 || o.b > RS_A || o.c > RS_A) return bad("MAC regs");
@@ -755,6 +781,10 @@ std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
           }
       } else if (l.kind == L_COL_PAD || l.kind == L_COL_BASE) {
         if (l.first < 0 || l.count < 1 || l.first + l.count > (int)p.tasks.size()) return "col launch";
+        if (l.c2 != 0 && !(l.c2 == 1 && l.kind == L_COL_BASE)) return "lift_sym variant on a padded pass";
+        for (int k = l.first; k < l.first + l.count; ++k)
+          for (int i = 0; i < p.tasks[k].no; ++i)
+            if (p.outs[p.tasks[k].o0 + i].lift_sym && l.c2 != 1) return "lift_sym output in a plain column launch";
       } else if (l.kind == L_PARSEVAL) {
         if (l.first >= p.nbase || l.count >= p.nbase || l.c2 >= p.nbase || l.d2 >= p.nbase) return "parseval";
       } else {
@@ -763,9 +793,7 @@ std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
     }
     return "";
   };
-  for (auto *seq : {&p.dtn, &p.rhs, &p.ham, &p.step_entry, &p.step_body[0], &p.step_body[1], &p.step_lift[0],
-                    &p.step_lift[1], &p.step_exit[0], &p.step_exit[1], &p.rhs_g, &p.filter, &p.ab2_first[0],
-                    &p.ab2_first[1], &p.ab2_body[0], &p.ab2_body[1], &p.inv_entry, &p.inv_iter, &p.inv_exit, &p.lift_phi, &p.layer_uw, &p.layer_v}) {
+  for (auto *seq : plan_sequences(const_cast<Plan &>(p))) {
     std::string e = chk(*seq);
     if (!e.empty()) return e;
   }

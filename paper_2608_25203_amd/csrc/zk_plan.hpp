@@ -28,6 +28,7 @@ enum LaunchKind : int { L_ROW_PAD = 0, L_ROW_BASE = 1, L_COL_PAD = 2, L_COL_BASE
 struct Launch {
   int kind;
   int first, count;  // program or task range; for L_PARSEVAL: base ids a, b (c, d in c2, d2)
+                     // a column launch with c2 = 1 applies its outputs' lift_sym (depth lift)
   int c2, d2;
   double bytes;  // algorithmic HBM bytes of the launch (fields read + written once each)
   double flops;  // FFT flops of the launch, 5 N log2 N per complex transform of length N
@@ -65,12 +66,19 @@ struct Plan {
   // each iteration psi <- psi + G0^{-1} (v - G^[M] psi), exit writes psi.
   std::vector<Launch> inv_entry, inv_iter, inv_exit;
   // Bulk velocity (Alg. ComputeVolumeVelFrom2D): lift_phi stores the tapered
-  // first-order potential on the flat plane; per layer (its (C, S) table filled
-  // first) layer_uw writes u, w (output slots 0, 1) and layer_v writes v (slot 0).
-  std::vector<Launch> lift_phi, layer_uw, layer_v;
+  // first-order potential on the flat plane; depth_chunk[r] (1 <= r <=
+  // depth_chunk_max) lifts r layers, whose depths the column args carry, in
+  // one column and one row launch and writes (u, v, w) of layer i to planes
+  // 3i, 3i+1, 3i+2 of output slot 0.
+  std::vector<Launch> lift_phi;
+  std::vector<Launch> depth_chunk[kMaxChunkLayers + 1];
+  int depth_chunk_max = 0;
   std::vector<Launch> rhs_g;   // eta, psi, G (LDP slots 0, 1, 2) -> eta_t = P_B G, psi_t
   std::vector<Launch> filter;  // eta, psi -> A eta, A psi (the state filter alone)
 };
+
+// Every launch sequence of a plan (for annotation, validation and dumps).
+std::vector<std::vector<Launch> *> plan_sequences(Plan &p);
 
 // Build the full plan (host only; deterministic).  Throws std::runtime_error
 // on an internal inconsistency.

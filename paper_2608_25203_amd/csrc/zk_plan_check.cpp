@@ -44,7 +44,7 @@ int main(int argc, char **argv) {
     std::fprintf(stderr, "validation: %s\n", v.c_str());
     return 1;
   }
-  std::printf("{\"nmix\": %d, \"nbase\": %d,\n", p.nmix, p.nbase);
+  std::printf("{\"nmix\": %d, \"nbase\": %d, \"depth_chunk_max\": %d,\n", p.nmix, p.nbase, p.depth_chunk_max);
   std::printf("\"ops\": [");
   for (size_t i = 0; i < p.ops.size(); ++i) {
     const RowOp &o = p.ops[i];
@@ -58,8 +58,8 @@ int main(int argc, char **argv) {
     std::printf("%s[%d,%u,%.17g]", i ? "," : "", p.terms[i].src, p.terms[i].sym, p.terms[i].coef);
   std::printf("],\n\"outs\": [");
   for (size_t i = 0; i < p.outs.size(); ++i)
-    std::printf("%s[%d,%d,%d,%d,%.17g]", i ? "," : "", p.outs[i].dst_base, p.outs[i].dst_mixed, p.outs[i].t0,
-                p.outs[i].nt, p.outs[i].lift_coef);
+    std::printf("%s[%d,%d,%d,%d,%.17g,%u]", i ? "," : "", p.outs[i].dst_base, p.outs[i].dst_mixed, p.outs[i].t0,
+                p.outs[i].nt, p.outs[i].lift_coef, p.outs[i].lift_sym);
   std::printf("],\n\"tasks\": [");
   for (size_t i = 0; i < p.tasks.size(); ++i)
     std::printf("%s[%d,%u,%.17g,%d,%d]", i ? "," : "", p.tasks[i].fwd, p.tasks[i].fwd_sym, p.tasks[i].fwd_coef,
@@ -85,8 +85,8 @@ int main(int argc, char **argv) {
   dump_seq("inv_iter", p.inv_iter, false);
   dump_seq("inv_exit", p.inv_exit, false);
   dump_seq("lift_phi", p.lift_phi, false);
-  dump_seq("layer_uw", p.layer_uw, false);
-  dump_seq("layer_v", p.layer_v, true);
+  for (int r = 1; r <= p.depth_chunk_max; ++r)
+    dump_seq(("depth_chunk" + std::to_string(r)).c_str(), p.depth_chunk[r], r == p.depth_chunk_max);
   std::printf("}\n");
   return 0;
 }

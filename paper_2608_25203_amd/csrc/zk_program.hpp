@@ -28,7 +28,7 @@ enum RowCode : uint8_t {
   OP_BERN = 6, // o0 <- Bernoulli term from o0 = |grad eta|^2, o1 = grad eta.grad psi,
                //       o2 = |grad psi|^2, u = G psi; coef = eps
   OP_ST2 = 7,  // forward x-FFT of R[a] + i R[b]; split; store kx < nx/2 to mixed fa, fb
-  OP_STP = 8   // physical row of R[a] -> caller field slot fa (base grid)
+  OP_STP = 8   // physical row of R[a] -> caller field slot fa, plane fb >= 0 of it (base grid)
 };
 
 // register sets of a row team (each E values per thread)
@@ -62,10 +62,13 @@ enum SymBits : uint32_t {
 };
 constexpr int SYM_IF_SHIFT = 8;
 constexpr uint32_t SYM_INVG0 = 0x800;  // 1 / G0 off k = 0, 0 at k = 0 (inverse DNO seed and update)
-// Bulk velocity at a depth layer (Sec. on finite-depth kernels and coupling taper):
+// Bulk velocity at a depth layer (Sec. on finite-depth kernels and coupling
+// taper); these act only through ColOut.lift_sym:
 constexpr uint32_t SYM_COUPLE = 0x1000;   // prod_a exp(-(|k_a| / (kNyq_a / 2))^8)
-constexpr uint32_t SYM_LAYER_C = 0x2000;  // C_i of the current layer (eq:Ci, eq:CiSi_stable)
-constexpr uint32_t SYM_LAYER_S = 0x4000;  // S_i of the current layer (eq:Si, eq:CiSi_stable)
+constexpr uint32_t SYM_LAYER_C = 0x2000;  // C_i of layer i of the chunk (eq:Ci, eq:CiSi_stable)
+constexpr uint32_t SYM_LAYER_S = 0x4000;  // S_i of layer i of the chunk (eq:Si, eq:CiSi_stable)
+constexpr int SYM_LAYER_SHIFT = 16;       // bits 16..19: i, the layer's index in its chunk
+constexpr int kMaxChunkLayers = 16;       // depth layers lifted per column/row launch pair
 constexpr int kIfCoefs = 6;
 
 struct ColTerm {
@@ -79,6 +82,8 @@ struct ColOut {
   int32_t dst_mixed;  // mixed-field id to lift the combination into, or -1
   int32_t t0, nt;     // terms [t0, t0 + nt)
   double lift_coef;   // extra factor applied before the lift (1/N)
+  uint32_t lift_sym;  // depth-lift factors (SYM_COUPLE, SYM_LAYER_*) applied to the lifted copy only, or 0
+  uint32_t pad_;
 };
 
 struct ColTask {

@@ -24,12 +24,13 @@ L_ROW_PAD, L_ROW_BASE, L_COL_PAD, L_COL_BASE, L_PARSEVAL = range(5)
 
 
 def pow2_scale(a):
-    """Per-row power-of-two scale bringing max(|re|, |im|) of each row to [1, 2)."""
+    """Per-row power-of-two scale bringing max(|re|, |im|) of each row to [1, 2),
+    and its inverse, which is 0 for an all-zero row (whose result is exactly 0)."""
     a = np.asarray(a)
     m = np.max(np.maximum(np.abs(a.real), np.abs(a.imag)), axis=1, keepdims=True)
     with np.errstate(divide="ignore"):
         e = np.where(m > 0, np.floor(np.log2(np.where(m > 0, m, 1.0))), 0.0)
-    return np.exp2(-e)
+    return np.exp2(-e), np.where(m > 0, np.exp2(e), 0.0)
 
 
 def build_checker():
@@ -99,8 +100,17 @@ class Interp:
             rx = np.abs(self.kx) / (0.5 * np.pi * self.nx / self.Lx)
             ry = np.abs(self.ky) / (0.5 * np.pi * self.ny / self.Ly)
             f = f * np.exp(-rx ** 8 - ry ** 8)
-        if s & 0x6000:  # C or S of the current depth layer
-            f = f * self.layer[1 if s & 0x4000 else 0]
+        if s & 0x6000:  # C or S of layer (s >> 16) & 15 of the chunk
+            y = self.layer_y[(s >> 16) & 15]
+            k = self.kk
+            e1 = np.exp(-k * y)
+            if self.depth > 0:
+                e2 = np.exp(-2 * k * (self.depth - y))
+                den = 1 + np.exp(-2 * k * self.depth)
+                C, S = e1 * (1 + e2) / den, k * e1 * (1 - e2) / den
+            else:
+                C, S = e1, k * e1
+            f = f * (np.where(k == 0, 0.0, S) if s & 0x4000 else np.where(k == 0, 1.0, C))
         if s & SYM_IKY:
             return 1j * self.ky * f
         return f.astype(complex)
@@ -139,13 +149,13 @@ class Interp:
                         return S
                     Sa = spec(fa, fla)
                     Sb = spec(fb, flb) if fb >= 0 else np.zeros_like(Sa)
-                    sa, sb = pow2_scale(Sa), pow2_scale(Sb)
+                    (sa, ia), (sb, ib) = pow2_scale(Sa), pow2_scale(Sb)
                     Sa, Sb = Sa * sa, Sb * sb
                     Z = np.zeros((rows, N), complex)
                     Z[:, :K] = Sa + 1j * Sb
                     Z[:, N - K + 1:] = (np.conj(Sa) + 1j * np.conj(Sb))[:, 1:][:, ::-1]
                     z = np.fft.ifft(Z, axis=1) * N
-                    R[0], R[1] = z.real / sa, z.imag / sb
+                    R[0], R[1] = z.real * ia, z.imag * ib
                 elif code == OP_LDP:
                     slot = lambda i: 4 if i == 2 else i  # phys: in0, in1, out0, out1, in2
                     R[0] = np.array(phys[slot(fa)], dtype=float)
@@ -164,16 +174,19 @@ class Interp:
                 elif code == OP_ST2:
                     x = R[a]
                     y = R[b] if b != RS_NONE else np.zeros_like(x)
-                    sx, sy = pow2_scale(x), pow2_scale(y)
+                    (sx, ix), (sy, iy) = pow2_scale(x), pow2_scale(y)
                     Z = np.fft.fft(x * sx + 1j * (y * sy), axis=1)
                     k = np.arange(K)
                     Zk = Z[:, k]
                     Zm = Z[:, (N - k) % N]
-                    self._mix_put(fa, rows, (Zk + np.conj(Zm)) / 2 / sx)
+                    self._mix_put(fa, rows, (Zk + np.conj(Zm)) / 2 * ix)
                     if fb >= 0:
-                        self._mix_put(fb, rows, (Zk - np.conj(Zm)) / 2j / sy)
+                        self._mix_put(fb, rows, (Zk - np.conj(Zm)) / 2j * iy)
                 elif code == OP_STP:
-                    phys[2 + fa][...] = R[a]
+                    if fb >= 0:
+                        phys[2 + fa][fb][...] = R[a]
+                    else:
+                        phys[2 + fa][...] = R[a]
                 else:
                     raise ValueError(code)
 
@@ -198,7 +211,7 @@ class Interp:
                 X = V[idx, :] * fcoef * self.sym(fsym)
                 X[ny // 2, :] = 0
             for oi in range(o0, o0 + no):
-                dst_b, dst_m, t0, nt, lc = P["outs"][oi]
+                dst_b, dst_m, t0, nt, lc, lsym = P["outs"][oi]
                 acc = np.zeros((ny, self.K), complex)
                 for src, s, coef in P["terms"][t0:t0 + nt]:
                     v = X if src < 0 else self.base[src]
@@ -208,7 +221,7 @@ class Interp:
                     self.base[dst_b] = acc
                 if dst_m >= 0:
                     Z = np.zeros((rows, self.K), complex)
-                    Z[idx, :] = acc * lc
+                    Z[idx, :] = acc * lc * (self.sym(lsym).real if lsym else 1.0)
                     if pad:
                         Z[ny // 2 + (rows - ny), :] = 0  # the Nyquist slot mapped by idx is zero anyway
                     z = np.fft.ifft(Z, axis=0) * rows
@@ -272,27 +285,18 @@ class Interp:
         self.run(P["inv_exit"], phys)
         return phys[2]
 
-    def depth_velocity(self, eta, psi, ys):
-        """(u, v, w) at depths ys, [L][3][ny][nx]; the layer kernels C, S in
-        the numerically stable exponential form, C = 1, S = 0 at k = 0."""
+    def depth_velocity(self, eta, psi, ys, chunk=None):
+        """(u, v, w) at depths ys, [L][3][ny][nx]: the potential on the flat
+        plane, then chunks of at most depth_chunk_max layers (or `chunk`)."""
         P = self._plan(self.dt if self.dt is not None else 1.0)
+        lc = min(P["depth_chunk_max"], chunk or P["depth_chunk_max"])
         out = np.zeros((len(ys), 3, self.ny, self.nx))
-        phys = [eta, psi, None, None]
-        self.run(P["lift_phi"], phys)
-        k = self.kk
-        for i, y in enumerate(ys):
-            e1 = np.exp(-k * y)
-            if self.depth > 0:
-                e2 = np.exp(-2 * k * (self.depth - y))
-                den = 1 + np.exp(-2 * k * self.depth)
-                C, S = e1 * (1 + e2) / den, k * e1 * (1 - e2) / den
-            else:
-                C, S = e1, k * e1
-            self.layer = (np.where(k == 0, 1.0, C), np.where(k == 0, 0.0, S))
-            phys = [eta, psi, out[i, 0], out[i, 2]]
-            self.run(P["layer_uw"], phys)
-            phys = [eta, psi, out[i, 1], None]
-            self.run(P["layer_v"], phys)
+        self.run(P["lift_phi"], [eta, psi, None, None])
+        for i0 in range(0, len(ys), lc):
+            r = min(lc, len(ys) - i0)
+            self.layer_y = list(ys[i0:i0 + r])
+            planes = out[i0:i0 + r].reshape(3 * r, self.ny, self.nx)
+            self.run(P["depth_chunk%d" % r], [eta, psi, planes, None])
         return out
 
     def step_ab2(self, eta, psi, dt, nsteps):

@@ -338,6 +338,7 @@ def test_inverse_dtn_parity(torch, M, boundary):
     (128, 128, TWO_PI, TWO_PI, None, "periodic", [0.0, 0.1, 0.5, 2.0]),
     (128, 64, 4.0, 2.0, 1.0, "periodic", [0.0, 0.3, 1.0]),
     (64, 64, 20.0, 20.0, 20.0, "reflect", [0.0, 2.0, 10.0, 20.0]),
+    (256, 128, 8.0, 4.0, 2.0, "periodic", list(np.linspace(0.0, 2.0, 37))),  # full chunks and a remainder
 ])
 def test_depth_velocity_parity(torch, nx, ny, Lx, Ly, depth, boundary, ys):
     """Bulk velocity at depth layers (Alg. ComputeVolumeVelFrom2D) against

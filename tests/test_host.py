@@ -118,16 +118,19 @@ def test_inverse_dtn_schedule_matches_oracle(M):
 def test_depth_velocity_schedule_matches_oracle(depth):
     """The depth-lift schedules (potential on the flat plane, then per layer
     the u, w and v lifts) executed literally equal the oracle's bulk
-    velocity at the surface plane, mid-depth and the bottom (or 1.5 deep)."""
+    velocity at seven depths from the surface plane to the bottom (or 1.5
+    deep), for every chunking of the layers."""
     nx, ny, Lx, Ly = 32, 16, 3.0, 2.0
     eta, psi = random_band_fields(nx, ny, 17, 7, amplitude=0.02)
     I = Interp(nx, ny, Lx, Ly, depth, 9.81, 3)
     m = HOSModel(Grid(nx, ny, Lx, Ly, depth), 3)
-    ys = [0.0, 0.2, depth if depth else 1.5]
-    got, ref = I.depth_velocity(eta, psi, ys), m.depth_velocity(eta, psi, ys)
-    for i in range(len(ys)):
-        for c in range(3):
-            assert rel(got[i, c], ref[i, c]) < 1e-13, (i, c)
+    d = depth if depth else 1.5
+    ys = [0.0, 0.2, d, 0.5 * d, 0.1, 0.7 * d, 0.3]
+    ref = m.depth_velocity(eta, psi, ys)
+    for chunk in (None, 1, 2, 3):  # full chunks, single layers, pairs, an odd chunk with a remainder
+        got = I.depth_velocity(eta, psi, ys, chunk)
+        for i in range(len(ys)):  # relative to the layer's largest component (v = 0 at a flat bottom)
+            assert np.max(np.abs(got[i] - ref[i])) < 1e-13 * np.max(np.abs(ref[i])), (chunk, i)
 
 
 # ---------------------------------------------------------------- the library
