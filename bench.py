@@ -414,40 +414,45 @@ def depth_velocity_form(w, nlayers=32, ncalls=10):
             "kernels": kern}
 
 
-PAPER_TANK_MS = {2: 6.352, 3: 13.52}  # Order 2 / Order 3, deep water, RTX 4090 (tab:wave_prop_time_comp)
+# ms per step of Orders 2 and 3 on an RTX 4090 (tab:wave_prop_time_comp): deep and shallow water
+PAPER_TANK_MS = {"deep": {2: 6.352, 3: 13.52}, "shallow": {2: 6.167, 3: 13.43}}
+TANK_CASES = {"deep": (20.0, 2.0), "shallow": (1.0, 1.0)}  # depth (m), bump amplitude A (m)
 
 
 def paper_tank(nsteps=2000):
     """The paper's wave-propagation timing workload (Sec. 8, tab:wave_prop_time_comp):
     20 m x 20 m tank, 128 x 128 cells, reflecting walls on all sides (even
-    extension to 256 x 256), depth 20 m, Gaussian bump A = 2 m, sigma = 1 m,
-    R = 6 m, at rest, eps = 1, IF-AB2 with dt = 0.01 s, 2000 steps, at Orders 2
-    and 3 (M = 2, 3); ms per step beside the paper's RTX 4090 figures."""
+    extension to 256 x 256), Gaussian bump sigma = 1 m, R = 6 m, at rest,
+    eps = 1, IF-AB2 with dt = 0.01 s, 2000 steps, at Orders 2 and 3 (M = 2, 3),
+    deep (20 m, A = 2 m) and shallow (1 m, A = 1 m); ms per step beside the
+    paper's RTX 4090 figures."""
     import torch
 
     from paper_2608_25203_amd.inputs import tank_bump
     from paper_2608_25203_amd.zk import Solver
 
     n, L, dt = 128, 20.0, 0.01
-    eta, psi = tank_bump(n, n, L, L, 2.0)
     dev = torch.device("cuda:0")
-    out = {"workload": "20 m tank, 128^2 cells, reflecting walls (256^2 extended), depth 20 m, Gaussian bump "
-                       "A = 2 m sigma = 1 m, at rest, eps = 1, IF-AB2 dt = 0.01 s, FP64",
+    out = {"workload": "20 m tank, 128^2 cells, reflecting walls (256^2 extended), Gaussian bump sigma = 1 m, "
+                       "R = 6 m, at rest, eps = 1, IF-AB2 dt = 0.01 s, FP64",
            "steps": nsteps}
-    for M in (2, 3):
-        s = Solver(n, n, L, L, 20.0, 9.81, M, check=False, device=dev, integrator="ifab2", boundary="reflect")
-        e, p = (torch.tensor(a, dtype=torch.float64, device=dev) for a in (eta, psi))
-        s.step(e.clone(), p.clone(), dt, 10)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.step(e, p, dt, nsteps)
-        torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0) / nsteps
-        out[f"order{M}"] = {"ms_per_step": round(ms, 4), "paper_ms_per_step_rtx4090": PAPER_TANK_MS[M],
-                            "speedup_vs_paper": round(PAPER_TANK_MS[M] / ms, 1),
-                            "finite": bool(torch.isfinite(e).all().item()),
-                            "max_eta": float(e.abs().max().item())}
-        s.close()
+    for case, (depth, A) in TANK_CASES.items():
+        eta, psi = tank_bump(n, n, L, L, A)
+        for M in (2, 3):
+            s = Solver(n, n, L, L, depth, 9.81, M, check=False, device=dev, integrator="ifab2", boundary="reflect")
+            e, p = (torch.tensor(a, dtype=torch.float64, device=dev) for a in (eta, psi))
+            s.step(e.clone(), p.clone(), dt, 10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(e, p, dt, nsteps)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / nsteps
+            ref = PAPER_TANK_MS[case][M]
+            out[f"{case}_order{M}"] = {"depth": depth, "A": A, "ms_per_step": round(ms, 4),
+                                       "paper_ms_per_step_rtx4090": ref, "speedup_vs_paper": round(ref / ms, 1),
+                                       "finite": bool(torch.isfinite(e).all().item()),
+                                       "max_eta": float(e.abs().max().item())}
+            s.close()
     return out
 
 
