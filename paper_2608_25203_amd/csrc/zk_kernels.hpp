@@ -1,23 +1,26 @@
 // zk_kernels.hpp -- row-pass and column-pass kernels of the HOS pipeline.
 //
 // Data layouts (all device memory carved from the caller's workspace):
-//   base spectrum   complex<double> [nx/2 / CBB][ny][CBB]: column kx (0 <= kx < nx/2,
-//                   the kx = nx/2 Nyquist column is not stored) tiled CBB wide,
-//                   index b = ky mode mod ny (b = ny/2 is the Nyquist row, kept 0).
-//   mixed field     complex<real> [nx/2 / CBM][rows][CBM]: y physical (rows =
+//   base spectrum   complex<double> [nx/2 / CBB][ny][CBB] with CBB = 1, i.e.
+//                   column-major: column kx (0 <= kx < nx/2; the kx = nx/2
+//                   Nyquist column is not stored) holds its ny ky modes
+//                   contiguously, index b = ky mode mod ny (b = ny/2 is the
+//                   Nyquist row, kept 0).
+//   mixed field     complex<real> [nx/2 / CB][rows][CB]: y physical (rows =
 //                   3ny/2 padded, or ny for the base transforms), kx spectral.
 //   caller fields   double [ny][nx] row-major.
-// A row team is T = nx/8 threads and owns one row; a column team is T = ny/8
-// threads and owns one kx column.  Every index below stays inside these
-// arrays when the host launches exactly rows/RPB x nprog row blocks and
-// ncols/CPB x ntask column blocks (checked on the host).
+// A row team of T threads owns one row, a column team one kx column; T and
+// the first-pass radix E are template parameters (T * E = transform length).
+// Every index below stays inside these arrays when the host launches exactly
+// rows / TPB x nprog row blocks and ncols / TPB x ntask column blocks
+// (checked on the host).
 #pragma once
 #include "zk_fft.hpp"
 #include "zk_program.hpp"
 
 namespace zk {
 
-constexpr int CBB = 4;  // tile width of base spectra (4 x 16 B = 64 B segments)
+constexpr int CBB = 1;  // tile width of base spectra: 1 = column-major, each column contiguous
 
 template <typename real>
 struct MixTile {
@@ -123,15 +126,36 @@ __device__ __forceinline__ int xcd_unit(int b, int nunits, int per) {
   return ((slot / per) * 8 + x) * per + (slot % per);
 }
 
-// Max over one team of T threads.  Teams of up to 64 threads sit inside one
-// wavefront and reduce with lane shuffles; larger teams (one per block) add
-// an LDS step across their wavefronts.  red: >= 4 floats of LDS.  Every
+// Max of a non-negative float over the 64 lanes of a wavefront, returned
+// to every lane: DPP row shifts build each 16-lane row's max in its last
+// lane, two row broadcasts carry it to lane 63, and a readlane hands it out.
+// Non-negative floats order like their bit patterns, so the max runs on
+// unsigned words; lanes whose DPP source lies outside the row read 0.
+__device__ __forceinline__ float wave_max(float x) {
+  unsigned v = __float_as_uint(x);
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = max(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return __uint_as_float((unsigned)__builtin_amdgcn_readlane((int)v, 63));
+}
+
+// Max over one team of T threads (non-negative values).  Teams of fewer than
+// 64 threads sit inside one wavefront and reduce with lane shuffles, a full
+// wavefront with wave_max; larger teams (one per block) add an LDS step
+// across their wavefronts.  red: >= 4 floats of LDS.  Every
 // thread of the block must call it.
 template <int T>
 __device__ __forceinline__ float team_max(float v, float *red) {
   constexpr int W = T < 64 ? T : 64;
+  if constexpr (W == 64) {
+    v = wave_max(v);
+  } else {
 #pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    for (int o = W / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  }
   if constexpr (T > 64) {
     const int w0 = (threadIdx.x / T) * (T / 64);  // first wavefront of this team
     __syncthreads();
@@ -149,10 +173,15 @@ __device__ __forceinline__ float team_max(float v, float *red) {
 template <int T>
 __device__ __forceinline__ float2 team_max2(float a, float b, float *red) {
   constexpr int W = T < 64 ? T : 64;
+  if constexpr (W == 64) {
+    a = wave_max(a);
+    b = wave_max(b);
+  } else {
 #pragma unroll
-  for (int o = W / 2; o > 0; o >>= 1) {
-    a = fmaxf(a, __shfl_xor(a, o, 64));
-    b = fmaxf(b, __shfl_xor(b, o, 64));
+    for (int o = W / 2; o > 0; o >>= 1) {
+      a = fmaxf(a, __shfl_xor(a, o, 64));
+      b = fmaxf(b, __shfl_xor(b, o, 64));
+    }
   }
   if constexpr (T > 64) {
     const int w0 = (threadIdx.x / T) * (T / 64);
@@ -211,6 +240,22 @@ struct Shape {
   }
 };
 
+// Schedule records (programs, ops, tasks, outputs, terms) are uniform across
+// a block and never written while a kernel runs: read them through the
+// constant address space so they arrive in scalar registers (scalar loads)
+// and the interpreter's dispatch is scalar branches, not masked lanes.
+template <typename Tp>
+__device__ __forceinline__ Tp uniform_load(const Tp *p) {
+  static_assert(sizeof(Tp) % 4 == 0, "schedule records are whole words");
+  const __attribute__((address_space(4))) uint32_t *q = (const __attribute__((address_space(4))) uint32_t *)p;
+  uint32_t w[sizeof(Tp) / 4];
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(Tp) / 4); ++k) w[k] = q[k];
+  Tp v;
+  __builtin_memcpy(&v, w, sizeof(Tp));
+  return v;
+}
+
 // One entry of a batched launch: the tile's argument record and the
 // program (row pass) or task (column pass) its blocks run.
 struct BatchItem {
@@ -234,7 +279,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   const int row = (S::TPB == 1 ? xcd_unit(blk, a.rows, 2) : blk) * S::TPB + team;
   cpx<real> *b0 = smem + team * NB * L;
   cpx<real> *b1 = b0 + (NB - 1) * L;
-  const RowProg pg = a.progs[prog];
+  const RowProg pg = uniform_load(a.progs + prog);
   const cpx<real> *tw = a.tw;
   if constexpr (TWL) {
     for (int i = threadIdx.x; i < N; i += 256) twl[i] = a.tw[i];
@@ -259,7 +304,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   };
 
   for (int i = 0; i < pg.nop; ++i) {
-    const RowOp op = a.ops[pg.op0 + i];
+    const RowOp op = uniform_load(a.ops + pg.op0 + i);
     switch (op.code) {
       case OP_LD2: {
         const cpx<real> *Fa = a.mix + (long long)op.fa * a.mix_stride;
@@ -299,11 +344,8 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
             ma = fmaxf(ma, ca[c]);
             mb = fmaxf(mb, cb[c]);
           }
-#pragma unroll
-          for (int o = 32; o > 0; o >>= 1) {
-            ma = fmaxf(ma, __shfl_xor(ma, o, 64));
-            mb = fmaxf(mb, __shfl_xor(mb, o, 64));
-          }
+          ma = wave_max(ma);
+          mb = wave_max(mb);
         }
         const float2 pa = pow2_scale(ma);
         const float2 pb = has_b ? pow2_scale(mb) : make_float2(1.f, 1.f);
@@ -520,7 +562,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   const int col = xcd_unit(blk, a.nx / 2 / S::TPB, CBMAX / S::TPB) * S::TPB + team;
   cpx<real> *b0 = smem + team * NB * L;
   cpx<real> *b1 = b0 + (NB - 1) * L;
-  const ColTask task = a.tasks[task_index];
+  const ColTask task = uniform_load(a.tasks + task_index);
   const int ny = a.ny;
   const cpx<real> *tw = a.tw;
   if constexpr (TWL) {
@@ -567,14 +609,14 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   }
 
   for (int o = 0; o < task.no; ++o) {
-    const ColOut out = a.outs[task.o0 + o];
+    const ColOut out = uniform_load(a.outs + task.o0 + o);
     cpx<double> acc[QB];
 #pragma unroll
     for (int q = 0; q < QB; ++q) acc[q] = {0.0, 0.0};
     // Base-spectrum terms: the next term's spectrum is loaded while the
     // current one is accumulated (one global latency per term instead of two).
     cpx<double> nxt[QB];
-    ColTerm ntm = out.nt > 0 ? a.terms[out.t0] : ColTerm{};
+    ColTerm ntm = out.nt > 0 ? uniform_load(a.terms + out.t0) : ColTerm{};
     auto fetch = [&](const ColTerm &tm2) {
       if (tm2.src >= 0) {
         const cpx<double> *B = a.base + (long long)tm2.src * a.base_stride;
@@ -589,7 +631,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
 #pragma unroll
       for (int q = 0; q < QB; ++q) cur[q] = nxt[q];
       if (i + 1 < out.nt) {
-        ntm = a.terms[out.t0 + i + 1];
+        ntm = uniform_load(a.terms + out.t0 + i + 1);
         fetch(ntm);
       }
       if (tm.src >= 0) {

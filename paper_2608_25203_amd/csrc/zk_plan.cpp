@@ -782,6 +782,13 @@ std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
       } else if (l.kind == L_COL_PAD || l.kind == L_COL_BASE) {
         if (l.first < 0 || l.count < 1 || l.first + l.count > (int)p.tasks.size()) return "col launch";
         if (l.c2 != 0 && !(l.c2 == 1 && l.kind == L_COL_BASE)) return "lift_sym variant on a padded pass";
+        // one lift per mixed field per launch (blocks of one launch run in any order)
+        std::vector<char> lifted(p.nmix, 0);
+        for (int k = l.first; k < l.first + l.count; ++k)
+          for (int i = 0; i < p.tasks[k].no; ++i) {
+            const int d = p.outs[p.tasks[k].o0 + i].dst_mixed;
+            if (d >= 0 && lifted[d]++) return "mixed field lifted twice in one launch";
+          }
         for (int k = l.first; k < l.first + l.count; ++k)
           for (int i = 0; i < p.tasks[k].no; ++i)
             if (p.outs[p.tasks[k].o0 + i].lift_sym && l.c2 != 1) return "lift_sym output in a plain column launch";
