@@ -72,9 +72,9 @@ void compute_layout(zk_ctx *c) {
   const size_t cs = 2 * rs;
   const int lens[4] = {3 * nx / 2, nx, 3 * ny / 2, ny};
   size_t off = 0;
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < 4; ++i) {  // kTwSlots pass-ordered tables per transform length
     c->off_tw[i] = off;
-    off = align_up(off + lens[i] * cs);
+    off = align_up(off + (size_t)kTwSlots * lens[i] * cs);
   }
   Plan probe = build_plan(c->pp, 1.0);
   c->sched_cap[0] = probe.ops.size();
@@ -131,12 +131,30 @@ void compute_layout(zk_ctx *c) {
   c->total = off;
 }
 
+// The kTwSlots pass-ordered twiddle tables of transform length n, one per
+// first-pass radix E of slot tw_slot(E) (see stage order in zk_fft.hpp):
+// entry Ns_p - E + (r-1) Ns_p + k of table E is W_n^(r k step_p), in long
+// double on the host.  A slot whose E does not give a valid team is unused.
 template <typename real>
 std::vector<cpx<real>> twiddles(int n) {
-  std::vector<cpx<real>> t(n);
-  for (int j = 0; j < n; ++j) {
-    const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)n;
-    t[j] = {(real)cosl(a), (real)sinl(a)};
+  std::vector<cpx<real>> t((size_t)kTwSlots * n, cpx<real>{(real)0, (real)0});
+  const long double two_pi = 2.0L * 3.14159265358979323846264338327950288L;
+  const bool pad = n % 3 == 0;
+  for (int s = 0; s < kTwSlots; ++s) {
+    const int E = pad ? 3 << s : 2 << s;
+    const int T = n / E;
+    if (n % E || T < 2 || (T & (T - 1)) || num_passes(T) < 2) continue;
+    cpx<real> *tab = t.data() + (size_t)s * n;
+    int ns = E;
+    for (int p = 1; p < num_passes(T); ++p) {
+      const int rp = later_radix(T, p), step = n / (ns * rp);
+      for (int r = 1; r < rp; ++r)
+        for (int k = 0; k < ns; ++k) {
+          const long double a = -two_pi * (long double)(r * k * step) / (long double)n;
+          tab[ns - E + (r - 1) * ns + k] = {(real)cosl(a), (real)sinl(a)};
+        }
+      ns *= rp;
+    }
   }
   return t;
 }

@@ -204,8 +204,17 @@ __host__ __device__ constexpr int lds_len(int N) { return N; }
 // buf0 and buf1 (one barrier per pass); NBUF = 1 works in place in buf0 (two
 // barriers per pass).  Returns the buffer holding the transform in natural
 // order (lpad-indexed); the final barrier is included, so every thread may
-// read any element.  tw[i] = exp(-2 pi i * i / N).  Every thread of the block
-// must call it.
+// read any element.  tw: the pass-ordered twiddle table of this (N, E).
+// Every thread of the block must call it.
+// Pass-ordered twiddles: the later passes p = 1 .. NP-1 of a team FFT with
+// first-pass radix E read W_N^(r k step_p) for r = 1 .. R_p-1 and
+// k = 0 .. Ns_p-1 (Ns_p = E R_1 ... R_(p-1), step_p = N / (Ns_p R_p)).  The
+// host stores them at Ns_p - E + (r-1) Ns_p + k (N - E entries), so a lane's
+// consecutive k read adjacent words instead of a stride of r step_p.  Each
+// transform length keeps one table per candidate E, slot tw_slot(E).
+constexpr int kTwSlots = 3;
+__host__ __device__ constexpr int tw_slot(int E) { return (E == 2 || E == 3) ? 0 : ((E == 4 || E == 6) ? 1 : 2); }
+
 template <typename R, int N, int E, int NBUF, int DIR>
 __device__ __forceinline__ cpx<R> *team_fft(cpx<R> (&v)[E], cpx<R> *buf0, cpx<R> *buf1,
                                             const cpx<R> *__restrict__ tw, int t) {
@@ -252,7 +261,7 @@ __device__ __forceinline__ cpx<R> *team_fft(cpx<R> (&v)[E], cpx<R> *buf0, cpx<R>
         constexpr int step = N / (Ns * Rp);
 #pragma unroll
         for (int r = 1; r < Rp; ++r) {
-          cpx<R> tr = tw[r * k * step];
+          cpx<R> tr = tw[Ns - E + (r - 1) * Ns + k];
           if constexpr (DIR > 0) tr.y = -tr.y;
           w[it][r] = cmul(w[it][r], tr);
         }

@@ -38,7 +38,7 @@ struct RowArgs {
   int nx;                // base-grid row length (physical fields)
   const double *pin0, *pin1, *pin2;  // OP_LDP slots 0..2
   double *pout0, *pout1;             // OP_STP slots 0..1
-  const cpx<real> *tw;    // exp(-2 pi i j / N), N = row FFT length
+  const cpx<real> *tw;    // kTwSlots pass-ordered twiddle tables of the row FFT length N
   double kx_scale;        // 2 pi / Lx
   const float *colmax;    // [mixed field][nx/2]: per-column max |value| written by the lifts
 };
@@ -60,7 +60,7 @@ struct ColArgs {
   cpx<double> *base;
   long long base_stride;
   int ny, nx;
-  const cpx<real> *tw;
+  const cpx<real> *tw;  // kTwSlots pass-ordered twiddle tables of the column FFT length
   double kx_scale, ky_scale;
   double depth;   // <= 0: deep water
   double inv_kc;  // 1 / kc of the taper
@@ -280,9 +280,9 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   cpx<real> *b0 = smem + team * NB * L;
   cpx<real> *b1 = b0 + (NB - 1) * L;
   const RowProg pg = uniform_load(a.progs + prog);
-  const cpx<real> *tw = a.tw;
+  const cpx<real> *tw = a.tw + tw_slot(E) * N;  // this shape's pass-ordered table
   if constexpr (TWL) {
-    for (int i = threadIdx.x; i < N; i += 256) twl[i] = a.tw[i];
+    for (int i = threadIdx.x; i < N - E; i += 256) twl[i] = tw[i];
     tw = twl;
   }
   __syncthreads();
@@ -564,9 +564,9 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   cpx<real> *b1 = b0 + (NB - 1) * L;
   const ColTask task = uniform_load(a.tasks + task_index);
   const int ny = a.ny;
-  const cpx<real> *tw = a.tw;
+  const cpx<real> *tw = a.tw + tw_slot(E) * N;  // this shape's pass-ordered table
   if constexpr (TWL) {
-    for (int i = threadIdx.x; i < N; i += 256) twl[i] = a.tw[i];
+    for (int i = threadIdx.x; i < N - E; i += 256) twl[i] = tw[i];
     tw = twl;
   }
   __syncthreads();
