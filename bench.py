@@ -107,10 +107,11 @@ def precision_form(segments=(1, 9, 90, 400)):
     eta, psi = jonswap_state(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"], w["kp"], w["steepness"],
                              w["seed"])
     dev = torch.device("cuda:0")
-    runs = {}
+    runs, shapes = {}, {}
     for prec in (64, 32):
         s = Solver(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"], w["M"], precision=prec, check=False,
                    device=dev)
+        shapes[prec] = {k: {"T": v[0], "E": v[1]} for k, v in s.autotune(w["dt"], reps=2).items()}
         e = torch.tensor(eta, dtype=torch.float64, device=dev)
         p = torch.tensor(psi, dtype=torch.float64, device=dev)
         ew, pw = e.clone(), p.clone()
@@ -145,7 +146,7 @@ def precision_form(segments=(1, 9, 90, 400)):
                         f"JONSWAP steepness {w['steepness']}, {nsteps} steps",
             "fp64_value": round(v64, 1), "fp32_value": round(v32, 1), "unit": "grid-point-steps/s",
             "speedup": round(v32 / v64, 3), "errors_vs_fp64": errs, "max_rel_err": worst,
-            "within_1e-4": bool(worst <= 1e-4)}
+            "within_1e-4": bool(worst <= 1e-4), "team_shapes": shapes}
 
 
 def closure_form(nsteps=1000, audit_every=10, tol=1e-4):
@@ -173,6 +174,8 @@ def closure_form(nsteps=1000, audit_every=10, tol=1e-4):
     full = Solver(n, n, L, L, w["depth"], w["g"], 6, check=False, device=dev)
     low64 = Solver(n, n, L, L, w["depth"], w["g"], 2, check=False, device=dev)
     low32 = Solver(n, n, L, L, w["depth"], w["g"], 2, precision=32, check=False, device=dev)
+    for sv in (full, low64, low32):
+        sv.autotune(dt, reps=2)
     net = Net(n * n, device=dev)
     net.set_params(params)
     clo64 = Closure(low64, full, net, meta["k0"], meta["eta_scale"], meta["out_scale"])

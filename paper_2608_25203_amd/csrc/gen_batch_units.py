@@ -4,7 +4,12 @@ any directory; the units are committed, this script regenerates them."""
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SHAPES = [(T, E) for T in (32, 64, 128, 256) for E in (2, 3, 4, 6, 8, 12)]
+SHAPES = ([(T, E) for T in (32, 64, 128, 256) for E in (2, 3, 4, 6, 8, 12)] + [(512, E) for E in (2, 3, 4, 6)]
+          + [(1024, E) for E in (2, 3)])
+
+
+def bs(T):
+    return max(256, T)
 
 for kind in ("row", "col"):
     for real, tag in (("double", "f64"), ("float", "f32")):
@@ -20,7 +25,7 @@ for kind in ("row", "col"):
                   "                                   const BatchItem *items, PhysArgs ph) {"]
         for T, E in SHAPES:
             lines.append(f"  if (T == {T} && E == {E}) {{")
-            lines.append(f"    hipLaunchKernelGGL(({kind}_kernel_batch<{real}, {T}, {E}>), grid, dim3(256), 0, s, args, items, ph);")
+            lines.append(f"    hipLaunchKernelGGL(({kind}_kernel_batch<{real}, {T}, {E}>), grid, dim3({bs(T)}), 0, s, args, items, ph);")
             lines.append("    return hipGetLastError();")
             lines.append("  }")
         lines += ["  return hipErrorInvalidValue;", "}", ""]
@@ -32,7 +37,7 @@ for kind in ("row", "col"):
                 if E % 3 == 0:
                     continue
                 lines.append(f"  if (T == {T} && E == {E}) {{")
-                lines.append(f"    hipLaunchKernelGGL((col_kernel_batch<{real}, {T}, {E}, true>), grid, dim3(256), 0, s, args, items, ph);")
+                lines.append(f"    hipLaunchKernelGGL((col_kernel_batch<{real}, {T}, {E}, true>), grid, dim3({bs(T)}), 0, s, args, items, ph);")
                 lines.append("    return hipGetLastError();")
                 lines.append("  }")
             lines += ["  return hipErrorInvalidValue;", "}", ""]

@@ -388,13 +388,16 @@ int crop_out(zk_ctx *c, int k, double *a) {
 namespace zk {
 
 TeamShape ctx_team(const zk_ctx *c, bool row, bool pad) {
-  // default T = min(256, n/2) threads per transform, or the autotuned shape;
-  // first-pass radix E = N / T; a 256-thread block holds 256 / T teams
+  // default: the smallest first-pass radix (E = 3 padded, 2 base), i.e.
+  // T = N / E threads per transform (at most 1024 for n <= 2048), or the
+  // autotuned shape; a block has max(256, T) threads, 256 / T teams when T < 256
   const int n = row ? c->pp.nx : c->pp.ny;
+  const int N = pad ? 3 * n / 2 : n;
   TeamShape sh;
-  sh.T = c->tuneT[row][pad] ? c->tuneT[row][pad] : std::min(256, n / 2);
-  sh.E = (pad ? 3 * n / 2 : n) / sh.T;
-  sh.blocks = row ? (pad ? 3 * c->pp.ny / 2 : c->pp.ny) / (256 / sh.T) : (c->pp.nx / 2) / (256 / sh.T);
+  sh.T = c->tuneT[row][pad] ? c->tuneT[row][pad] : N / (pad ? 3 : 2);
+  sh.E = N / sh.T;
+  const int tpb = sh.T < 256 ? 256 / sh.T : 1;
+  sh.blocks = row ? (pad ? 3 * c->pp.ny / 2 : c->pp.ny) / tpb : (c->pp.nx / 2) / tpb;
   return sh;
 }
 
@@ -796,7 +799,7 @@ int zk_autotune(zk_ctx *c, double dt, int reps) {
       int bestT = 0;
       for (int E : pad ? std::vector<int>{3, 6, 12} : std::vector<int>{2, 4, 8}) {
         const int T = N / E;
-        if (N % E || !(T == 32 || T == 64 || T == 128 || T == 256)) continue;
+        if (N % E || T < 32 || T > 1024 || (T & (T - 1))) continue;
         const void *fn = c->precision == 32 ? (row ? batch_row_kernel<float>(T, E) : batch_col_kernel<float>(T, E))
                                             : (row ? batch_row_kernel<double>(T, E) : batch_col_kernel<double>(T, E));
         if (!fn) continue;

@@ -96,14 +96,14 @@ const void *kernel_for(const zk_batch *b, bool row, int T, int E) {
 }
 
 // Candidate team shapes of a transform of length N (padded: E in {3, 6, 12};
-// base: E in {2, 4, 8}), T in {32, ..., 256} threads.
+// base: E in {2, 4, 8}), T in {32, ..., 1024} threads.
 std::vector<std::pair<int, int>> candidates(const zk_batch *b, bool row, bool pad, int n) {
   std::vector<std::pair<int, int>> out;
   const int N = pad ? 3 * n / 2 : n;
   for (int E : pad ? std::vector<int>{3, 6, 12} : std::vector<int>{2, 4, 8}) {
     if (N % E) continue;
     const int T = N / E;
-    if ((T == 32 || T == 64 || T == 128 || T == 256) && kernel_for(b, row, T, E)) out.push_back({T, E});
+    if (T >= 32 && T <= 1024 && !(T & (T - 1)) && kernel_for(b, row, T, E)) out.push_back({T, E});
   }
   return out;
 }
@@ -112,13 +112,13 @@ std::pair<int, int> shape_of(zk_batch *b, bool row, bool pad, int nx, int ny) {
   const Key k{row, pad, nx, ny};
   auto it = b->tune.find(k);
   if (it != b->tune.end()) return it->second;
-  const int n = row ? nx : ny;
-  const int T = std::min(256, n / 2);
-  return {T, (pad ? 3 * n / 2 : n) / T};
+  const int n = row ? nx : ny;  // default: the smallest first-pass radix (as a single context)
+  const int E = pad ? 3 : 2;
+  return {(pad ? 3 * n / 2 : n) / E, E};
 }
 
 int blocks_of(bool row, bool pad, int nx, int ny, int T) {
-  const int per = 256 / T;
+  const int per = T < 256 ? 256 / T : 1;
   return row ? (pad ? 3 * ny / 2 : ny) / per : (nx / 2) / per;
 }
 
@@ -178,7 +178,7 @@ int launch(zk_batch *b, const BL &l) {
   if (!fn) return fail(b, ZK_EINVAL, "team shape not built");
   PhysArgs ph{};
   void *params[] = {&args, &it, &ph};
-  HIP_TRY(b, hipLaunchKernel(fn, dim3(l.blocks, l.nitems), dim3(256), params, 0, b->stream));
+  HIP_TRY(b, hipLaunchKernel(fn, dim3(l.blocks, l.nitems), dim3(std::max(256, l.T)), params, 0, b->stream));
   return ZK_OK;
 }
 
@@ -207,7 +207,7 @@ int build_graph(zk_batch *b, int s) {
       hipKernelNodeParams p{};
       p.func = const_cast<void *>(fn);
       p.gridDim = dim3(l.blocks, l.nitems);
-      p.blockDim = dim3(256);
+      p.blockDim = dim3(std::max(256, l.T));
       p.sharedMemBytes = 0;
       p.kernelParams = params;
       p.extra = nullptr;

@@ -30,6 +30,12 @@ const void *batch_col_kernel<float>(int T, int E) {
   if (T == 256 && E == 6) return reinterpret_cast<const void *>(&col_kernel_batch<float, 256, 6>);
   if (T == 256 && E == 8) return reinterpret_cast<const void *>(&col_kernel_batch<float, 256, 8>);
   if (T == 256 && E == 12) return reinterpret_cast<const void *>(&col_kernel_batch<float, 256, 12>);
+  if (T == 512 && E == 2) return reinterpret_cast<const void *>(&col_kernel_batch<float, 512, 2>);
+  if (T == 512 && E == 3) return reinterpret_cast<const void *>(&col_kernel_batch<float, 512, 3>);
+  if (T == 512 && E == 4) return reinterpret_cast<const void *>(&col_kernel_batch<float, 512, 4>);
+  if (T == 512 && E == 6) return reinterpret_cast<const void *>(&col_kernel_batch<float, 512, 6>);
+  if (T == 1024 && E == 2) return reinterpret_cast<const void *>(&col_kernel_batch<float, 1024, 2>);
+  if (T == 1024 && E == 3) return reinterpret_cast<const void *>(&col_kernel_batch<float, 1024, 3>);
   return nullptr;
 }
 
@@ -132,6 +138,30 @@ hipError_t launch_batch_col<float>(int T, int E, dim3 grid, hipStream_t s, const
     hipLaunchKernelGGL((col_kernel_batch<float, 256, 12>), grid, dim3(256), 0, s, args, items, ph);
     return hipGetLastError();
   }
+  if (T == 512 && E == 2) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 512, 2>), grid, dim3(512), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 512 && E == 3) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 512, 3>), grid, dim3(512), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 512 && E == 4) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 512, 4>), grid, dim3(512), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 512 && E == 6) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 512, 6>), grid, dim3(512), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 1024 && E == 2) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 1024, 2>), grid, dim3(1024), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 1024 && E == 3) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 1024, 3>), grid, dim3(1024), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
   return hipErrorInvalidValue;
 }
 
@@ -184,6 +214,18 @@ hipError_t launch_batch_col_lift<float>(int T, int E, dim3 grid, hipStream_t s, 
   }
   if (T == 256 && E == 8) {
     hipLaunchKernelGGL((col_kernel_batch<float, 256, 8, true>), grid, dim3(256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 512 && E == 2) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 512, 2, true>), grid, dim3(512), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 512 && E == 4) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 512, 4, true>), grid, dim3(512), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 1024 && E == 2) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 1024, 2, true>), grid, dim3(1024), 0, s, args, items, ph);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;

@@ -30,6 +30,12 @@ const void *batch_row_kernel<double>(int T, int E) {
   if (T == 256 && E == 6) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 6>);
   if (T == 256 && E == 8) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 8>);
   if (T == 256 && E == 12) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 12>);
+  if (T == 512 && E == 2) return reinterpret_cast<const void *>(&row_kernel_batch<double, 512, 2>);
+  if (T == 512 && E == 3) return reinterpret_cast<const void *>(&row_kernel_batch<double, 512, 3>);
+  if (T == 512 && E == 4) return reinterpret_cast<const void *>(&row_kernel_batch<double, 512, 4>);
+  if (T == 512 && E == 6) return reinterpret_cast<const void *>(&row_kernel_batch<double, 512, 6>);
+  if (T == 1024 && E == 2) return reinterpret_cast<const void *>(&row_kernel_batch<double, 1024, 2>);
+  if (T == 1024 && E == 3) return reinterpret_cast<const void *>(&row_kernel_batch<double, 1024, 3>);
   return nullptr;
 }
 
@@ -130,6 +136,30 @@ hipError_t launch_batch_row<double>(int T, int E, dim3 grid, hipStream_t s, cons
   }
   if (T == 256 && E == 12) {
     hipLaunchKernelGGL((row_kernel_batch<double, 256, 12>), grid, dim3(256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 512 && E == 2) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 512, 2>), grid, dim3(512), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 512 && E == 3) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 512, 3>), grid, dim3(512), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 512 && E == 4) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 512, 4>), grid, dim3(512), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 512 && E == 6) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 512, 6>), grid, dim3(512), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 1024 && E == 2) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 1024, 2>), grid, dim3(1024), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 1024 && E == 3) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 1024, 3>), grid, dim3(1024), 0, s, args, items, ph);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;

@@ -145,7 +145,7 @@ __device__ __forceinline__ float wave_max(float x) {
 // Max over one team of T threads (non-negative values).  Teams of fewer than
 // 64 threads sit inside one wavefront and reduce with lane shuffles, a full
 // wavefront with wave_max; larger teams (one per block) add an LDS step
-// across their wavefronts.  red: >= 4 floats of LDS.  Every
+// across their wavefronts.  red: >= one float per wavefront of the block.  Every
 // thread of the block must call it.
 template <int T>
 __device__ __forceinline__ float team_max(float v, float *red) {
@@ -169,7 +169,7 @@ __device__ __forceinline__ float team_max(float v, float *red) {
 }
 
 // Max of two values over one team at once (same scheme as team_max).
-// red: >= 8 floats of LDS.
+// red: >= two floats per wavefront of the block.
 template <int T>
 __device__ __forceinline__ float2 team_max2(float a, float b, float *red) {
   constexpr int W = T < 64 ? T : 64;
@@ -227,7 +227,8 @@ struct Shape {
   static constexpr int KR = PADDED ? E / 3 : E / 2;    // positive slots
   static constexpr int NEG0 = PADDED ? 2 * E / 3 : E / 2;  // first negative slot
   static constexpr int QB = PADDED ? 2 * E / 3 : E;    // base-band elements per thread
-  static constexpr int TPB = 256 / T;                  // teams per 256-thread block
+  static constexpr int BS = T > 256 ? T : 256;          // threads per block
+  static constexpr int TPB = BS / T;                   // teams per block
   static constexpr int L = lds_len(N);
   // two LDS buffers per team when they fit comfortably, else one
   template <typename real>
@@ -272,7 +273,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   constexpr bool TWL = S::template tw_in_lds<real>();
   __shared__ cpx<real> smem[S::TPB * NB * L];
   __shared__ cpx<real> twl[TWL ? N : 1];
-  __shared__ float red[8];
+  __shared__ float red[2 * (S::BS / 64)];
   const int team = threadIdx.x / T;
   const int t = threadIdx.x % T;
   // rows y and y+1 share 128-byte lines of the tiled fields
@@ -282,7 +283,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   const RowProg pg = uniform_load(a.progs + prog);
   const cpx<real> *tw = a.tw + tw_slot(E) * N;  // this shape's pass-ordered table
   if constexpr (TWL) {
-    for (int i = threadIdx.x; i < N - E; i += 256) twl[i] = tw[i];
+    for (int i = threadIdx.x; i < N - E; i += S::BS) twl[i] = tw[i];
     tw = twl;
   }
   __syncthreads();
@@ -554,7 +555,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   constexpr bool TWL = S::template tw_in_lds<real>();
   __shared__ cpx<real> smem[S::TPB * NB * L];
   __shared__ cpx<real> twl[TWL ? N : 1];
-  __shared__ float red[8];
+  __shared__ float red[2 * (S::BS / 64)];
   const int team = threadIdx.x / T;
   const int t = threadIdx.x % T;
   // columns of one tile share 128-byte lines; keep a tile's blocks on one XCD
@@ -566,7 +567,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   const int ny = a.ny;
   const cpx<real> *tw = a.tw + tw_slot(E) * N;  // this shape's pass-ordered table
   if constexpr (TWL) {
-    for (int i = threadIdx.x; i < N - E; i += 256) twl[i] = tw[i];
+    for (int i = threadIdx.x; i < N - E; i += S::BS) twl[i] = tw[i];
     tw = twl;
   }
   __syncthreads();
@@ -700,7 +701,7 @@ struct PhysArgs {
 // (T, E), so blockIdx.x spans the same rows or columns for each.  A single
 // grid is the batch of one tile.
 template <typename real, int T, int E>
-__global__ __launch_bounds__(256) void row_kernel_batch(const RowArgs<real> *__restrict__ args,
+__global__ __launch_bounds__(T > 256 ? T : 256) void row_kernel_batch(const RowArgs<real> *__restrict__ args,
                                                         const BatchItem *__restrict__ items, PhysArgs ph) {
   const BatchItem it = items[blockIdx.y];
   RowArgs<real> a = args[it.tile];
@@ -716,7 +717,7 @@ __global__ __launch_bounds__(256) void row_kernel_batch(const RowArgs<real> *__r
 // LIFTSYM: the variant that applies ColOut.lift_sym (the bulk velocity
 // lift's column launches); the plain passes never carry its exponentials.
 template <typename real, int T, int E, bool LIFTSYM = false>
-__global__ __launch_bounds__(256) void col_kernel_batch(const ColArgs<real> *__restrict__ args,
+__global__ __launch_bounds__(T > 256 ? T : 256) void col_kernel_batch(const ColArgs<real> *__restrict__ args,
                                                         const BatchItem *__restrict__ items, PhysArgs) {
   const BatchItem it = items[blockIdx.y];
   const ColArgs<real> a = args[it.tile];
@@ -724,10 +725,12 @@ __global__ __launch_bounds__(256) void col_kernel_batch(const ColArgs<real> *__r
 }
 
 // Team shapes (T, E) compiled for the batched kernels: T in {32, 64, 128,
-// 256} threads and E in {2, 3, 4, 6, 8, 12}, so that each power-of-two length
-// n in [64, 2048] has one to three candidate shapes for its padded (3n/2)
-// and base (n) transforms; the autotuner picks among them.  These return the
-// kernel for (T, E), or nullptr if that shape is not built.
+// 256} threads with E in {2, 3, 4, 6, 8, 12}, and T = 512 (E in {2, 3, 4, 6})
+// and 1024 (E in {2, 3}) as blocks of their own, so that each power-of-two
+// length n in [64, 2048] has two to four candidate shapes for its padded
+// (3n/2) and base (n) transforms; the autotuner picks among them.  A block
+// has max(256, T) threads.  These return the kernel for (T, E), or nullptr if
+// that shape is not built.
 template <typename real>
 const void *batch_row_kernel(int T, int E);
 template <typename real>
