@@ -593,8 +593,9 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   cpx<double> X[QB];
 #pragma unroll
   for (int q = 0; q < QB; ++q) X[q] = {0.0, 0.0};
-  if (task.fwd >= 0) {
-    const cpx<real> *F = a.mix + (long long)task.fwd * a.mix_stride;
+  for (int f = 0; f < kMaxFolds; ++f) {
+    if (task.fwd[f] < 0) continue;
+    const cpx<real> *F = a.mix + (long long)task.fwd[f] * a.mix_stride;
     cpx<real> v[E];
 #pragma unroll
     for (int r = 0; r < E; ++r) v[r] = F[mix_index<real>(col, t + T * r, a.rows)];
@@ -602,12 +603,13 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       const cpx<real> w = res[lpad(pos_of(q))];
-      const cpx<double> sv = sym(task.fwd_sym, q);
-      const cpx<double> x = {(double)w.x * task.fwd_coef, (double)w.y * task.fwd_coef};
-      X[q] = {x.x * sv.x - x.y * sv.y, x.x * sv.y + x.y * sv.x};
+      const cpx<double> sv = sym(task.fwd_sym[f], q);
+      const cpx<double> x = {(double)w.x * task.fwd_coef[f], (double)w.y * task.fwd_coef[f]};
+      X[q].x += x.x * sv.x - x.y * sv.y;
+      X[q].y += x.x * sv.y + x.y * sv.x;
     }
-    if (t == 0) X[S::KR] = {0.0, 0.0};  // ky Nyquist row
   }
+  if (t == 0) X[S::KR] = {0.0, 0.0};  // ky Nyquist row
 
   for (int o = 0; o < task.no; ++o) {
     const ColOut out = uniform_load(a.outs + task.o0 + o);

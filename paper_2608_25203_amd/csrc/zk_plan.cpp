@@ -38,10 +38,17 @@ struct OutSpec {
   uint32_t lift_sym = 0;
 };
 
+struct FoldSpec {
+  int fwd;
+  uint32_t sym;
+  double coef;
+};
+
 struct TaskSpec {
-  int fwd = -1;
+  int fwd = -1;  // first fold
   uint32_t fwd_sym = 0;
   double fwd_coef = 1.0;
+  std::vector<FoldSpec> more;  // further folds summed into the same X
   std::vector<OutSpec> outs;
 };
 
@@ -148,9 +155,20 @@ class Builder {
   void add_tasks(const std::vector<TaskSpec> &ts) {
     for (auto &t : ts) {
       ColTask ct{};
-      ct.fwd = t.fwd;
-      ct.fwd_sym = t.fwd_sym;
-      ct.fwd_coef = t.fwd_coef;
+      if (t.more.size() + 1 > (size_t)kMaxFolds) throw std::runtime_error("too many folds in a task");
+      for (int f = 0; f < kMaxFolds; ++f) {
+        ct.fwd[f] = -1;
+        ct.fwd_sym[f] = 0;
+        ct.fwd_coef[f] = 0.0;
+      }
+      ct.fwd[0] = t.fwd;
+      ct.fwd_sym[0] = t.fwd_sym;
+      ct.fwd_coef[0] = t.fwd_coef;
+      for (size_t f = 0; f < t.more.size(); ++f) {
+        ct.fwd[f + 1] = t.more[f].fwd;
+        ct.fwd_sym[f + 1] = t.more[f].sym;
+        ct.fwd_coef[f + 1] = t.more[f].coef;
+      }
       ct.o0 = (int32_t)P.outs.size();
       ct.no = (int32_t)t.outs.size();
       for (auto &o : t.outs) {
@@ -371,21 +389,37 @@ Plan build_plan(const PlanParams &pp, double dt) {
     }
     return ts;
   };
-  auto g_terms = [&](int p) {
-    std::vector<TermSpec> tm{{p, 1u, 1.0}};
-    for (int r = 1; r <= M - 1; ++r) {
-      tm.push_back({bPHI[r], 1u, epow(r)});
-      tm.push_back({bWP[r], 0u, epow(r)});
-    }
-    if (hasGX1) tm.push_back({bGX[1], 0u, 1.0});
-    if (hasGXlast && M - 1 != 1) tm.push_back({bGX[M - 1], 0u, 1.0});
-    return tm;
-  };
   // levels 1..M-1 for stage state (e, p); ends with G stored (and lifted)
+  // The last level stores nothing but its PHI, WP and GX folds, which only G
+  // uses: one task folds all three (each with its G coefficient) into X and
+  // assembles G from X and the stored lower levels, in the same launch.
+  auto last_level_g = [&](int p, bool lift_g) {
+    const int r = M - 1;
+    TaskSpec t;
+    t.fwd = oPHI;
+    t.fwd_sym = SYM_TAPER | 1u;
+    t.fwd_coef = B.fold * epow(r);
+    t.more.push_back({oWP, SYM_TAPER, B.fold * kref * epow(r)});
+    if ((r == 1 && hasGX1) || (r == M - 1 && hasGXlast)) t.more.push_back({oGX, SYM_TAPER, B.fold});
+    std::vector<TermSpec> tm{{p, 1u, 1.0}};
+    for (int i = 1; i < r; ++i) {
+      tm.push_back({bPHI[i], 1u, epow(i)});
+      tm.push_back({bWP[i], 0u, epow(i)});
+    }
+    if (hasGX1 && r != 1) tm.push_back({bGX[1], 0u, 1.0});
+    tm.push_back({-1, 0u, 1.0});
+    t.outs.push_back(B.store(bG, tm));
+    if (lift_g) t.outs.push_back(B.lift(mG, tm));
+    return t;
+  };
   auto core = [&](std::vector<Launch> &seq, int e, int p, bool lift_g) {
     (void)e;
     for (int r = 1; r <= M - 1; ++r) {
       seq.push_back(row_launch(L_ROW_PAD, level_progs[r]));
+      if (r == M - 1) {
+        seq.push_back(B.col_launch(L_COL_PAD, {last_level_g(p, lift_g)}));
+        continue;
+      }
       std::vector<TaskSpec> A;
       {
         TaskSpec t = B.fold_task(oPHI);
@@ -426,12 +460,6 @@ Plan build_plan(const PlanParams &pp, double dt) {
         A.push_back(std::move(t));
       }
       seq.push_back(B.col_launch(L_COL_PAD, A));
-    }
-    if (M >= 2) {
-      TaskSpec t;
-      t.outs.push_back(B.store(bG, g_terms(p)));
-      if (lift_g) t.outs.push_back(B.lift(mG, g_terms(p)));
-      seq.push_back(B.col_launch(L_COL_PAD, {t}));
     }
   };
   auto entry = [&](std::vector<Launch> &seq) {
@@ -497,10 +525,38 @@ Plan build_plan(const PlanParams &pp, double dt) {
           ap.push_back({bAP, 0, 1.0});
           ae.push_back({bAE, 0, 1.0});
         }
+        const std::vector<TermSpec> pt{{bUP[par], 0, 1.0}, {se[s], 0, -g * c}, {-1, 0, c}};  // next stage psi
+        const std::vector<TermSpec> et{{bUE[par], 0, 1.0}, {bG, 0, c}};                      // next stage eta
         tp.outs.push_back(B.store(bAP, ap));
-        tp.outs.push_back(B.store(np[s], {{bUP[par], 0, 1.0}, {se[s], 0, -g * c}, {-1, 0, c}}));
+        tp.outs.push_back(B.store(np[s], pt));
         te.outs.push_back(B.store(bAE, ae));
-        te.outs.push_back(B.store(ne[s], {{bUE[par], 0, 1.0}, {bG, 0, c}}));
+        te.outs.push_back(B.store(ne[s], et));
+        if (M >= 2) {
+          // The next stage's lifts in the same launch, each from the stage
+          // combination itself (the tasks that need the folded N fold it
+          // again): one launch instead of two.  (M = 1 stores G from psi in
+          // its lift launch, which te's read of this stage's G forbids.)
+          auto with = [](std::vector<TermSpec> tm, uint32_t sym, double f) {
+            for (auto &x : tm) {
+              x.sym |= sym;
+              x.coef *= f;
+            }
+            return tm;
+          };
+          tp.outs.push_back(B.lift(mP, with(pt, 0, 1.0)));
+          tp.outs.push_back(B.lift(mPy, with(pt, SYM_IKY, 1.0)));
+          te.outs.push_back(B.lift(mE, with(et, 0, kref)));
+          te.outs.push_back(B.lift(mEy, with(et, SYM_IKY, 1.0)));
+          std::vector<TaskSpec> ts{tp, te};
+          for (int l = 1; l <= M; l += 2) {
+            TaskSpec tl = B.fold_task(mN);
+            for (int m = l; m <= std::min(M, l + 1); ++m)
+              tl.outs.push_back(B.lift(mL[m], with(pt, (uint32_t)m, 1.0 / kpow(m))));
+            ts.push_back(tl);
+          }
+          seq.push_back(B.col_launch(L_COL_PAD, ts));
+          continue;
+        }
       } else {
         const double h = dt / 6.0;
         tp.outs.push_back(B.store(np[s], {{bUP[par], FILT, 1.0}, {bAP, FILT, h}, {se[s], FILT, -g * h}, {-1, FILT, h}}));
@@ -682,10 +738,11 @@ Plan build_plan(const PlanParams &pp, double dt) {
           const double rows = l.kind == L_COL_PAD ? rows_pad : rows_base;
           for (int k = l.first; k < l.first + l.count; ++k) {
             const ColTask &t = P.tasks[k];
-            if (t.fwd >= 0) {
-              l.bytes += rows * K * cb;
-              l.flops += K * fft_flops(rows);
-            }
+            for (int f = 0; f < kMaxFolds; ++f)
+              if (t.fwd[f] >= 0) {
+                l.bytes += rows * K * cb;
+                l.flops += K * fft_flops(rows);
+              }
             for (int i = 0; i < t.no; ++i) {
               const ColOut &o = P.outs[t.o0 + i];
               for (int j = 0; j < o.nt; ++j)
@@ -757,7 +814,8 @@ std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
     }
   }
   for (auto &t : p.tasks) {
-    if (t.fwd >= p.nmix) return bad("task fwd");
+    for (int f = 0; f < kMaxFolds; ++f)
+      if (t.fwd[f] >= p.nmix || (f > 0 && t.fwd[f] >= 0 && t.fwd[0] < 0)) return bad("task fwd");
     if (t.o0 < 0 || t.no < 0 || t.o0 + t.no > (int)p.outs.size()) return bad("task outs");
     for (int i = 0; i < t.no; ++i) {
       const ColOut &o = p.outs[t.o0 + i];
@@ -766,7 +824,7 @@ std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
       for (int k = 0; k < o.nt; ++k) {
         const ColTerm &tm = p.terms[o.t0 + k];
         if (tm.src >= p.nbase) return bad("term src");
-        if (tm.src < 0 && t.fwd < 0) return bad("term uses missing fold");
+        if (tm.src < 0 && t.fwd[0] < 0) return bad("term uses missing fold");
       }
     }
   }

@@ -62,7 +62,9 @@ int main(int argc, char **argv) {
                 p.outs[i].nt, p.outs[i].lift_coef, p.outs[i].lift_sym);
   std::printf("],\n\"tasks\": [");
   for (size_t i = 0; i < p.tasks.size(); ++i)
-    std::printf("%s[%d,%u,%.17g,%d,%d]", i ? "," : "", p.tasks[i].fwd, p.tasks[i].fwd_sym, p.tasks[i].fwd_coef,
+    std::printf("%s[[%d,%d,%d],[%u,%u,%u],[%.17g,%.17g,%.17g],%d,%d]", i ? "," : "", p.tasks[i].fwd[0],
+                p.tasks[i].fwd[1], p.tasks[i].fwd[2], p.tasks[i].fwd_sym[0], p.tasks[i].fwd_sym[1],
+                p.tasks[i].fwd_sym[2], p.tasks[i].fwd_coef[0], p.tasks[i].fwd_coef[1], p.tasks[i].fwd_coef[2],
                 p.tasks[i].o0, p.tasks[i].no);
   std::printf("],\n\"chk\": [%d,%d,%d,%d],\n", p.chk_e[0], p.chk_p[0], p.chk_e[1], p.chk_p[1]);
   dump_seq("dtn", p.dtn, false);

@@ -72,7 +72,7 @@ constexpr int kMaxChunkLayers = 16;       // depth layers lifted per column/row 
 constexpr int kIfCoefs = 6;
 
 struct ColTerm {
-  int32_t src;   // base-spectrum id, or -1 = result of the task's forward FFT
+  int32_t src;   // base-spectrum id, or -1 = the task's folded sum X
   uint32_t sym;
   double coef;
 };
@@ -86,12 +86,15 @@ struct ColOut {
   uint32_t pad_;
 };
 
+// A column task folds up to kMaxFolds mixed fields (forward y-FFT, band
+// truncation), each times its symbol and scale, into one sum X that its
+// outputs' terms may use (src = -1).
+constexpr int kMaxFolds = 3;
 struct ColTask {
-  int32_t fwd;       // mixed-field id to fold (forward y-FFT + band + taper), or -1
-  uint32_t fwd_sym;  // symbol applied to the folded result
-  double fwd_coef;   // scale applied to the folded result
-  int32_t o0, no;    // outputs [o0, o0 + no)
-  int32_t pad0, pad1;
+  int32_t fwd[kMaxFolds];       // mixed-field ids to fold, or -1
+  uint32_t fwd_sym[kMaxFolds];  // symbol applied to each folded field
+  double fwd_coef[kMaxFolds];   // scale applied to each folded field
+  int32_t o0, no;               // outputs [o0, o0 + no)
 };
 
 }  // namespace zk

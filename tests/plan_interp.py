@@ -204,11 +204,15 @@ class Interp:
         idx = np.where(b < ny // 2, b, b + (rows - ny))
         P = self.plan
         for ti in range(first, first + count):
-            fwd, fsym, fcoef, o0, no = P["tasks"][ti]
+            fwds, fsyms, fcoefs, o0, no = P["tasks"][ti]
             X = None
-            if fwd >= 0:
+            for fwd, fsym, fcoef in zip(fwds, fsyms, fcoefs):  # folds summed into X
+                if fwd < 0:
+                    continue
                 V = np.fft.fft(self.mix[fwd][:rows, :], axis=0)
-                X = V[idx, :] * fcoef * self.sym(fsym)
+                Xf = V[idx, :] * fcoef * self.sym(fsym)
+                X = Xf if X is None else X + Xf
+            if X is not None:
                 X[ny // 2, :] = 0
             for oi in range(o0, o0 + no):
                 dst_b, dst_m, t0, nt, lc, lsym = P["outs"][oi]
