@@ -92,13 +92,21 @@ class Builder {
   void mac(int out, uint8_t x, uint8_t y, double c) { op(OP_MAC, (uint8_t)(RS_O0 + out), x, y, -1, 0, -1, 0, c); }
 
   // One program computing sum-of-products outputs (at most 3) and storing
-  // them to the mixed fields outf[].  Greedy: take the factor shared by the
-  // most products, load it with its first partner, hold it in A, then load
-  // the remaining partners in pairs.
+  // them to the mixed fields outf[].  Products are grouped by a held factor,
+  // greedily the factor shared by the most products; the groups' factors
+  // and their partners form one load stream, [x1, y11, y12, ..., x2, y21,
+  // ...], loaded two at a time, so a group's last partner may share its
+  // transform with the next group's factor.  A holds the current group's
+  // factor while partners arrive in later transforms.
   int product_program(std::vector<Prod> prods, const std::vector<int> &outf) {
     if (outf.empty() || outf.size() > 3) throw std::runtime_error("program outputs");
     const int pg = prog_begin();
     for (size_t k = 0; k < outf.size(); ++k) op(OP_ZERO, (uint8_t)(RS_O0 + k), 0, 0, -1, 0, -1, 0, 0.0);
+    struct Group {
+      Fac x;
+      std::vector<Prod> partners, self;  // partners: x is .a
+    };
+    std::vector<Group> groups;
     while (!prods.empty()) {
       std::map<Fac, int> cnt;
       for (auto &p : prods) {
@@ -112,35 +120,54 @@ class Builder {
           best = kv.second;
           x = kv.first;
         }
-      std::vector<Prod> nonself, self, rest;
+      Group g{x, {}, {}};
       std::vector<Prod> keep;
       for (auto &p : prods) {
-        if (p.a == x && p.b == x) self.push_back(p);
-        else if (p.a == x) nonself.push_back(p);
-        else if (p.b == x) nonself.push_back({p.b, p.a, p.out, p.coef});
+        if (p.a == x && p.b == x) g.self.push_back(p);
+        else if (p.a == x) g.partners.push_back(p);
+        else if (p.b == x) g.partners.push_back({p.b, p.a, p.out, p.coef});
         else keep.push_back(p);
       }
-      if (!nonself.empty()) {
-        const Prod &f = nonself[0];
-        ld2(x, f.b.f, f.b.fl);
-        mac(f.out, RS_U, RS_V, f.coef);
-        rest.assign(nonself.begin() + 1, nonself.end());
-      } else {
-        ld2(x, -1, 0);
-      }
-      if (!self.empty() || !rest.empty()) op(OP_MOV, RS_A, RS_U, 0, -1, 0, -1, 0, 0.0);
-      for (auto &p : self) mac(p.out, RS_A, RS_A, p.coef);
-      for (size_t i = 0; i < rest.size(); i += 2) {
-        if (i + 1 < rest.size()) {
-          ld2(rest[i].b, rest[i + 1].b.f, rest[i + 1].b.fl);
-          mac(rest[i].out, RS_A, RS_U, rest[i].coef);
-          mac(rest[i + 1].out, RS_A, RS_V, rest[i + 1].coef);
+      groups.push_back(g);
+      prods.swap(keep);
+    }
+    struct Item {
+      Fac f;
+      int group, partner;  // partner = -1: the group's held factor
+    };
+    std::vector<Item> items;
+    for (int gi = 0; gi < (int)groups.size(); ++gi) {
+      items.push_back({groups[gi].x, gi, -1});
+      for (int k = 0; k < (int)groups[gi].partners.size(); ++k) items.push_back({groups[gi].partners[k].b, gi, k});
+    }
+    int in_a = -1;                // group whose factor A holds
+    int hold_group = -1, hold_reg = -1;  // a factor loaded in this transform's U or V
+    for (size_t i = 0; i < items.size(); i += 2) {
+      const bool two = i + 1 < items.size();
+      ld2(items[i].f, two ? items[i + 1].f.f : -1, two ? items[i + 1].f.fl : 0);
+      hold_group = -1;
+      for (size_t j = i; j < i + (two ? 2 : 1); ++j) {
+        const Item &it = items[j];
+        const uint8_t reg = j == i ? RS_U : RS_V;
+        const Group &g = groups[it.group];
+        if (it.partner < 0) {  // the group's factor: self products, keep it if partners follow
+          for (auto &p : g.self) mac(p.out, reg, reg, p.coef);
+          hold_group = it.group;
+          hold_reg = reg;
+          bool later = false;
+          for (size_t k = j + 1; k < items.size(); ++k)
+            if (items[k].group == it.group && k >= i + 2) later = true;
+          if (later) {
+            op(OP_MOV, RS_A, reg, 0, -1, 0, -1, 0, 0.0);
+            in_a = it.group;
+          }
         } else {
-          ld2(rest[i].b, -1, 0);
-          mac(rest[i].out, RS_A, RS_U, rest[i].coef);
+          const Prod &p = g.partners[it.partner];
+          const uint8_t h = (hold_group == it.group) ? (uint8_t)hold_reg : RS_A;
+          if (h == RS_A && in_a != it.group) throw std::runtime_error("product schedule lost its held factor");
+          mac(p.out, h, reg, p.coef);
         }
       }
-      prods.swap(keep);
     }
     for (size_t k = 0; k < outf.size(); k += 2) {
       if (k + 1 < outf.size())
