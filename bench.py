@@ -522,6 +522,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default team shapes")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision-form (2048^2 M=5), closure-form (1024^2) and batch-form (256 tiles) runs")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed benchmark run and its instrumented pass (no diagnostics or forms; for profiling)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -622,7 +624,9 @@ def main():
         "team_shapes": {k: {"T": v[0], "E": v[1]} for k, v in shapes.items()},
         "finite": finite,
     }
-    if args.workload == "c2_512_m4":
+    if args.headline_only:
+        args.no_forms = args.no_cpu_baseline = True
+    elif args.workload == "c2_512_m4":
         out["c2_diagnostics"] = c2_diagnostics(w, H_before, H_after)
         out["c2_diagnostics"]["H_before"] = H_before
         out["ifab2_form"] = ifab2_form(w, args.warmup, args.steps, value, e_timed)
