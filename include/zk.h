@@ -208,6 +208,14 @@ int zk_autotune(zk_ctx *ctx, double dt, int reps);
  * transform). */
 int zk_team_shape(const zk_ctx *ctx, int row, int pad, int *T, int *E);
 
+/* Choose the team shape of a pass kind by hand (the autotuner's setting):
+ * T threads per transform, first-pass radix E = N / T for the pass's
+ * transform length N (3n/2 padded, n base).  T = 0 restores the default.
+ * ZK_EINVAL if T does not divide N into a compiled shape (T a power of two
+ * in [32, 1024]; E in {3, 6, 12} padded or {2, 4, 8} base, and the pair
+ * built for the context's precision).  Host only; applies from the next call. */
+int zk_set_team_shape(zk_ctx *ctx, int row, int pad, int T);
+
 /* Text of the last error on this context ("" if none).  Valid until the next
  * call on the context. */
 const char *zk_last_error(const zk_ctx *ctx);

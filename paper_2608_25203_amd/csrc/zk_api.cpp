@@ -835,6 +835,27 @@ int zk_team_shape(const zk_ctx *c, int row, int pad, int *T, int *E) {
   return ZK_OK;
 }
 
+int zk_set_team_shape(zk_ctx *c, int row, int pad, int T) {
+  if (!c) return ZK_EINVAL;
+  c->err.clear();
+  row = row != 0;
+  pad = pad != 0;
+  if (T == 0) {  // back to the default shape
+    c->tuneT[row][pad] = 0;
+    return ZK_OK;
+  }
+  const int n = row ? c->pp.nx : c->pp.ny;
+  const int N = pad ? 3 * n / 2 : n;
+  if (T < 32 || T > 1024 || (T & (T - 1)) || N % T) return fail(c, ZK_EINVAL, "team size must divide the transform length");
+  const int E = N / T;
+  const void *fn = c->precision == 32 ? (row ? batch_row_kernel<float>(T, E) : batch_col_kernel<float>(T, E))
+                                      : (row ? batch_row_kernel<double>(T, E) : batch_col_kernel<double>(T, E));
+  if (!fn || !(pad ? (E == 3 || E == 6 || E == 12) : (E == 2 || E == 4 || E == 8)))
+    return fail(c, ZK_EINVAL, "team shape not built");
+  c->tuneT[row][pad] = T;
+  return ZK_OK;
+}
+
 const char *zk_last_error(const zk_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 }  // extern "C"

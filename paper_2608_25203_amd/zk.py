@@ -23,7 +23,7 @@ KERNEL_NAMES = {0: "row_pad", 1: "row_base", 2: "col_pad", 3: "col_base", 4: "re
 
 EXPORTS = ("zk_create", "zk_destroy", "zk_set_option", "zk_workspace_bytes", "zk_bind", "zk_dtn",
            "zk_rhs", "zk_step", "zk_hamiltonian", "zk_kernel_stats", "zk_autotune", "zk_team_shape", "zk_inverse_dtn",
-           "zk_depth_velocity", "zk_last_error",
+           "zk_depth_velocity", "zk_set_team_shape", "zk_last_error",
            "zk_cnn_create", "zk_cnn_destroy", "zk_cnn_workspace_bytes", "zk_cnn_bind", "zk_cnn_set_params",
            "zk_cnn_get_params", "zk_cnn_forward", "zk_cnn_gradient", "zk_cnn_train_step", "zk_cnn_last_error",
            "zk_closure_create", "zk_closure_destroy", "zk_closure_workspace_bytes", "zk_closure_bind",
@@ -85,6 +85,8 @@ def lib():
     L.zk_depth_velocity.restype = i
     L.zk_autotune.argtypes = [vp, d, i]
     L.zk_autotune.restype = i
+    L.zk_set_team_shape.argtypes = [vp, i, i, i]
+    L.zk_set_team_shape.restype = i
     L.zk_team_shape.argtypes = [vp, i, i, ctypes.POINTER(i), ctypes.POINTER(i)]
     L.zk_team_shape.restype = i
     L.zk_last_error.argtypes = [vp]
@@ -286,6 +288,10 @@ class Solver:
         """Time the compiled team shapes of every pass kind on one step and keep the fastest."""
         _check(self.ctx, lib().zk_autotune(self.ctx, float(dt), int(reps)))
         return self.team_shapes()
+
+    def set_team_shape(self, row, pad, T):
+        """Team size T of one pass kind (0 = default)."""
+        _check(self.ctx, lib().zk_set_team_shape(self.ctx, int(bool(row)), int(bool(pad)), int(T)))
 
     def team_shapes(self):
         out = {}

@@ -365,3 +365,30 @@ def test_depth_velocity_parity(torch, nx, ny, Lx, Ly, depth, boundary, ys):
         err = np.max(np.abs(got[i] - ref[i])) / np.max(np.abs(ref[i]))
         print(f"  layer y = {ys[i]}: rel err {err:.3e}", flush=True)
         assert err < 1e-10
+
+
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_every_team_shape_keeps_parity(torch, n):
+    """Every compiled team shape of the 1024^2 and 2048^2 transforms (the
+    512- and 1024-thread teams included), set by hand for all four pass
+    kinds at once, gives the oracle's RHS: FP64 to 1e-10, FP32 to 2e-5."""
+    from oracle.hos import PocketDFT
+
+    M, L = 3, TWO_PI
+    eta, psi = jonswap_state(n, n, L, L, None, 9.81, n / 32, 0.1, 5)
+    m = HOSModel(Grid(n, n, L, L, None, dft=PocketDFT(workers=16)), M)
+    a0, b0 = m.rhs(eta, psi)
+    for prec, tol in ((64, 1e-10), (32, 2e-5)):
+        s = solver(torch, n, n, L, L, None, M, precision=prec)
+        e, p = dev(torch, eta), dev(torch, psi)
+        for k in range(3):
+            for row in (1, 0):
+                for pad in (1, 0):
+                    N = 3 * n // 2 if pad else n
+                    s.set_team_shape(row, pad, N // ((3, 6, 12) if pad else (2, 4, 8))[k])
+            print(f"  fp{prec} {s.team_shapes()}", flush=True)
+            a, b = s.rhs(e, p)
+            assert rel(host(a), a0) < tol and rel(host(b), b0) < tol
+        s.close()
+        del s
+        torch.cuda.empty_cache()

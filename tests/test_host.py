@@ -174,6 +174,14 @@ def test_library_host_side_argument_checks():
     assert L.zk_dtn(ctx, None, None, None) == zk.ZK_ENOWS
     assert L.zk_inverse_dtn(ctx, None, None, None, 8) == zk.ZK_ENOWS
     assert L.zk_depth_velocity(ctx, None, None, 1, None, None) == zk.ZK_ENOWS
+    # team shapes by hand: T must split the transform (768 padded, 512 base) into a built shape
+    for row, pad, T, ok in ((1, 1, 256, True), (1, 1, 128, True), (1, 1, 64, True), (1, 1, 512, False),
+                            (1, 1, 32, False), (0, 0, 256, True), (0, 0, 64, True), (0, 0, 512, False),
+                            (0, 0, 100, False), (1, 0, 0, True)):
+        assert (L.zk_set_team_shape(ctx, row, pad, T) == 0) == ok, (row, pad, T)
+    T, E = ctypes.c_int(0), ctypes.c_int(0)
+    assert L.zk_set_team_shape(ctx, 1, 1, 128) == 0
+    assert L.zk_team_shape(ctx, 1, 1, ctypes.byref(T), ctypes.byref(E)) == 0 and (T.value, E.value) == (128, 6)
     L.zk_destroy(ctx)
 
 
