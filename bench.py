@@ -59,7 +59,7 @@ def cpu_baseline(w, eta, psi, nsteps):
 
 
 def kernel_source_hash():
-    """Hash of the HIP kernel sources: counter records apply to this build only."""
+    """Hash of the HIP kernel sources: a counter record applies to the sources it was taken on."""
     import hashlib
 
     h = hashlib.sha256()
@@ -539,7 +539,7 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus 1).", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path (--gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -286,7 +286,7 @@ const char *zk_cnn_last_error(const zk_cnn *net);
  * modes removed), then the state filter A(k) (Sec. 3.4).  The residual is
  * linear in psi for fixed eta, as the DtN operator is; the psi-scale s makes
  * the network see that exactly.  The full-order context is the closure's
- * fallback and the judge of its error: an audit at the first step and every
+ * fallback and the reference for its error: an audit at the first step and every
  * audit_every steps computes e = ||G_closure - G^[full] psi||_2 /
  * ||G^[full] psi||_2 on the current state; while e > tol the next
  * audit_every steps are taken by the full-order context (zk_step), else by

@@ -12,6 +12,6 @@ Modules
 hos      grid, DFT backends, dealiased product, Craig-Sulem/HOS DtN series,
          Bernoulli term, Zakharov RHS, RK4 + state filter, Hamiltonian.
 laplace  dense direct Laplace solve of the Dirichlet-Neumann problem, the
-         independent judge of the series (no series arithmetic inside).
+         independent check of the series (no series arithmetic inside).
 cnn      plain im2col CNN (forward, backward, Adam) for the learned closure.
 """

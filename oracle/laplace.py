@@ -4,7 +4,7 @@ The DNO G(eta) psi is defined by a harmonic extension (Sec. 3.1, eq:dno_def):
 Phi harmonic in -h <= z <= eta(x), Phi = psi on z = eta, d_z Phi = 0 on the
 bed, G(eta) psi = sqrt(1 + |grad eta|^2) d_n Phi = Phi_z - grad eta . grad_h Phi
 at the surface.  This module solves that Laplace problem directly -- no series,
-no products, no dealiasing -- so it can judge the HOS series independently.
+no products, no dealiasing -- so it checks the HOS series independently.
 
 Discretisation: the fluid column is mapped to s = (z + h) / D in [0, 1],
 D = h + eta, Phi(x, z) = u(x, s).  With a_a = -s eta_a / D the Laplacian is

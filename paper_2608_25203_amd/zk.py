@@ -420,7 +420,7 @@ class Net:
 # ---- learned-closure stepper ----------------------------------------------------------
 class Closure:
     """zk_closure_* over a low-order Solver, an optional full-order Solver
-    (fallback and judge) and a Net, all on one device stream."""
+    (fallback and error reference) and a Net, all on one device stream."""
 
     def __init__(self, low, full, net, k0, eta_scale, out_scale):
         import torch

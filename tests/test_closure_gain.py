@@ -1,4 +1,4 @@
-"""What the trained closure gains over order 2 alone, judged by the oracle
+"""What the trained closure gains over order 2 alone, measured by the oracle
 alone (no HIP code): the network's parameters (trained on the GPU, stored
 in the package) are evaluated by the numpy network of oracle/cnn.py on a
 small periodic domain with the training grid spacing (2 pi / 1024) and the
