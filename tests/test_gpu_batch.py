@@ -26,6 +26,7 @@ TILES = [
     dict(nx=256, ny=256, Lx=50.0, Ly=50.0, depth=8.0, M=5),
     dict(nx=64, ny=64, Lx=1.0, Ly=1.0, depth=0.3, M=1),
     dict(nx=128, ny=128, Lx=2 * math.pi, Ly=2 * math.pi, depth=math.inf, M=3),
+    dict(nx=1024, ny=512, Lx=8.0, Ly=4.0, depth=2.0, M=3),  # 512- and 1024-thread team candidates
 ]
 DT = 0.004
 
