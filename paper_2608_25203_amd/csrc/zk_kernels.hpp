@@ -389,32 +389,41 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         }
         break;
       }
-      case OP_MOV: {
-        with_any(op.a, [&](auto D) {
-          with_any(op.b, [&](auto Sx) {
+      // MOV, MAC and ZERO write their targets without a branch on the target
+      // register: a switch per target would make the compiler copy every
+      // register set at each merge of the interpreter loop.
+      case OP_MOV: {  // A <- u, v or A
+        real m[E];
+        with_in(op.b, [&](auto Sx) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) reg(D, e) = reg(Sx, e);
-          });
+          for (int e = 0; e < E; ++e) m[e] = reg(Sx, e);
         });
+#pragma unroll
+        for (int e = 0; e < E; ++e) R[RS_A - 2][e] = m[e];
         break;
       }
-      case OP_MAC: {
+      case OP_MAC: {  // o[a] += coef * x * y, as weighted adds to all three outputs
         const real c = (real)op.coef;
-        with_out(op.a, [&](auto D) {
-          with_in(op.b, [&](auto X) {
-            with_in(op.c, [&](auto Y) {
+        const real w0 = op.a == RS_O0 ? c : (real)0, w1 = op.a == RS_O1 ? c : (real)0,
+                   w2 = op.a == RS_O2 ? c : (real)0;
+        real pr[E];
+        with_in(op.b, [&](auto X) {
+          with_in(op.c, [&](auto Y) {
 #pragma unroll
-              for (int e = 0; e < E; ++e) reg(D, e) += c * reg(X, e) * reg(Y, e);
-            });
+            for (int e = 0; e < E; ++e) pr[e] = reg(X, e) * reg(Y, e);
           });
         });
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          R[RS_O0 - 2][e] += w0 * pr[e];
+          R[RS_O1 - 2][e] += w1 * pr[e];
+          R[RS_O2 - 2][e] += w2 * pr[e];
+        }
         break;
       }
-      case OP_ZERO: {
-        with_any(op.a, [&](auto D) {
+      case OP_ZERO: {  // clears all three outputs
 #pragma unroll
-          for (int e = 0; e < E; ++e) reg(D, e) = (real)0;
-        });
+        for (int e = 0; e < E; ++e) R[RS_O0 - 2][e] = R[RS_O1 - 2][e] = R[RS_O2 - 2][e] = (real)0;
         break;
       }
       case OP_BERN: {

@@ -101,7 +101,7 @@ class Builder {
   int product_program(std::vector<Prod> prods, const std::vector<int> &outf) {
     if (outf.empty() || outf.size() > 3) throw std::runtime_error("program outputs");
     const int pg = prog_begin();
-    for (size_t k = 0; k < outf.size(); ++k) op(OP_ZERO, (uint8_t)(RS_O0 + k), 0, 0, -1, 0, -1, 0, 0.0);
+    op(OP_ZERO, RS_O0, 0, 0, -1, 0, -1, 0, 0.0);  // clears all three outputs
     struct Group {
       Fac x;
       std::vector<Prod> partners, self;  // partners: x is .a
@@ -357,7 +357,7 @@ Plan build_plan(const PlanParams &pp, double dt) {
 
   // Bernoulli program: o0 = |grad eta|^2, o1 = grad eta . grad psi, o2 = |grad psi|^2
   int bern_prog = B.prog_begin();
-  for (int k = 0; k < 3; ++k) B.op(OP_ZERO, (uint8_t)(RS_O0 + k), 0, 0, -1, 0, -1, 0, 0.0);
+  B.op(OP_ZERO, RS_O0, 0, 0, -1, 0, -1, 0, 0.0);
   B.ld2(Fac{mE, FL_DX}, mP, FL_DX);
   B.mac(0, RS_U, RS_U, 1.0 / (kref * kref));
   B.mac(1, RS_U, RS_V, 1.0 / kref);
@@ -828,7 +828,7 @@ std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
           if (o.a < RS_O0 || o.a > RS_O2 || o.b > RS_A || o.c > RS_A) return bad("MAC regs");
           break;
         case OP_MOV:
-          if (o.a > RS_O2 || o.b > RS_O2) return bad("MOV regs");
+          if (o.a != RS_A || o.b > RS_A) return bad("MOV regs");
           break;
         case OP_ZERO:
           if (o.a > RS_O2) return bad("ZERO reg");

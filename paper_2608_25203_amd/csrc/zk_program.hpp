@@ -22,9 +22,9 @@ namespace zk {
 enum RowCode : uint8_t {
   OP_LD2 = 1,  // u + i v <- inverse x-FFT of (F_a, F_b) mixed rows (Hermitian ext.)
   OP_LDP = 2,  // u, v <- physical rows of caller fields (base grid)
-  OP_MOV = 3,  // R[a] <- R[b]
-  OP_MAC = 4,  // R[a] += coef * R[b] * R[c]
-  OP_ZERO = 5, // R[a] <- 0
+  OP_MOV = 3,  // A <- R[b] (a = A)
+  OP_MAC = 4,  // R[a] += coef * R[b] * R[c], a in o0..o2, b, c in u, v, A
+  OP_ZERO = 5, // o0, o1, o2 <- 0
   OP_BERN = 6, // o0 <- Bernoulli term from o0 = |grad eta|^2, o1 = grad eta.grad psi,
                //       o2 = |grad psi|^2, u = G psi; coef = eps
   OP_ST2 = 7,  // forward x-FFT of R[a] + i R[b]; split; store kx < nx/2 to mixed fa, fb

@@ -164,8 +164,9 @@ class Interp:
                     R[a] = R[b].copy()
                 elif code == OP_MAC:
                     R[a] = R[a] + coef * R[b] * R[c]
-                elif code == OP_ZERO:
-                    R[a] = np.zeros((rows, N))
+                elif code == OP_ZERO:  # clears o0, o1, o2
+                    for k in (3, 4, 5):
+                        R[k] = np.zeros((rows, N))
                 elif code == OP_BERN:
                     e = coef
                     S = 1 + e * e * R[3]
