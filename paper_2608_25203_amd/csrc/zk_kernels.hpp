@@ -241,6 +241,34 @@ struct Shape {
   }
 };
 
+// Field data goes through global-address-space pointers: global loads and
+// stores (not flat ones, which also count against the LDS wait counter and
+// would make every LDS wait of a transform wait for them too).
+template <typename R>
+struct Vec2 {
+  typedef R T __attribute__((ext_vector_type(2)));
+};
+template <typename R>
+__device__ __forceinline__ cpx<R> gload(const cpx<R> *p, long long i) {
+  const typename Vec2<R>::T v = ((const __attribute__((address_space(1))) typename Vec2<R>::T *)p)[i];
+  return {v.x, v.y};
+}
+template <typename R>
+__device__ __forceinline__ void gstore(cpx<R> *p, long long i, cpx<R> c) {
+  typename Vec2<R>::T v;
+  v.x = c.x;
+  v.y = c.y;
+  ((__attribute__((address_space(1))) typename Vec2<R>::T *)p)[i] = v;
+}
+template <typename Tp>
+__device__ __forceinline__ Tp gload1(const Tp *p, long long i) {
+  return ((const __attribute__((address_space(1))) Tp *)p)[i];
+}
+template <typename Tp>
+__device__ __forceinline__ void gstore1(Tp *p, long long i, Tp v) {
+  ((__attribute__((address_space(1))) Tp *)p)[i] = v;
+}
+
 // Schedule records (programs, ops, tasks, outputs, terms) are uniform across
 // a block and never written while a kernel runs: read them through the
 // constant address space so they arrive in scalar registers (scalar loads)
@@ -283,7 +311,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   const RowProg pg = uniform_load(a.progs + prog);
   const cpx<real> *tw = a.tw + tw_slot(E) * N;  // this shape's pass-ordered table
   if constexpr (TWL) {
-    for (int i = threadIdx.x; i < N - E; i += S::BS) twl[i] = tw[i];
+    for (int i = threadIdx.x; i < N - E; i += S::BS) twl[i] = gload(tw, i);
     tw = twl;
   }
   __syncthreads();
@@ -329,8 +357,8 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
           if (pos || neg) {
             const int kk = pos ? (t + T * r) : ((E - r) * T - t);
             const int idx = mix_index<real>(kk, row, a.rows);
-            za = Fa[idx];
-            if (has_b) zb[r] = Fb[idx];
+            za = gload(Fa, idx);
+            if (has_b) zb[r] = gload(Fb, idx);
           }
           z[r] = za;
         }
@@ -342,8 +370,8 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
           const int lane = threadIdx.x & 63;
 #pragma unroll
           for (int c = lane; c < NC; c += 64) {
-            ma = fmaxf(ma, ca[c]);
-            mb = fmaxf(mb, cb[c]);
+            ma = fmaxf(ma, gload1(ca, c));
+            mb = fmaxf(mb, gload1(cb, c));
           }
           ma = wave_max(ma);
           mb = wave_max(mb);
@@ -384,8 +412,8 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         const long long off = (long long)row * a.nx;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          z[e].x = (real)pa[off + t + T * e];
-          z[e].y = op.fb >= 0 ? (real)pb[off + t + T * e] : (real)0;
+          z[e].x = (real)gload1(pa, off + t + T * e);
+          z[e].y = op.fb >= 0 ? (real)gload1(pb, off + t + T * e) : (real)0;
         }
         break;
       }
@@ -476,8 +504,8 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
           const cpx<real> zk = res[lpad(k)];
           const cpx<real> zm = res[lpad(k == 0 ? 0 : N - k)];
           const int idx = mix_index<real>(k, row, a.rows);
-          Fa[idx] = {hx * (zk.x + zm.x), hx * (zk.y - zm.y)};
-          if (op.fb >= 0) Fb[idx] = {hy * (zk.y + zm.y), -hy * (zk.x - zm.x)};
+          gstore(Fa, idx, cpx<real>{hx * (zk.x + zm.x), hx * (zk.y - zm.y)});
+          if (op.fb >= 0) gstore(Fb, idx, cpx<real>{hy * (zk.y + zm.y), -hy * (zk.x - zm.x)});
         }
         break;
       }
@@ -487,7 +515,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         const long long off = ((long long)(op.fb > 0 ? op.fb : 0) * a.rows + row) * a.nx;
         with_any(op.a, [&](auto X) {
 #pragma unroll
-          for (int e = 0; e < E; ++e) po[off + t + T * e] = (double)reg(X, e);
+          for (int e = 0; e < E; ++e) gstore1(po, off + t + T * e, (double)reg(X, e));
         });
         break;
       }
@@ -546,9 +574,9 @@ __device__ __forceinline__ cpx<double> symval(uint32_t s, double kk, double g0, 
     f = (l & 1) ? g0 : kk;
     for (int i = 1; i < l; ++i) f *= kk;
   }
-  if (s & SYM_FILT) f *= a.filt_x[col] * a.filt_y[b];
+  if (s & SYM_FILT) f *= gload1(a.filt_x, col) * gload1(a.filt_y, b);
   if ((s & SYM_TAPER) && a.taper_on) f *= tp;
-  if (s & SYM_IF) f *= a.ifsym[(long long)base_index(col, b, a.ny) * kIfCoefs + ((s >> SYM_IF_SHIFT) & 7)];
+  if (s & SYM_IF) f *= gload1(a.ifsym, (long long)base_index(col, b, a.ny) * kIfCoefs + ((s >> SYM_IF_SHIFT) & 7));
   if (s & SYM_INVG0) f = g0 > 0.0 ? f / g0 : 0.0;
   if (s & SYM_IKY) return {0.0, f * ky};
   return {f, 0.0};
@@ -576,7 +604,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   const int ny = a.ny;
   const cpx<real> *tw = a.tw + tw_slot(E) * N;  // this shape's pass-ordered table
   if constexpr (TWL) {
-    for (int i = threadIdx.x; i < N - E; i += S::BS) twl[i] = tw[i];
+    for (int i = threadIdx.x; i < N - E; i += S::BS) twl[i] = gload(tw, i);
     tw = twl;
   }
   __syncthreads();
@@ -590,10 +618,11 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   double skk[QB], sg0[QB], stp[QB];
 #pragma unroll
   for (int q = 0; q < QB; ++q) {
-    const SymEl e = a.sym[base_index(col, t + T * q, ny)];
-    skk[q] = e.kk;
-    sg0[q] = e.g0;
-    stp[q] = e.tp;
+    const double *e = reinterpret_cast<const double *>(a.sym) + 4LL * base_index(col, t + T * q, ny);
+    const typename Vec2<double>::T k01 = ((const __attribute__((address_space(1))) typename Vec2<double>::T *)e)[0];
+    skk[q] = k01.x;
+    sg0[q] = k01.y;
+    stp[q] = gload1(e, 2);
   }
   auto sym = [&](uint32_t s, int q) -> cpx<double> {
     return symval(s, skk[q], sg0[q], stp[q], col, t + T * q, a.ky_scale * my_of(q), a);
@@ -607,7 +636,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
     const cpx<real> *F = a.mix + (long long)task.fwd[f] * a.mix_stride;
     cpx<real> v[E];
 #pragma unroll
-    for (int r = 0; r < E; ++r) v[r] = F[mix_index<real>(col, t + T * r, a.rows)];
+    for (int r = 0; r < E; ++r) v[r] = gload(F, mix_index<real>(col, t + T * r, a.rows));
     const cpx<real> *res = team_fft<real, N, E, NB, -1>(v, b0, b1, tw, t);
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
@@ -633,7 +662,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
       if (tm2.src >= 0) {
         const cpx<double> *B = a.base + (long long)tm2.src * a.base_stride;
 #pragma unroll
-        for (int q = 0; q < QB; ++q) nxt[q] = B[base_index(col, t + T * q, ny)];
+        for (int q = 0; q < QB; ++q) nxt[q] = gload(B, base_index(col, t + T * q, ny));
       }
     };
     fetch(ntm);
@@ -669,7 +698,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
     if (out.dst_base >= 0) {
       cpx<double> *B = a.base + (long long)out.dst_base * a.base_stride;
 #pragma unroll
-      for (int q = 0; q < QB; ++q) B[base_index(col, t + T * q, ny)] = acc[q];
+      for (int q = 0; q < QB; ++q) gstore(B, base_index(col, t + T * q, ny), acc[q]);
     }
     if (out.dst_mixed >= 0) {
       const double lc = out.lift_coef;
@@ -690,11 +719,11 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
 #pragma unroll
       for (int r = 0; r < E; ++r) {
         const cpx<real> w = res[lpad(t + T * r)];
-        F[mix_index<real>(col, t + T * r, a.rows)] = w;
+        gstore(F, mix_index<real>(col, t + T * r, a.rows), w);
         m = fmaxf(m, fmaxf(fabsf((float)w.x), fabsf((float)w.y)));
       }
       m = team_max<T>(m, red);
-      if (t == 0) a.colmax[(long long)out.dst_mixed * (a.nx / 2) + col] = m;
+      if (t == 0) gstore1(a.colmax, (long long)out.dst_mixed * (a.nx / 2) + col, m);
     }
   }
 }
