@@ -197,7 +197,7 @@ int zk_kernel_stats(zk_ctx *ctx, int kind, double *ms, double *bytes, double *fl
 
 /* Autotuner: for each pass kind (row / column, padded / base transform),
  * time every compiled team shape (T threads per transform, first-pass radix
- * E = N / T, T in {32, 64, 128, 256}) on the passes of one RK4 step of this
+ * E = N / T, T a power of two in [32, 1024]) on the passes of one RK4 step of this
  * context (reps timed repetitions each; the context's internal spectra are
  * overwritten, no caller field is touched) and keep the fastest for later
  * calls.  Results are identical up to FP64 (or FP32) rounding order.
@@ -338,8 +338,8 @@ const char *zk_closure_last_error(const zk_closure *clo);
  * batched launch per phase and tile size (blockIdx.y runs over the tiles'
  * programs or tasks), and one step's phases are replayed as a HIP graph of
  * kernel nodes.  The team shape of each pass and size (threads per
- * transform and first-pass radix) is the default one (min(256, n/2)
- * threads) until zk_batch_autotune times the compiled alternatives on the
+ * transform and first-pass radix) is the default one (the smallest radix,
+ * as for a context) until zk_batch_autotune times the compiled alternatives on the
  * batch itself and keeps the fastest.  Tile sizes follow zk_create's rule.
  * ------------------------------------------------------------------------- */
 typedef struct zk_tile {
