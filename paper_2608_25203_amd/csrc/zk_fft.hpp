@@ -1,4 +1,4 @@
-// zk_fft.hpp -- Stockham FFT for one team of T threads (T = min(256, n/2)).
+// zk_fft.hpp -- Stockham FFT for one team of T threads (T a power of two, 32 to 1024).
 //
 // A team transforms one sequence of N = E * T complex points.  Thread t holds
 // the E elements t + T*r in registers on entry; the first pass is a radix-E
