@@ -392,3 +392,28 @@ def test_every_team_shape_keeps_parity(torch, n):
         s.close()
         del s
         torch.cuda.empty_cache()
+
+
+def test_degenerate_inputs(torch):
+    """Edge cases: zero steps leave the fields untouched (bit-identical); a
+    step of dt = 0 with the filter off is the band projection of the input;
+    psi = 0 gives G psi = 0 and psi_t = -g P_B eta exactly; order M = 1 is
+    G0 psi whatever eta is."""
+    n, L, M = 64, TWO_PI, 3
+    eta, psi = random_band_fields(n, n, 41, n // 2 - 1, amplitude=0.01)
+    g = Grid(n, n, L, L, 1.0)
+    s = solver(torch, n, n, L, L, 1.0, M)
+    e, p = dev(torch, eta), dev(torch, psi)
+    e0, p0 = e.clone(), p.clone()
+    s.step(e, p, 0.01, 0)
+    assert torch.equal(e, e0) and torch.equal(p, p0)
+    s0 = solver(torch, n, n, L, L, 1.0, M, filt=False)
+    s0.step(e, p, 0.0, 1)
+    assert rel(host(e), g.phys(g.spec(eta))) < 1e-13 and rel(host(p), g.phys(g.spec(psi))) < 1e-13
+    z = torch.zeros_like(p0)
+    assert float(s.dtn(e0, z).abs().max()) == 0.0
+    a, b = s.rhs(e0, z)
+    assert float(a.abs().max()) == 0.0 and rel(host(b), -9.81 * g.phys(g.spec(eta))) < 1e-13
+    s1 = solver(torch, n, n, L, L, 1.0, 1)
+    m1 = HOSModel(g, 1)
+    assert rel(host(s1.dtn(e0, p0)), m1.dtn(np.zeros_like(eta), psi)) < 1e-13
