@@ -417,3 +417,24 @@ def test_degenerate_inputs(torch):
     s1 = solver(torch, n, n, L, L, 1.0, 1)
     m1 = HOSModel(g, 1)
     assert rel(host(s1.dtn(e0, p0)), m1.dtn(np.zeros_like(eta), psi)) < 1e-13
+
+
+@pytest.mark.parametrize("nx,ny", [(2048, 64), (64, 2048)])
+def test_extreme_aspect_grids(torch, nx, ny):
+    """The largest transform length on one axis with the smallest on the
+    other (1024-thread row teams with 32-thread column teams, and the
+    reverse): G psi, the RHS and two RK4 steps at the FP64 bar."""
+    Lx, Ly, M = 0.05 * nx, 0.05 * ny, 3
+    kmax = math.hypot(math.pi * nx / Lx, math.pi * ny / Ly)
+    eta, psi = random_band_fields(nx, ny, 57, min(nx, ny) // 2 - 1, amplitude=0.1 / kmax)
+    s = solver(torch, nx, ny, Lx, Ly, 0.7, M)
+    m = HOSModel(Grid(nx, ny, Lx, Ly, 0.7), M)
+    e, p = dev(torch, eta), dev(torch, psi)
+    print(" ", s.team_shapes(), flush=True)
+    assert rel(host(s.dtn(e, p)), m.dtn(eta, psi)) < 1e-10
+    a, b = s.rhs(e, p)
+    a0, b0 = m.rhs(eta, psi)
+    assert rel(host(a), a0) < 1e-10 and rel(host(b), b0) < 1e-10
+    s.step(e, p, 0.002, 2)
+    e0, p0 = m.step(eta, psi, 0.002, 2)
+    assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
