@@ -438,3 +438,29 @@ def test_extreme_aspect_grids(torch, nx, ny):
     s.step(e, p, 0.002, 2)
     e0, p0 = m.step(eta, psi, 0.002, 2)
     assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
+
+
+def test_fp32_form_of_ifab2_inverse_and_depth_lift(torch):
+    """The FP32-transform form of the paper's integrator, the inverse DNO
+    map and the depth lift against the FP64 oracle: one IF-AB2 step and one
+    inverse map to 2e-6, the layer velocities to 2e-5 of each layer's largest
+    component (FP32 rounding times the band's |k|)."""
+    n, L, h, M = 128, TWO_PI, 1.0, 3
+    eta, psi = jonswap_state(n, n, L, L, h, 9.81, 8.0, 0.08, 61)
+    psi = psi - psi.mean()
+    m = HOSModel(Grid(n, n, L, L, h), M)
+    s = solver(torch, n, n, L, L, h, M, precision=32, integrator="ifab2")
+    e, p = dev(torch, eta), dev(torch, psi)
+    s.step(e, p, 0.01, 1)
+    e0, p0 = m.step_ifab2(eta, psi, 0.01, 1)
+    assert rel(host(e), e0) < 2e-6 and rel(host(p), p0) < 2e-6
+    v = m.dtn(eta, psi)
+    got = host(s.inverse_dtn(dev(torch, eta), dev(torch, v), 8))
+    assert rel(got, m.inverse_dtn(eta, v, 8)) < 2e-6
+    ys = [0.0, 0.25, 1.0]
+    uvw = host(s.depth_velocity(dev(torch, eta), dev(torch, psi), ys))
+    ref = m.depth_velocity(eta, psi, ys)
+    for i in range(len(ys)):
+        err = np.max(np.abs(uvw[i] - ref[i])) / np.max(np.abs(ref[i]))
+        print(f"  layer y = {ys[i]}: rel err {err:.3e}", flush=True)
+        assert err < 2e-5
