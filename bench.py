@@ -59,13 +59,14 @@ def cpu_baseline(w, eta, psi, nsteps):
 
 
 def kernel_source_hash():
-    """Hash of the HIP kernel sources: a counter record applies to the sources it was taken on."""
+    """Hash of the HIP kernel sources and the planner that schedules them: a
+    counter record applies to the sources it was taken on."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "paper_2608_25203_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
+        if f.endswith((".hip", ".hpp")) or f == "zk_plan.cpp":
             with open(os.path.join(csrc, f), "rb") as fh:
                 h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]

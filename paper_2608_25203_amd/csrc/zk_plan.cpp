@@ -120,6 +120,22 @@ class Builder {
           best = kv.second;
           x = kv.first;
         }
+      // Prefer a partner of the previous group as the next held factor: the
+      // partner goes last in that group and its load serves both roles.
+      if (!groups.empty()) {
+        int pbest = -1;
+        for (auto &q : groups.back().partners) {
+          auto it = cnt.find(q.b);
+          if (it != cnt.end() && it->second > pbest) {
+            pbest = it->second;
+            x = q.b;
+          }
+        }
+        if (pbest > 0) {
+          auto &ps = groups.back().partners;
+          std::stable_partition(ps.begin(), ps.end(), [&](const Prod &q) { return !(q.b == x); });
+        }
+      }
       Group g{x, {}, {}};
       std::vector<Prod> keep;
       for (auto &p : prods) {
@@ -134,11 +150,16 @@ class Builder {
     struct Item {
       Fac f;
       int group, partner;  // partner = -1: the group's held factor
+      int also_hold;       // a partner that is also the next group's held factor, or -1
     };
     std::vector<Item> items;
     for (int gi = 0; gi < (int)groups.size(); ++gi) {
-      items.push_back({groups[gi].x, gi, -1});
-      for (int k = 0; k < (int)groups[gi].partners.size(); ++k) items.push_back({groups[gi].partners[k].b, gi, k});
+      const bool shared = !items.empty() && items.back().partner >= 0 && items.back().group == gi - 1 &&
+                          items.back().f == groups[gi].x;
+      if (shared) items.back().also_hold = gi;
+      else items.push_back({groups[gi].x, gi, -1, -1});
+      for (int k = 0; k < (int)groups[gi].partners.size(); ++k)
+        items.push_back({groups[gi].partners[k].b, gi, k, -1});
     }
     int in_a = -1;                // group whose factor A holds
     int hold_group = -1, hold_reg = -1;  // a factor loaded in this transform's U or V
@@ -150,22 +171,24 @@ class Builder {
         const Item &it = items[j];
         const uint8_t reg = j == i ? RS_U : RS_V;
         const Group &g = groups[it.group];
-        if (it.partner < 0) {  // the group's factor: self products, keep it if partners follow
-          for (auto &p : g.self) mac(p.out, reg, reg, p.coef);
-          hold_group = it.group;
-          hold_reg = reg;
-          bool later = false;
-          for (size_t k = j + 1; k < items.size(); ++k)
-            if (items[k].group == it.group && k >= i + 2) later = true;
-          if (later) {
-            op(OP_MOV, RS_A, reg, 0, -1, 0, -1, 0, 0.0);
-            in_a = it.group;
-          }
-        } else {
+        if (it.partner >= 0) {
           const Prod &p = g.partners[it.partner];
           const uint8_t h = (hold_group == it.group) ? (uint8_t)hold_reg : RS_A;
           if (h == RS_A && in_a != it.group) throw std::runtime_error("product schedule lost its held factor");
           mac(p.out, h, reg, p.coef);
+        }
+        const int hg = it.partner < 0 ? it.group : it.also_hold;
+        if (hg >= 0) {  // a group's factor: self products, keep it if partners follow
+          for (auto &p : groups[hg].self) mac(p.out, reg, reg, p.coef);
+          hold_group = hg;
+          hold_reg = reg;
+          bool later = false;
+          for (size_t k = j + 1; k < items.size(); ++k)
+            if (items[k].group == hg && k >= i + 2) later = true;
+          if (later) {
+            op(OP_MOV, RS_A, reg, 0, -1, 0, -1, 0, 0.0);
+            in_a = hg;
+          }
         }
       }
     }
