@@ -631,12 +631,21 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   cpx<double> X[QB];
 #pragma unroll
   for (int q = 0; q < QB; ++q) X[q] = {0.0, 0.0};
-  for (int f = 0; f < kMaxFolds; ++f) {
-    if (task.fwd[f] < 0) continue;
+  // Folds: the next field's column is loaded while the current one is
+  // transformed (folds are consecutive from slot 0).
+  cpx<real> vn[E];
+  auto load_fold = [&](int f) {
     const cpx<real> *F = a.mix + (long long)task.fwd[f] * a.mix_stride;
+#pragma unroll
+    for (int r = 0; r < E; ++r) vn[r] = gload(F, mix_index<real>(col, t + T * r, a.rows));
+  };
+  if (task.fwd[0] >= 0) load_fold(0);
+  for (int f = 0; f < kMaxFolds; ++f) {
+    if (task.fwd[f] < 0) break;
     cpx<real> v[E];
 #pragma unroll
-    for (int r = 0; r < E; ++r) v[r] = gload(F, mix_index<real>(col, t + T * r, a.rows));
+    for (int r = 0; r < E; ++r) v[r] = vn[r];
+    if (f + 1 < kMaxFolds && task.fwd[f + 1] >= 0) load_fold(f + 1);
     const cpx<real> *res = team_fft<real, N, E, NB, -1>(v, b0, b1, tw, t);
 #pragma unroll
     for (int q = 0; q < QB; ++q) {

@@ -363,11 +363,13 @@ Plan build_plan(const PlanParams &pp, double dt) {
       if (M == 3) pr[iGX].push_back({Fac{mS, 0}, Fac{mL[1], 0}, 0, eps * eps * kpow(1)});
       else pr[iGX].push_back({Fac{mS, 0}, Fac{mV, 0}, 0, 1.0});
     }
-    // group outputs by three: [PHI, WP, EP] [GX, S]
-    for (size_t k0 = 0; k0 < outs.size(); k0 += 3) {
+    // group outputs by three: [PHI, WP, EP] [GX, S]; the last level, the
+    // longest program, as [PHI, WP] [GX] for two programs per row
+    const size_t grp = (r == M - 1 && M >= 3) ? 2 : 3;
+    for (size_t k0 = 0; k0 < outs.size(); k0 += grp) {
       std::vector<int> of;
       std::vector<Prod> ps;
-      for (size_t k = k0; k < outs.size() && k < k0 + 3; ++k) {
+      for (size_t k = k0; k < outs.size() && k < k0 + grp; ++k) {
         of.push_back(outs[k]);
         for (auto p : pr[k]) {
           p.out = (int)(k - k0);
@@ -865,7 +867,7 @@ std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
   }
   for (auto &t : p.tasks) {
     for (int f = 0; f < kMaxFolds; ++f)
-      if (t.fwd[f] >= p.nmix || (f > 0 && t.fwd[f] >= 0 && t.fwd[0] < 0)) return bad("task fwd");
+      if (t.fwd[f] >= p.nmix || (f > 0 && t.fwd[f] >= 0 && t.fwd[f - 1] < 0)) return bad("task fwd");
     if (t.o0 < 0 || t.no < 0 || t.o0 + t.no > (int)p.outs.size()) return bad("task outs");
     for (int i = 0; i < t.no; ++i) {
       const ColOut &o = p.outs[t.o0 + i];
