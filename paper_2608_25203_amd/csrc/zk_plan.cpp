@@ -443,9 +443,13 @@ Plan build_plan(const PlanParams &pp, double dt) {
   };
   // levels 1..M-1 for stage state (e, p); ends with G stored (and lifted)
   // The last level stores nothing but its PHI, WP and GX folds, which only G
-  // uses: one task folds all three (each with its G coefficient) into X and
-  // assembles G from X and the stored lower levels, in the same launch.
-  auto last_level_g = [&](int p, bool lift_g) {
+  // uses: a task folds all three (each with its G coefficient) into X and
+  // assembles G from X and the stored lower levels, in the same launch.  When
+  // G is also lifted, a second task repeats the folds and does the lift: the
+  // launch then has two blocks per column instead of one (a 512 x 512 grid
+  // has 256 columns: one block per CU), which more than pays for the
+  // repeated folds.
+  auto last_level_g = [&](int p, bool lift_g) -> std::vector<TaskSpec> {
     const int r = M - 1;
     TaskSpec t;
     t.fwd = oPHI;
@@ -460,16 +464,18 @@ Plan build_plan(const PlanParams &pp, double dt) {
     }
     if (hasGX1 && r != 1) tm.push_back({bGX[1], 0u, 1.0});
     tm.push_back({-1, 0u, 1.0});
+    TaskSpec tl = t;
     t.outs.push_back(B.store(bG, tm));
-    if (lift_g) t.outs.push_back(B.lift(mG, tm));
-    return t;
+    if (!lift_g) return {t};
+    tl.outs.push_back(B.lift(mG, tm));
+    return {t, tl};
   };
   auto core = [&](std::vector<Launch> &seq, int e, int p, bool lift_g) {
     (void)e;
     for (int r = 1; r <= M - 1; ++r) {
       seq.push_back(row_launch(L_ROW_PAD, level_progs[r]));
       if (r == M - 1) {
-        seq.push_back(B.col_launch(L_COL_PAD, {last_level_g(p, lift_g)}));
+        seq.push_back(B.col_launch(L_COL_PAD, last_level_g(p, lift_g)));
         continue;
       }
       std::vector<TaskSpec> A;
