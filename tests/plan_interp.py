@@ -38,7 +38,9 @@ def build_checker():
     src = [os.path.join(CSRC, "zk_plan.cpp"), os.path.join(CSRC, "zk_plan_check.cpp")]
     if not os.path.exists(EXE) or any(os.path.getmtime(s) > os.path.getmtime(EXE) for s in src + [
             os.path.join(CSRC, "zk_plan.hpp"), os.path.join(CSRC, "zk_program.hpp")]):
-        subprocess.run(["g++", "-O1", "-std=c++17", "-I", CSRC] + src + ["-o", EXE], check=True)
+        tmp = f"{EXE}.{os.getpid()}"  # parallel test workers each build, then rename atomically
+        subprocess.run(["g++", "-O1", "-std=c++17", "-I", CSRC] + src + ["-o", tmp], check=True)
+        os.replace(tmp, EXE)
     return EXE
 
 
