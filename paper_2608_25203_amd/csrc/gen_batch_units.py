@@ -8,6 +8,9 @@ SHAPES = ([(T, E) for T in (32, 64, 128, 256) for E in (2, 3, 4, 6, 8, 12)] + [(
           + [(1024, E) for E in (2, 3)])
 
 
+FOLD_SHAPES = [(T, E) for T in (64, 128, 256) for E in (2, 3)]  # as fold_team_shape() in zk_kernels.hpp
+
+
 def bs(T):
     return max(256, T)
 
@@ -38,6 +41,16 @@ for kind in ("row", "col"):
                     continue
                 lines.append(f"  if (T == {T} && E == {E}) {{")
                 lines.append(f"    hipLaunchKernelGGL((col_kernel_batch<{real}, {T}, {E}, true>), grid, dim3({bs(T)}), 0, s, args, items, ph);")
+                lines.append("    return hipGetLastError();")
+                lines.append("  }")
+            lines += ["  return hipErrorInvalidValue;", "}", ""]
+            # fold teams: kMaxFolds teams of T threads, one column per block
+            lines += ["template <>",
+                      f"hipError_t launch_batch_col_folds<{real}>(int T, int E, dim3 grid, hipStream_t s, const ColArgs<{real}> *args,",
+                      "                                         const BatchItem *items, PhysArgs ph) {"]
+            for T, E in FOLD_SHAPES:
+                lines.append(f"  if (T == {T} && E == {E}) {{")
+                lines.append(f"    hipLaunchKernelGGL((col_kernel_folds<{real}, {T}, {E}>), grid, dim3(kMaxFolds * {T}), 0, s, args, items, ph);")
                 lines.append("    return hipGetLastError();")
                 lines.append("  }")
             lines += ["  return hipErrorInvalidValue;", "}", ""]

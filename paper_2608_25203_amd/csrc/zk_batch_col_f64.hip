@@ -231,4 +231,34 @@ hipError_t launch_batch_col_lift<double>(int T, int E, dim3 grid, hipStream_t s,
   return hipErrorInvalidValue;
 }
 
+template <>
+hipError_t launch_batch_col_folds<double>(int T, int E, dim3 grid, hipStream_t s, const ColArgs<double> *args,
+                                         const BatchItem *items, PhysArgs ph) {
+  if (T == 64 && E == 2) {
+    hipLaunchKernelGGL((col_kernel_folds<double, 64, 2>), grid, dim3(kMaxFolds * 64), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 64 && E == 3) {
+    hipLaunchKernelGGL((col_kernel_folds<double, 64, 3>), grid, dim3(kMaxFolds * 64), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 2) {
+    hipLaunchKernelGGL((col_kernel_folds<double, 128, 2>), grid, dim3(kMaxFolds * 128), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 3) {
+    hipLaunchKernelGGL((col_kernel_folds<double, 128, 3>), grid, dim3(kMaxFolds * 128), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 256 && E == 2) {
+    hipLaunchKernelGGL((col_kernel_folds<double, 256, 2>), grid, dim3(kMaxFolds * 256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  if (T == 256 && E == 3) {
+    hipLaunchKernelGGL((col_kernel_folds<double, 256, 3>), grid, dim3(kMaxFolds * 256), 0, s, args, items, ph);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace zk

@@ -582,29 +582,44 @@ __device__ __forceinline__ cpx<double> symval(uint32_t s, double kk, double g0, 
   return {f, 0.0};
 }
 
-// Column pass body: TPB teams per block (block blk of the pass), one kx
-// column each, all running task tasks[task].  Thread t owns base-band rows
-// b = t + T q, q < QB (q = KR at t = 0 is the ky Nyquist row, kept zero).
-template <typename real, int T, int E, bool LIFTSYM = false>
+// Column pass body.  FT = 1: TPB teams per block (block blk of the pass),
+// one kx column each, all running task tasks[task], folds one after another.
+// FT = kMaxFolds (fold teams): the block's FT teams share one column; team f
+// transforms fold f and sums a share of each output's terms, the parts are
+// summed through LDS in team order, so a task with several folds and long
+// term lists runs them side by side instead of in sequence.  Thread t owns base-band rows b = t + T q, q < QB (q = KR at
+// t = 0 is the ky Nyquist row, kept zero).
+template <int T, int FT>
+struct ColBlock {
+  static constexpr int BS = FT == 1 ? (T > 256 ? T : 256) : FT * T;  // threads per block
+  static constexpr int TPB = FT == 1 ? BS / T : 1;                    // columns per block
+};
+template <typename real, int T, int E, bool LIFTSYM = false, int FT = 1>
 __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index, int blk) {
   using S = Shape<T, E>;
-  constexpr int N = S::N, L = S::L, NB = S::template nbuf<real>(), QB = S::QB;
-  constexpr bool TWL = S::template tw_in_lds<real>();
-  __shared__ cpx<real> smem[S::TPB * NB * L];
+  using CB = ColBlock<T, FT>;
+  static_assert(FT == 1 || (T >= 64 && FT * T <= 1024), "fold teams: whole wavefronts, one block");
+  constexpr int N = S::N, L = S::L, QB = S::QB;
+  constexpr int NB = FT == 1 ? S::template nbuf<real>() : 2;
+  constexpr bool TWL = FT == 1 ? S::template tw_in_lds<real>() : true;
+  __shared__ cpx<real> smem[(FT == 1 ? CB::TPB : FT) * NB * L];
   __shared__ cpx<real> twl[TWL ? N : 1];
-  __shared__ float red[2 * (S::BS / 64)];
-  const int team = threadIdx.x / T;
+  __shared__ float red[2 * (CB::BS / 64)];
+  __shared__ cpx<double> xs[FT == 1 ? 1 : FT * QB * T];  // fold teams: each team's part of X
+  // fold teams are whole wavefronts: the team index is wave-uniform (scalar)
+  const int team = FT == 1 ? (int)(threadIdx.x / T) : __builtin_amdgcn_readfirstlane((int)(threadIdx.x / T));
   const int t = threadIdx.x % T;
   // columns of one tile share 128-byte lines; keep a tile's blocks on one XCD
   constexpr int CBMAX = MixTile<real>::CB > CBB ? MixTile<real>::CB : CBB;
-  const int col = xcd_unit(blk, a.nx / 2 / S::TPB, CBMAX / S::TPB) * S::TPB + team;
+  const int col = FT == 1 ? xcd_unit(blk, a.nx / 2 / CB::TPB, CBMAX / CB::TPB) * CB::TPB + team
+                          : xcd_unit(blk, a.nx / 2, CBMAX);
   cpx<real> *b0 = smem + team * NB * L;
   cpx<real> *b1 = b0 + (NB - 1) * L;
   const ColTask task = uniform_load(a.tasks + task_index);
   const int ny = a.ny;
   const cpx<real> *tw = a.tw + tw_slot(E) * N;  // this shape's pass-ordered table
   if constexpr (TWL) {
-    for (int i = threadIdx.x; i < N - E; i += S::BS) twl[i] = gload(tw, i);
+    for (int i = threadIdx.x; i < N - E; i += CB::BS) twl[i] = gload(tw, i);
     tw = twl;
   }
   __syncthreads();
@@ -631,42 +646,88 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   cpx<double> X[QB];
 #pragma unroll
   for (int q = 0; q < QB; ++q) X[q] = {0.0, 0.0};
-  // Folds: the next field's column is loaded while the current one is
-  // transformed (folds are consecutive from slot 0).
-  cpx<real> vn[E];
-  auto load_fold = [&](int f) {
-    const cpx<real> *F = a.mix + (long long)task.fwd[f] * a.mix_stride;
-#pragma unroll
-    for (int r = 0; r < E; ++r) vn[r] = gload(F, mix_index<real>(col, t + T * r, a.rows));
-  };
-  if (task.fwd[0] >= 0) load_fold(0);
-  for (int f = 0; f < kMaxFolds; ++f) {
-    if (task.fwd[f] < 0) break;
-    cpx<real> v[E];
-#pragma unroll
-    for (int r = 0; r < E; ++r) v[r] = vn[r];
-    if (f + 1 < kMaxFolds && task.fwd[f + 1] >= 0) load_fold(f + 1);
-    const cpx<real> *res = team_fft<real, N, E, NB, -1>(v, b0, b1, tw, t);
+  auto fold_into = [&](const cpx<real> *res, uint32_t fsym, double fcoef) {
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
       const cpx<real> w = res[lpad(pos_of(q))];
-      const cpx<double> sv = sym(task.fwd_sym[f], q);
-      const cpx<double> x = {(double)w.x * task.fwd_coef[f], (double)w.y * task.fwd_coef[f]};
+      const cpx<double> sv = sym(fsym, q);
+      const cpx<double> x = {(double)w.x * fcoef, (double)w.y * fcoef};
       X[q].x += x.x * sv.x - x.y * sv.y;
       X[q].y += x.x * sv.y + x.y * sv.x;
+    }
+  };
+  if constexpr (FT == 1) {
+    // Folds: the next field's column is loaded while the current one is
+    // transformed (folds are consecutive from slot 0).
+    cpx<real> vn[E];
+    auto load_fold = [&](int f) {
+      const cpx<real> *F = a.mix + (long long)task.fwd[f] * a.mix_stride;
+#pragma unroll
+      for (int r = 0; r < E; ++r) vn[r] = gload(F, mix_index<real>(col, t + T * r, a.rows));
+    };
+    if (task.fwd[0] >= 0) load_fold(0);
+    for (int f = 0; f < kMaxFolds; ++f) {
+      if (task.fwd[f] < 0) break;
+      cpx<real> v[E];
+#pragma unroll
+      for (int r = 0; r < E; ++r) v[r] = vn[r];
+      if (f + 1 < kMaxFolds && task.fwd[f + 1] >= 0) load_fold(f + 1);
+      fold_into(team_fft<real, N, E, NB, -1>(v, b0, b1, tw, t), task.fwd_sym[f], task.fwd_coef[f]);
+    }
+  } else if (task.fwd[0] >= 0) {
+    // Team f folds field f (a team without one transforms zeros); the parts
+    // are summed in fold order, X = ((X_0 + X_1) + X_2).
+    int fid = -1;
+    uint32_t fsym = 0;
+    double fcoef = 0.0;
+#pragma unroll
+    for (int f = 0; f < FT; ++f)
+      if (team == f) {
+        fid = task.fwd[f];
+        fsym = task.fwd_sym[f];
+        fcoef = task.fwd_coef[f];
+      }
+    cpx<real> v[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) v[r] = {(real)0, (real)0};
+    if (fid >= 0) {
+      const cpx<real> *F = a.mix + (long long)fid * a.mix_stride;
+#pragma unroll
+      for (int r = 0; r < E; ++r) v[r] = gload(F, mix_index<real>(col, t + T * r, a.rows));
+    }
+    const cpx<real> *res = team_fft<real, N, E, NB, -1>(v, b0, b1, tw, t);
+    if (fid >= 0) fold_into(res, fsym, fcoef);
+#pragma unroll
+    for (int q = 0; q < QB; ++q) xs[(team * QB + q) * T + t] = X[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      X[q] = xs[q * T + t];
+#pragma unroll
+      for (int f = 1; f < FT; ++f) {
+        const cpx<double> y = xs[(f * QB + q) * T + t];
+        X[q].x += y.x;
+        X[q].y += y.y;
+      }
     }
   }
   if (t == 0) X[S::KR] = {0.0, 0.0};  // ky Nyquist row
 
+  // Outputs, one after another.  FT = 1: the team sums every term.  Fold
+  // teams: team f sums terms f, f + FT, ... (a third of the chain of
+  // base-spectrum loads each), the parts are summed through LDS in team
+  // order, and every team then holds the combination; team 0 stores it.
   for (int o = 0; o < task.no; ++o) {
     const ColOut out = uniform_load(a.outs + task.o0 + o);
+    constexpr int step = FT;
+    const int first = FT == 1 ? 0 : team;
     cpx<double> acc[QB];
 #pragma unroll
     for (int q = 0; q < QB; ++q) acc[q] = {0.0, 0.0};
     // Base-spectrum terms: the next term's spectrum is loaded while the
     // current one is accumulated (one global latency per term instead of two).
     cpx<double> nxt[QB];
-    ColTerm ntm = out.nt > 0 ? uniform_load(a.terms + out.t0) : ColTerm{};
+    ColTerm ntm = first < out.nt ? uniform_load(a.terms + out.t0 + first) : ColTerm{};
     auto fetch = [&](const ColTerm &tm2) {
       if (tm2.src >= 0) {
         const cpx<double> *B = a.base + (long long)tm2.src * a.base_stride;
@@ -675,13 +736,13 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
       }
     };
     fetch(ntm);
-    for (int i = 0; i < out.nt; ++i) {
+    for (int i = first; i < out.nt; i += step) {
       const ColTerm tm = ntm;
       cpx<double> cur[QB];
 #pragma unroll
       for (int q = 0; q < QB; ++q) cur[q] = nxt[q];
-      if (i + 1 < out.nt) {
-        ntm = uniform_load(a.terms + out.t0 + i + 1);
+      if (i + step < out.nt) {
+        ntm = uniform_load(a.terms + out.t0 + i + step);
         fetch(ntm);
       }
       if (tm.src >= 0) {
@@ -703,8 +764,25 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
         }
       }
     }
+    if constexpr (FT > 1) {
+      __syncthreads();  // xs: readers of the previous exchange are done
+#pragma unroll
+      for (int q = 0; q < QB; ++q) xs[(team * QB + q) * T + t] = acc[q];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        acc[q] = xs[q * T + t];
+#pragma unroll
+        for (int f = 1; f < FT; ++f) {
+          const cpx<double> y = xs[(f * QB + q) * T + t];
+          acc[q].x += y.x;
+          acc[q].y += y.y;
+        }
+      }
+    }
     if (t == 0) acc[S::KR] = {0.0, 0.0};
-    if (out.dst_base >= 0) {
+    const bool writer = FT == 1 || team == 0;  // fold teams: team 0 writes
+    if (out.dst_base >= 0 && writer) {
       cpx<double> *B = a.base + (long long)out.dst_base * a.base_stride;
 #pragma unroll
       for (int q = 0; q < QB; ++q) gstore(B, base_index(col, t + T * q, ny), acc[q]);
@@ -723,16 +801,18 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
         z[r] = {(real)(acc[q].x * f), (real)(acc[q].y * f)};
       }
       const cpx<real> *res = team_fft<real, N, E, NB, +1>(z, b0, b1, tw, t);
-      cpx<real> *F = a.mix + (long long)out.dst_mixed * a.mix_stride;
       float m = 0.f;
+      if (writer) {  // fold teams: every team transformed the same combination
+        cpx<real> *F = a.mix + (long long)out.dst_mixed * a.mix_stride;
 #pragma unroll
-      for (int r = 0; r < E; ++r) {
-        const cpx<real> w = res[lpad(t + T * r)];
-        gstore(F, mix_index<real>(col, t + T * r, a.rows), w);
-        m = fmaxf(m, fmaxf(fabsf((float)w.x), fabsf((float)w.y)));
+        for (int r = 0; r < E; ++r) {
+          const cpx<real> w = res[lpad(t + T * r)];
+          gstore(F, mix_index<real>(col, t + T * r, a.rows), w);
+          m = fmaxf(m, fmaxf(fabsf((float)w.x), fabsf((float)w.y)));
+        }
       }
       m = team_max<T>(m, red);
-      if (t == 0) gstore1(a.colmax, (long long)out.dst_mixed * (a.nx / 2) + col, m);
+      if (t == 0 && writer) gstore1(a.colmax, (long long)out.dst_mixed * (a.nx / 2) + col, m);
     }
   }
 }
@@ -771,6 +851,15 @@ __global__ __launch_bounds__(T > 256 ? T : 256) void col_kernel_batch(const ColA
   const BatchItem it = items[blockIdx.y];
   const ColArgs<real> a = args[it.tile];
   col_body<real, T, E, LIFTSYM>(a, it.index, blockIdx.x);
+}
+// Fold teams: kMaxFolds teams of T threads per block, one column per block
+// (tasks whose folds and outputs run side by side).
+template <typename real, int T, int E>
+__global__ __launch_bounds__(kMaxFolds * T) void col_kernel_folds(const ColArgs<real> *__restrict__ args,
+                                                             const BatchItem *__restrict__ items, PhysArgs) {
+  const BatchItem it = items[blockIdx.y];
+  const ColArgs<real> a = args[it.tile];
+  col_body<real, T, E, false, kMaxFolds>(a, it.index, blockIdx.x);
 }
 
 // Team shapes (T, E) compiled for the batched kernels: T in {32, 64, 128,
@@ -817,6 +906,21 @@ hipError_t launch_batch_col_lift<double>(int, int, dim3, hipStream_t, const ColA
 template <>
 hipError_t launch_batch_col_lift<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *,
                                         PhysArgs);
+
+// Fold-team column kernel (T in {64, 128, 256}, E in {2, 3}); grid.x = one
+// block per column.  hipErrorInvalidValue for a shape without an instance.
+__host__ __device__ constexpr bool fold_team_shape(int T, int E) {
+  return (T == 64 || T == 128 || T == 256) && (E == 2 || E == 3);
+}
+template <typename real>
+hipError_t launch_batch_col_folds(int T, int E, dim3 grid, hipStream_t s, const ColArgs<real> *args,
+                                  const BatchItem *items, PhysArgs ph);
+template <>
+hipError_t launch_batch_col_folds<double>(int, int, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *,
+                                          PhysArgs);
+template <>
+hipError_t launch_batch_col_folds<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *,
+                                         PhysArgs);
 
 // Reflecting walls (zk_bc.hip): dst [2ny][2nx] = even extension of src
 // [ny][nx]; crop: dst [ny][nx] = the physical quarter of src [2ny][2nx].

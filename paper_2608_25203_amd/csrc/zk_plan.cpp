@@ -202,6 +202,12 @@ class Builder {
   }
 
   // ---- column tasks --------------------------------------------------------
+  static bool same_terms(const std::vector<TermSpec> &a, const std::vector<TermSpec> &b) {
+    if (a.size() != b.size()) return false;
+    for (size_t i = 0; i < a.size(); ++i)
+      if (a[i].src != b[i].src || a[i].sym != b[i].sym || a[i].coef != b[i].coef) return false;
+    return true;
+  }
   void add_tasks(const std::vector<TaskSpec> &ts) {
     for (auto &t : ts) {
       ColTask ct{};
@@ -219,9 +225,26 @@ class Builder {
         ct.fwd_sym[f + 1] = t.more[f].sym;
         ct.fwd_coef[f + 1] = t.more[f].coef;
       }
+      // A lift whose terms equal those of an earlier store of the same task
+      // becomes that output's lifted copy: one combination, both destinations
+      // (the store keeps its place; lifts write mixed fields, which no term reads).
+      std::vector<OutSpec> outs;
+      for (const auto &o : t.outs) {
+        bool merged = false;
+        if (o.dst_base < 0 && o.dst_mixed >= 0)
+          for (auto &m : outs)
+            if (m.dst_mixed < 0 && m.dst_base >= 0 && same_terms(m.terms, o.terms)) {
+              m.dst_mixed = o.dst_mixed;
+              m.lift_coef = o.lift_coef;
+              m.lift_sym = o.lift_sym;
+              merged = true;
+              break;
+            }
+        if (!merged) outs.push_back(o);
+      }
       ct.o0 = (int32_t)P.outs.size();
-      ct.no = (int32_t)t.outs.size();
-      for (auto &o : t.outs) {
+      ct.no = (int32_t)outs.size();
+      for (auto &o : outs) {
         ColOut co{};
         co.dst_base = o.dst_base;
         co.dst_mixed = o.dst_mixed;
@@ -443,12 +466,11 @@ Plan build_plan(const PlanParams &pp, double dt) {
   };
   // levels 1..M-1 for stage state (e, p); ends with G stored (and lifted)
   // The last level stores nothing but its PHI, WP and GX folds, which only G
-  // uses: a task folds all three (each with its G coefficient) into X and
-  // assembles G from X and the stored lower levels, in the same launch.  When
-  // G is also lifted, a second task repeats the folds and does the lift: the
-  // launch then has two blocks per column instead of one (a 512 x 512 grid
-  // has 256 columns: one block per CU), which more than pays for the
-  // repeated folds.
+  // uses: one task folds all three (each with its G coefficient) into X and
+  // assembles G from X and the stored lower levels (and lifts it), in the
+  // same launch.  Its launch is marked for fold teams (d2 = kMaxFolds): a
+  // single grid runs it with one team per fold and per output, side by side
+  // (a 512 x 512 grid has only 256 columns, one block per CU).
   auto last_level_g = [&](int p, bool lift_g) -> std::vector<TaskSpec> {
     const int r = M - 1;
     TaskSpec t;
@@ -464,11 +486,9 @@ Plan build_plan(const PlanParams &pp, double dt) {
     }
     if (hasGX1 && r != 1) tm.push_back({bGX[1], 0u, 1.0});
     tm.push_back({-1, 0u, 1.0});
-    TaskSpec tl = t;
     t.outs.push_back(B.store(bG, tm));
-    if (!lift_g) return {t};
-    tl.outs.push_back(B.lift(mG, tm));
-    return {t, tl};
+    if (lift_g) t.outs.push_back(B.lift(mG, tm));
+    return {t};
   };
   auto core = [&](std::vector<Launch> &seq, int e, int p, bool lift_g) {
     (void)e;
@@ -476,6 +496,7 @@ Plan build_plan(const PlanParams &pp, double dt) {
       seq.push_back(row_launch(L_ROW_PAD, level_progs[r]));
       if (r == M - 1) {
         seq.push_back(B.col_launch(L_COL_PAD, last_level_g(p, lift_g)));
+        seq.back().d2 = kMaxFolds;  // fold teams
         continue;
       }
       std::vector<TaskSpec> A;
@@ -898,6 +919,7 @@ std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
       } else if (l.kind == L_COL_PAD || l.kind == L_COL_BASE) {
         if (l.first < 0 || l.count < 1 || l.first + l.count > (int)p.tasks.size()) return "col launch";
         if (l.c2 != 0 && !(l.c2 == 1 && l.kind == L_COL_BASE)) return "lift_sym variant on a padded pass";
+        if (l.d2 != 0 && !(l.d2 == kMaxFolds && l.c2 == 0)) return "fold teams on a lift_sym launch";
         // one lift per mixed field per launch (blocks of one launch run in any order)
         std::vector<char> lifted(p.nmix, 0);
         for (int k = l.first; k < l.first + l.count; ++k)

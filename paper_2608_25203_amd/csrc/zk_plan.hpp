@@ -28,7 +28,8 @@ enum LaunchKind : int { L_ROW_PAD = 0, L_ROW_BASE = 1, L_COL_PAD = 2, L_COL_BASE
 struct Launch {
   int kind;
   int first, count;  // program or task range; for L_PARSEVAL: base ids a, b (c, d in c2, d2)
-                     // a column launch with c2 = 1 applies its outputs' lift_sym (depth lift)
+                     // a column launch with c2 = 1 applies its outputs' lift_sym (depth lift);
+                     // d2 = kMaxFolds marks one a single grid may run with fold teams
   int c2, d2;
   double bytes;  // algorithmic HBM bytes of the launch (fields read + written once each)
   double flops;  // FFT flops of the launch, 5 N log2 N per complex transform of length N
