@@ -1,8 +1,9 @@
 """GPU parity of the batched tile stepper (zk_batch_*).
 
-Every tile of a batch must equal its own context's zk_step (same kernels
-and team shapes by default: bit-identical up to FP64 rounding order; after
-autotuning, other team shapes round differently: 1e-12), and the oracle at
+Every tile of a batch must equal its own context's zk_step to 1e-12 (same
+team shapes by default, but a single grid runs the last level's G task with
+fold teams, which sum its folds and terms in another order, and autotuned
+shapes round differently too), and the oracle at
 the FP64 bar (1e-10).  The graph path is checked against the launch-by-
 launch path on repeated calls with host synchronisation and eager work in
 between (every replay compared).  FP32 batches: 2e-6 per step against the
