@@ -215,9 +215,30 @@ __host__ __device__ constexpr int lds_len(int N) { return N; }
 constexpr int kTwSlots = 3;
 __host__ __device__ constexpr int tw_slot(int E) { return (E == 2 || E == 3) ? 0 : ((E == 4 || E == 6) ? 1 : 2); }
 
-template <typename R, int N, int E, int NBUF, int DIR>
-__device__ __forceinline__ cpx<R> *team_fft(cpx<R> (&v)[E], cpx<R> *buf0, cpx<R> *buf1,
-                                            const cpx<R> *__restrict__ tw, int t) {
+// Last pass of a team FFT of N = E T points: radix R, NB = N / R butterflies,
+// IT per thread.  Butterfly j = t + T it of that pass owns the elements
+// j + NB r, r < R, of the natural-order result (its output base is j).
+template <int N, int E>
+struct LastPass {
+  static constexpr int T = N / E;
+  static constexpr int NP = num_passes(T);
+  static constexpr int R = later_radix(T, NP - 1);
+  static constexpr int NB = N / R;
+  static constexpr int IT = (NB + T - 1) / T;
+};
+// Registers of the last pass's butterflies: [it][r] holds element j + NB r.
+template <typename R, int N, int E>
+using LastRegs = cpx<R>[LastPass<N, E>::IT][LastPass<N, E>::R];
+
+// Shared body of the two forward-order forms.  KEEP = false: the last pass
+// writes LDS and a final barrier follows (team_fft).  KEEP = true: the last
+// pass leaves butterfly j's outputs in o[it][r] (element j + NB r) and no
+// barrier follows (team_fft_keep); the next transform's first barrier
+// protects the buffers.
+template <typename R, int N, int E, int NBUF, int DIR, bool KEEP>
+__device__ __forceinline__ cpx<R> *team_fft_impl(cpx<R> (&v)[E], cpx<R> *buf0, cpx<R> *buf1,
+                                                 const cpx<R> *__restrict__ tw, int t,
+                                                 cpx<R> (*o)[LastPass<N, E>::R]) {
   constexpr int T = N / E;
   constexpr int NP = num_passes(T);
   static_assert(NP >= 2, "team FFT needs at least two passes");
@@ -242,6 +263,7 @@ __device__ __forceinline__ cpx<R> *team_fft(cpx<R> (&v)[E], cpx<R> *buf0, cpx<R>
       for (int i = 1; i < p; ++i) ns *= later_radix(T, i);
       return ns;
     }();
+    constexpr bool to_regs = KEEP && p == NP - 1;
     __syncthreads();
     cpx<R> w[IT][Rp];
 #pragma unroll
@@ -252,13 +274,12 @@ __device__ __forceinline__ cpx<R> *team_fft(cpx<R> (&v)[E], cpx<R> *buf0, cpx<R>
         for (int r = 0; r < Rp; ++r) w[it][r] = in[lpad(j + r * nb)];
       }
     }
-    if constexpr (NBUF == 1) __syncthreads();
+    if constexpr (NBUF == 1 && !to_regs) __syncthreads();
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int j = t + T * it;
       if (j < nb) {
         const int k = j % Ns;
-        constexpr int step = N / (Ns * Rp);
 #pragma unroll
         for (int r = 1; r < Rp; ++r) {
           cpx<R> tr = tw[Ns - E + (r - 1) * Ns + k];
@@ -266,9 +287,14 @@ __device__ __forceinline__ cpx<R> *team_fft(cpx<R> (&v)[E], cpx<R> *buf0, cpx<R>
           w[it][r] = cmul(w[it][r], tr);
         }
         DFT<Rp, DIR, R>::run(w[it]);
-        const int base = (j / Ns) * Ns * Rp + k;
+        if constexpr (to_regs) {
 #pragma unroll
-        for (int r = 0; r < Rp; ++r) out[lpad(base + r * Ns)] = w[it][r];
+          for (int r = 0; r < Rp; ++r) o[it][r] = w[it][r];  // base = j in the last pass
+        } else {
+          const int base = (j / Ns) * Ns * Rp + k;
+#pragma unroll
+          for (int r = 0; r < Rp; ++r) out[lpad(base + r * Ns)] = w[it][r];
+        }
       }
     }
     if constexpr (NBUF == 2) {
@@ -277,8 +303,96 @@ __device__ __forceinline__ cpx<R> *team_fft(cpx<R> (&v)[E], cpx<R> *buf0, cpx<R>
       out = tmp;
     }
   });
-  __syncthreads();
+  if constexpr (!KEEP) __syncthreads();
   return in;
+}
+
+template <typename R, int N, int E, int NBUF, int DIR>
+__device__ __forceinline__ cpx<R> *team_fft(cpx<R> (&v)[E], cpx<R> *buf0, cpx<R> *buf1,
+                                            const cpx<R> *__restrict__ tw, int t) {
+  return team_fft_impl<R, N, E, NBUF, DIR, false>(v, buf0, buf1, tw, t, nullptr);
+}
+
+// Team FFT whose result stays in registers in the last pass's layout:
+// o[it][r] = X[j + NB r] for butterfly j = t + T it < NB (LastPass<N, E>);
+// o is unset where j >= NB.  In: as team_fft.
+template <typename R, int N, int E, int NBUF, int DIR>
+__device__ __forceinline__ void team_fft_keep(cpx<R> (&v)[E], cpx<R> *buf0, cpx<R> *buf1,
+                                              const cpx<R> *__restrict__ tw, int t,
+                                              LastRegs<R, N, E> &o) {
+  team_fft_impl<R, N, E, NBUF, DIR, true>(v, buf0, buf1, tw, t, o);
+}
+
+// Transposed team FFT: the same passes in reverse order, each with its
+// gather and scatter exchanged and its twiddles applied after the butterfly
+// (the transpose of the algorithm above; the DFT matrix is symmetric, so it
+// computes the same transform from the same twiddle table).  In: x[it][r] =
+// x[j + NB r] for butterfly j = t + T it < NB of LastPass<N, E> (unused where
+// j >= NB), the layout in which the caller loads it; out: v[r] = X[t + T r],
+// the layout of team_fft's input.  No LDS readout: the last (radix-E) step
+// runs in registers.  Every thread of the block must call it.
+template <typename R, int N, int E, int NBUF, int DIR>
+__device__ __forceinline__ void team_fft_t(LastRegs<R, N, E> &x, cpx<R> (&v)[E], cpx<R> *buf0, cpx<R> *buf1,
+                                           const cpx<R> *__restrict__ tw, int t) {
+  constexpr int T = N / E;
+  constexpr int NP = num_passes(T);
+  static_assert(NP >= 2, "team FFT needs at least two passes");
+  asm volatile("" : "+v"(t));
+  cpx<R> *in = buf0;
+  cpx<R> *out = buf0;
+  __syncthreads();  // readers of the previous transform's buffers are done
+  static_for<1, NP>([&](auto qc) {
+    constexpr int p = NP - decltype(qc)::value;  // NP - 1 down to 1
+    constexpr int Rp = later_radix(T, p);
+    constexpr int nb = N / Rp;
+    constexpr int IT = (nb + T - 1) / T;
+    constexpr int Ns = [] {
+      int ns = E;
+      for (int i = 1; i < p; ++i) ns *= later_radix(T, i);
+      return ns;
+    }();
+    constexpr bool from_regs = p == NP - 1;
+    cpx<R> w[IT][Rp];
+    if constexpr (!from_regs) {
+      __syncthreads();
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int j = t + T * it;
+        if (j < nb) {
+          const int base = (j / Ns) * Ns * Rp + j % Ns;
+#pragma unroll
+          for (int r = 0; r < Rp; ++r) w[it][r] = in[lpad(base + r * Ns)];
+        }
+      }
+      if constexpr (NBUF == 1) __syncthreads();
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int j = t + T * it;
+      if (j < nb) {
+        if constexpr (from_regs) {
+#pragma unroll
+          for (int r = 0; r < Rp; ++r) w[it][r] = x[it][r];
+        }
+        const int k = j % Ns;
+        DFT<Rp, DIR, R>::run(w[it]);
+#pragma unroll
+        for (int r = 1; r < Rp; ++r) {
+          cpx<R> tr = tw[Ns - E + (r - 1) * Ns + k];
+          if constexpr (DIR > 0) tr.y = -tr.y;
+          w[it][r] = cmul(w[it][r], tr);
+        }
+#pragma unroll
+        for (int r = 0; r < Rp; ++r) out[lpad(j + r * nb)] = w[it][r];
+      }
+    }
+    in = out;
+    if constexpr (NBUF == 2) out = (out == buf0) ? buf1 : buf0;
+  });
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < E; ++r) v[r] = in[lpad(t * E + r)];
+  DFT<E, DIR, R>::run(v);
 }
 
 }  // namespace zk

@@ -628,8 +628,6 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
     const int b = t + T * q;
     return (b < ny / 2) ? b : b - ny;
   };
-  // padded (or base) position of base element q
-  auto pos_of = [&](int q) { return t + T * (q < S::KR ? q : q + (S::PADDED ? E / 3 : 0)); };
   double skk[QB], sg0[QB], stp[QB];
 #pragma unroll
   for (int q = 0; q < QB; ++q) {
@@ -646,10 +644,25 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   cpx<double> X[QB];
 #pragma unroll
   for (int q = 0; q < QB; ++q) X[q] = {0.0, 0.0};
-  auto fold_into = [&](const cpx<real> *res, uint32_t fsym, double fcoef) {
+  // Folds run the transposed transform: the column is loaded in the layout
+  // of the transform's first butterflies and the result arrives in registers,
+  // element t + T r in v[r]; base element q sits at padded (or base)
+  // position t + T base_slot(q).
+  using LP = LastPass<N, E>;
+  auto base_slot = [](int q) { return q < S::KR ? q : q + (S::PADDED ? E / 3 : 0); };
+  auto load_col = [&](const cpx<real> *F, cpx<real> (&x)[LP::IT][LP::R]) {
+#pragma unroll
+    for (int it = 0; it < LP::IT; ++it) {
+      const int j = t + T * it;
+#pragma unroll
+      for (int r = 0; r < LP::R; ++r) x[it][r] = j < LP::NB ? gload(F, mix_index<real>(col, j + LP::NB * r, a.rows))
+                                                           : cpx<real>{(real)0, (real)0};
+    }
+  };
+  auto fold_into = [&](const cpx<real> (&v)[E], uint32_t fsym, double fcoef) {
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
-      const cpx<real> w = res[lpad(pos_of(q))];
+      const cpx<real> w = v[base_slot(q)];
       const cpx<double> sv = sym(fsym, q);
       const cpx<double> x = {(double)w.x * fcoef, (double)w.y * fcoef};
       X[q].x += x.x * sv.x - x.y * sv.y;
@@ -659,20 +672,20 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   if constexpr (FT == 1) {
     // Folds: the next field's column is loaded while the current one is
     // transformed (folds are consecutive from slot 0).
-    cpx<real> vn[E];
-    auto load_fold = [&](int f) {
-      const cpx<real> *F = a.mix + (long long)task.fwd[f] * a.mix_stride;
-#pragma unroll
-      for (int r = 0; r < E; ++r) vn[r] = gload(F, mix_index<real>(col, t + T * r, a.rows));
-    };
+    cpx<real> xn[LP::IT][LP::R];
+    auto load_fold = [&](int f) { load_col(a.mix + (long long)task.fwd[f] * a.mix_stride, xn); };
     if (task.fwd[0] >= 0) load_fold(0);
     for (int f = 0; f < kMaxFolds; ++f) {
       if (task.fwd[f] < 0) break;
-      cpx<real> v[E];
+      cpx<real> x[LP::IT][LP::R];
 #pragma unroll
-      for (int r = 0; r < E; ++r) v[r] = vn[r];
+      for (int it = 0; it < LP::IT; ++it)
+#pragma unroll
+        for (int r = 0; r < LP::R; ++r) x[it][r] = xn[it][r];
       if (f + 1 < kMaxFolds && task.fwd[f + 1] >= 0) load_fold(f + 1);
-      fold_into(team_fft<real, N, E, NB, -1>(v, b0, b1, tw, t), task.fwd_sym[f], task.fwd_coef[f]);
+      cpx<real> v[E];
+      team_fft_t<real, N, E, NB, -1>(x, v, b0, b1, tw, t);
+      fold_into(v, task.fwd_sym[f], task.fwd_coef[f]);
     }
   } else if (task.fwd[0] >= 0) {
     // Team f folds field f (a team without one transforms zeros); the parts
@@ -687,16 +700,15 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
         fsym = task.fwd_sym[f];
         fcoef = task.fwd_coef[f];
       }
+    cpx<real> x[LP::IT][LP::R];
+#pragma unroll
+    for (int it = 0; it < LP::IT; ++it)
+#pragma unroll
+      for (int r = 0; r < LP::R; ++r) x[it][r] = {(real)0, (real)0};
+    if (fid >= 0) load_col(a.mix + (long long)fid * a.mix_stride, x);
     cpx<real> v[E];
-#pragma unroll
-    for (int r = 0; r < E; ++r) v[r] = {(real)0, (real)0};
-    if (fid >= 0) {
-      const cpx<real> *F = a.mix + (long long)fid * a.mix_stride;
-#pragma unroll
-      for (int r = 0; r < E; ++r) v[r] = gload(F, mix_index<real>(col, t + T * r, a.rows));
-    }
-    const cpx<real> *res = team_fft<real, N, E, NB, -1>(v, b0, b1, tw, t);
-    if (fid >= 0) fold_into(res, fsym, fcoef);
+    team_fft_t<real, N, E, NB, -1>(x, v, b0, b1, tw, t);
+    if (fid >= 0) fold_into(v, fsym, fcoef);
 #pragma unroll
     for (int q = 0; q < QB; ++q) xs[(team * QB + q) * T + t] = X[q];
     __syncthreads();
@@ -800,15 +812,23 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
           if (out.lift_sym) f *= lift_factor(out.lift_sym, skk[q], col, t + T * q, a.nx, ny, a.depth, a.layer_y);
         z[r] = {(real)(acc[q].x * f), (real)(acc[q].y * f)};
       }
-      const cpx<real> *res = team_fft<real, N, E, NB, +1>(z, b0, b1, tw, t);
+      // the last pass's outputs are stored from registers (element j + NB r)
+      cpx<real> o[LP::IT][LP::R];
+      team_fft_keep<real, N, E, NB, +1>(z, b0, b1, tw, t, o);
       float m = 0.f;
       if (writer) {  // fold teams: every team transformed the same combination
         cpx<real> *F = a.mix + (long long)out.dst_mixed * a.mix_stride;
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-          const cpx<real> w = res[lpad(t + T * r)];
-          gstore(F, mix_index<real>(col, t + T * r, a.rows), w);
-          m = fmaxf(m, fmaxf(fabsf((float)w.x), fabsf((float)w.y)));
+        for (int it = 0; it < LP::IT; ++it) {
+          const int j = t + T * it;
+          if (j < LP::NB) {
+#pragma unroll
+            for (int r = 0; r < LP::R; ++r) {
+              const cpx<real> w = o[it][r];
+              gstore(F, mix_index<real>(col, j + LP::NB * r, a.rows), w);
+              m = fmaxf(m, fmaxf(fabsf((float)w.x), fabsf((float)w.y)));
+            }
+          }
         }
       }
       m = team_max<T>(m, red);
