@@ -347,21 +347,27 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         // Data loads first; the field maxima (one per column, published by
         // the lifts) are reduced over all columns by each wavefront on its
         // own, so no block barrier sits between the loads and their use.
-        cpx<real> zb[E];
+        // The half spectra are loaded in the layout of the transposed
+        // transform's first butterflies (element p = j + NB r of butterfly
+        // j = t + T it), whose result arrives in z[] as element t + T e.
+        using LP = LastPass<N, E>;
+        cpx<real> xa[LP::IT][LP::R], xb[LP::IT][LP::R];
+        auto elem = [&](int it, int r) { return t + T * it + LP::NB * r; };
+        auto live = [&](int it) { return t + T * it < LP::NB; };
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-          cpx<real> za = {0, 0};
-          zb[r] = {0, 0};
-          const bool pos = r < S::KR;
-          const bool neg = (r > S::NEG0) || (r == S::NEG0 && t > 0);
-          if (pos || neg) {
-            const int kk = pos ? (t + T * r) : ((E - r) * T - t);
-            const int idx = mix_index<real>(kk, row, a.rows);
-            za = gload(Fa, idx);
-            if (has_b) zb[r] = gload(Fb, idx);
+        for (int it = 0; it < LP::IT; ++it)
+#pragma unroll
+          for (int r = 0; r < LP::R; ++r) {
+            const int p = elem(it, r);
+            const bool pos = p < S::KR * T, neg = p > S::NEG0 * T;  // kept band, upper half by symmetry
+            xa[it][r] = {(real)0, (real)0};
+            xb[it][r] = {(real)0, (real)0};
+            if (live(it) && (pos || neg)) {
+              const int idx = mix_index<real>(pos ? p : N - p, row, a.rows);
+              xa[it][r] = gload(Fa, idx);
+              if (has_b) xb[it][r] = gload(Fb, idx);
+            }
           }
-          z[r] = za;
-        }
         float ma = 0.f, mb = 0.f;
         {
           constexpr int NC = S::KR * T;  // nx / 2 columns
@@ -380,29 +386,27 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         const float2 pb = has_b ? pow2_scale(mb) : make_float2(1.f, 1.f);
         const real sa = (real)pa.x, sb = (real)pb.x;
 #pragma unroll
-        for (int r = 0; r < E; ++r) {
-          const bool pos = r < S::KR;
-          const bool neg = (r > S::NEG0) || (r == S::NEG0 && t > 0);
-          cpx<real> za = z[r], zbr = zb[r];
-          if (pos || neg) {
-            const int kk = pos ? (t + T * r) : ((E - r) * T - t);
-            const real kxv = (real)(a.kx_scale * kk);
-            if (dxa) za = {-kxv * za.y, kxv * za.x};
-            if (dxb) zbr = {-kxv * zbr.y, kxv * zbr.x};
-            if (neg) {
-              za.y = -za.y;
-              zbr.y = -zbr.y;
+        for (int it = 0; it < LP::IT; ++it)
+#pragma unroll
+          for (int r = 0; r < LP::R; ++r) {
+            const int p = elem(it, r);
+            const bool pos = p < S::KR * T, neg = p > S::NEG0 * T;
+            cpx<real> za = xa[it][r], zbr = xb[it][r];
+            if (pos || neg) {
+              const real kxv = (real)(a.kx_scale * (pos ? p : N - p));
+              if (dxa) za = {-kxv * za.y, kxv * za.x};
+              if (dxb) zbr = {-kxv * zbr.y, kxv * zbr.x};
+              if (neg) {
+                za.y = -za.y;
+                zbr.y = -zbr.y;
+              }
             }
+            xa[it][r] = {za.x * sa - zbr.y * sb, za.y * sa + zbr.x * sb};
           }
-          z[r] = {za.x * sa - zbr.y * sb, za.y * sa + zbr.x * sb};
-        }
-        const cpx<real> *res = team_fft<real, N, E, NB, +1>(z, b0, b1, tw, t);
+        team_fft_t<real, N, E, NB, +1>(xa, z, b0, b1, tw, t);
         const real ia = (real)pa.y, ib = (real)pb.y;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const cpx<real> w = res[lpad(t + T * e)];
-          z[e] = {w.x * ia, w.y * ib};
-        }
+        for (int e = 0; e < E; ++e) z[e] = {z[e].x * ia, z[e].y * ib};
         break;
       }
       case OP_LDP: {
