@@ -395,4 +395,35 @@ __device__ __forceinline__ void team_fft_t(LastRegs<R, N, E> &x, cpx<R> (&v)[E],
   DFT<E, DIR, R>::run(v);
 }
 
+// Register layouts on the HBM side of a transform.  LAST: the last pass's
+// butterfly layout ([it][r] = element t + T it + NB r, live where
+// t + T it < NB), used by team_fft_t (input) and team_fft_keep (output);
+// otherwise the team layout ([0][r] = element t + T r).
+template <int N, int E, bool LAST>
+struct HbmLayout {
+  static constexpr int T = N / E;
+  static constexpr int IT = LAST ? LastPass<N, E>::IT : 1;
+  static constexpr int R = LAST ? LastPass<N, E>::R : E;
+  static constexpr int STRIDE = LAST ? LastPass<N, E>::NB : T;
+  __device__ __forceinline__ static bool live(int t, int it) { return !LAST || t + T * it < LastPass<N, E>::NB; }
+  __device__ __forceinline__ static int elem(int t, int it, int r) { return t + T * it + STRIDE * r; }
+};
+template <typename R, int N, int E, bool LAST>
+using HbmRegs = cpx<R>[HbmLayout<N, E, LAST>::IT][HbmLayout<N, E, LAST>::R];
+
+// x in the HBM-side layout -> v[r] = X[t + T r].
+template <typename R, int N, int E, int NBUF, int DIR, bool LAST>
+__device__ __forceinline__ void fft_in(HbmRegs<R, N, E, LAST> &x, cpx<R> (&v)[E], cpx<R> *buf0, cpx<R> *buf1,
+                                       const cpx<R> *__restrict__ tw, int t) {
+  if constexpr (LAST) {
+    team_fft_t<R, N, E, NBUF, DIR>(x, v, buf0, buf1, tw, t);
+  } else {
+#pragma unroll
+    for (int r = 0; r < E; ++r) v[r] = x[0][r];
+    const cpx<R> *res = team_fft<R, N, E, NBUF, DIR>(v, buf0, buf1, tw, t);
+#pragma unroll
+    for (int r = 0; r < E; ++r) v[r] = res[lpad(t + (N / E) * r)];
+  }
+}
+
 }  // namespace zk

@@ -347,17 +347,20 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         // Data loads first; the field maxima (one per column, published by
         // the lifts) are reduced over all columns by each wavefront on its
         // own, so no block barrier sits between the loads and their use.
-        // The half spectra are loaded in the layout of the transposed
-        // transform's first butterflies (element p = j + NB r of butterfly
-        // j = t + T it), whose result arrives in z[] as element t + T e.
-        using LP = LastPass<N, E>;
-        cpx<real> xa[LP::IT][LP::R], xb[LP::IT][LP::R];
-        auto elem = [&](int it, int r) { return t + T * it + LP::NB * r; };
-        auto live = [&](int it) { return t + T * it < LP::NB; };
+        // Up to 512-thread teams the half spectra are loaded in the layout of
+        // the transposed transform's first butterflies (element p = j + NB r
+        // of butterfly j = t + T it); its result arrives in z[] as element
+        // t + T e without an LDS readout.  (1024-thread teams measured faster
+        // with team_fft from the t + T e layout.)
+        constexpr bool XP = T <= 512;
+        using HL = HbmLayout<N, E, XP>;
+        cpx<real> xa[HL::IT][HL::R], xb[HL::IT][HL::R];
+        auto elem = [&](int it, int r) { return HL::elem(t, it, r); };
+        auto live = [&](int it) { return HL::live(t, it); };
 #pragma unroll
-        for (int it = 0; it < LP::IT; ++it)
+        for (int it = 0; it < HL::IT; ++it)
 #pragma unroll
-          for (int r = 0; r < LP::R; ++r) {
+          for (int r = 0; r < HL::R; ++r) {
             const int p = elem(it, r);
             const bool pos = p < S::KR * T, neg = p > S::NEG0 * T;  // kept band, upper half by symmetry
             xa[it][r] = {(real)0, (real)0};
@@ -386,9 +389,9 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         const float2 pb = has_b ? pow2_scale(mb) : make_float2(1.f, 1.f);
         const real sa = (real)pa.x, sb = (real)pb.x;
 #pragma unroll
-        for (int it = 0; it < LP::IT; ++it)
+        for (int it = 0; it < HL::IT; ++it)
 #pragma unroll
-          for (int r = 0; r < LP::R; ++r) {
+          for (int r = 0; r < HL::R; ++r) {
             const int p = elem(it, r);
             const bool pos = p < S::KR * T, neg = p > S::NEG0 * T;
             cpx<real> za = xa[it][r], zbr = xb[it][r];
@@ -403,7 +406,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
             }
             xa[it][r] = {za.x * sa - zbr.y * sb, za.y * sa + zbr.x * sb};
           }
-        team_fft_t<real, N, E, NB, +1>(xa, z, b0, b1, tw, t);
+        fft_in<real, N, E, NB, +1, XP>(xa, z, b0, b1, tw, t);
         const real ia = (real)pa.y, ib = (real)pb.y;
 #pragma unroll
         for (int e = 0; e < E; ++e) z[e] = {z[e].x * ia, z[e].y * ib};
@@ -648,48 +651,66 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   cpx<double> X[QB];
 #pragma unroll
   for (int q = 0; q < QB; ++q) X[q] = {0.0, 0.0};
-  // Folds run the transposed transform: the column is loaded in the layout
-  // of the transform's first butterflies and the result arrives in registers,
-  // element t + T r in v[r]; base element q sits at padded (or base)
-  // position t + T base_slot(q).
-  using LP = LastPass<N, E>;
+  // Up to 512-thread teams folds run the transposed transform (the column
+  // is loaded in the layout of its first butterflies) and lifts keep the
+  // last pass in registers (stored from there), each an LDS round trip
+  // fewer; 1024-thread teams, and the depth-lift variant, whose registers
+  // these forms would push past an occupancy step, use team_fft with LDS
+  // readouts.  Either way a fold's result is element t + T r in v[r]; base
+  // element q sits at padded (or base) position t + T base_slot(q).
+  constexpr bool XP = T <= 512 && !LIFTSYM, KEEP = XP;
+  using HL = HbmLayout<N, E, XP>;
+  using HO = HbmLayout<N, E, true>;
   auto base_slot = [](int q) { return q < S::KR ? q : q + (S::PADDED ? E / 3 : 0); };
-  auto load_col = [&](const cpx<real> *F, cpx<real> (&x)[LP::IT][LP::R]) {
+  auto load_col = [&](const cpx<real> *F, HbmRegs<real, N, E, XP> &x) {
 #pragma unroll
-    for (int it = 0; it < LP::IT; ++it) {
-      const int j = t + T * it;
+    for (int it = 0; it < HL::IT; ++it)
 #pragma unroll
-      for (int r = 0; r < LP::R; ++r) x[it][r] = j < LP::NB ? gload(F, mix_index<real>(col, j + LP::NB * r, a.rows))
-                                                           : cpx<real>{(real)0, (real)0};
-    }
+      for (int r = 0; r < HL::R; ++r)
+        x[it][r] = HL::live(t, it) ? gload(F, mix_index<real>(col, HL::elem(t, it, r), a.rows))
+                                   : cpx<real>{(real)0, (real)0};
   };
-  auto fold_into = [&](const cpx<real> (&v)[E], uint32_t fsym, double fcoef) {
+  // get(r): element t + T r of the fold's transform
+  auto fold_into = [&](auto get, uint32_t fsym, double fcoef) {
 #pragma unroll
     for (int q = 0; q < QB; ++q) {
-      const cpx<real> w = v[base_slot(q)];
+      const cpx<real> w = get(base_slot(q));
       const cpx<double> sv = sym(fsym, q);
       const cpx<double> x = {(double)w.x * fcoef, (double)w.y * fcoef};
       X[q].x += x.x * sv.x - x.y * sv.y;
       X[q].y += x.x * sv.y + x.y * sv.x;
     }
   };
+  // transform x (HBM-side layout) and fold it: XP from registers, else
+  // read from LDS as it is needed
+  auto transform_fold = [&](HbmRegs<real, N, E, XP> &x, uint32_t fsym, double fcoef, bool use) {
+    if constexpr (XP) {
+      cpx<real> v[E];
+      team_fft_t<real, N, E, NB, -1>(x, v, b0, b1, tw, t);
+      if (use) fold_into([&](int r) { return v[r]; }, fsym, fcoef);
+    } else {
+      cpx<real> v[E];
+#pragma unroll
+      for (int r = 0; r < E; ++r) v[r] = x[0][r];
+      const cpx<real> *res = team_fft<real, N, E, NB, -1>(v, b0, b1, tw, t);
+      if (use) fold_into([&](int r) { return res[lpad(t + T * r)]; }, fsym, fcoef);
+    }
+  };
   if constexpr (FT == 1) {
     // Folds: the next field's column is loaded while the current one is
     // transformed (folds are consecutive from slot 0).
-    cpx<real> xn[LP::IT][LP::R];
+    cpx<real> xn[HL::IT][HL::R];
     auto load_fold = [&](int f) { load_col(a.mix + (long long)task.fwd[f] * a.mix_stride, xn); };
     if (task.fwd[0] >= 0) load_fold(0);
     for (int f = 0; f < kMaxFolds; ++f) {
       if (task.fwd[f] < 0) break;
-      cpx<real> x[LP::IT][LP::R];
+      cpx<real> x[HL::IT][HL::R];
 #pragma unroll
-      for (int it = 0; it < LP::IT; ++it)
+      for (int it = 0; it < HL::IT; ++it)
 #pragma unroll
-        for (int r = 0; r < LP::R; ++r) x[it][r] = xn[it][r];
+        for (int r = 0; r < HL::R; ++r) x[it][r] = xn[it][r];
       if (f + 1 < kMaxFolds && task.fwd[f + 1] >= 0) load_fold(f + 1);
-      cpx<real> v[E];
-      team_fft_t<real, N, E, NB, -1>(x, v, b0, b1, tw, t);
-      fold_into(v, task.fwd_sym[f], task.fwd_coef[f]);
+      transform_fold(x, task.fwd_sym[f], task.fwd_coef[f], true);
     }
   } else if (task.fwd[0] >= 0) {
     // Team f folds field f (a team without one transforms zeros); the parts
@@ -704,15 +725,13 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
         fsym = task.fwd_sym[f];
         fcoef = task.fwd_coef[f];
       }
-    cpx<real> x[LP::IT][LP::R];
+    cpx<real> x[HL::IT][HL::R];
 #pragma unroll
-    for (int it = 0; it < LP::IT; ++it)
+    for (int it = 0; it < HL::IT; ++it)
 #pragma unroll
-      for (int r = 0; r < LP::R; ++r) x[it][r] = {(real)0, (real)0};
+      for (int r = 0; r < HL::R; ++r) x[it][r] = {(real)0, (real)0};
     if (fid >= 0) load_col(a.mix + (long long)fid * a.mix_stride, x);
-    cpx<real> v[E];
-    team_fft_t<real, N, E, NB, -1>(x, v, b0, b1, tw, t);
-    if (fid >= 0) fold_into(v, fsym, fcoef);
+    transform_fold(x, fsym, fcoef, fid >= 0);
 #pragma unroll
     for (int q = 0; q < QB; ++q) xs[(team * QB + q) * T + t] = X[q];
     __syncthreads();
@@ -816,24 +835,27 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
           if (out.lift_sym) f *= lift_factor(out.lift_sym, skk[q], col, t + T * q, a.nx, ny, a.depth, a.layer_y);
         z[r] = {(real)(acc[q].x * f), (real)(acc[q].y * f)};
       }
-      // the last pass's outputs are stored from registers (element j + NB r)
-      cpx<real> o[LP::IT][LP::R];
-      team_fft_keep<real, N, E, NB, +1>(z, b0, b1, tw, t, o);
       float m = 0.f;
-      if (writer) {  // fold teams: every team transformed the same combination
-        cpx<real> *F = a.mix + (long long)out.dst_mixed * a.mix_stride;
+      cpx<real> *F = a.mix + (long long)out.dst_mixed * a.mix_stride;
+      auto put = [&](int e, const cpx<real> &w) {  // element e of the lifted column
+        gstore(F, mix_index<real>(col, e, a.rows), w);
+        m = fmaxf(m, fmaxf(fabsf((float)w.x), fabsf((float)w.y)));
+      };
+      // fold teams: every team transformed the same combination, team 0 writes
+      if constexpr (KEEP) {
+        cpx<real> o[HO::IT][HO::R];
+        team_fft_keep<real, N, E, NB, +1>(z, b0, b1, tw, t, o);
+        if (writer)
 #pragma unroll
-        for (int it = 0; it < LP::IT; ++it) {
-          const int j = t + T * it;
-          if (j < LP::NB) {
+          for (int it = 0; it < HO::IT; ++it)
+            if (HO::live(t, it))
 #pragma unroll
-            for (int r = 0; r < LP::R; ++r) {
-              const cpx<real> w = o[it][r];
-              gstore(F, mix_index<real>(col, j + LP::NB * r, a.rows), w);
-              m = fmaxf(m, fmaxf(fabsf((float)w.x), fabsf((float)w.y)));
-            }
-          }
-        }
+              for (int r = 0; r < HO::R; ++r) put(HO::elem(t, it, r), o[it][r]);
+      } else {
+        const cpx<real> *res = team_fft<real, N, E, NB, +1>(z, b0, b1, tw, t);
+        if (writer)
+#pragma unroll
+          for (int r = 0; r < E; ++r) put(t + T * r, res[lpad(t + T * r)]);
       }
       m = team_max<T>(m, red);
       if (t == 0 && writer) gstore1(a.colmax, (long long)out.dst_mixed * (a.nx / 2) + col, m);
