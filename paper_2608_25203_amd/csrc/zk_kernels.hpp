@@ -347,12 +347,13 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         // Data loads first; the field maxima (one per column, published by
         // the lifts) are reduced over all columns by each wavefront on its
         // own, so no block barrier sits between the loads and their use.
-        // Up to 512-thread teams the half spectra are loaded in the layout of
-        // the transposed transform's first butterflies (element p = j + NB r
-        // of butterfly j = t + T it); its result arrives in z[] as element
-        // t + T e without an LDS readout.  (1024-thread teams measured faster
-        // with team_fft from the t + T e layout.)
-        constexpr bool XP = T <= 512;
+        // Padded passes up to 512-thread teams load the half spectra in the
+        // layout of the transposed transform's first butterflies (element
+        // p = j + NB r of butterfly j = t + T it); its result arrives in z[]
+        // as element t + T e without an LDS readout.  (1024-thread teams, and
+        // base lengths, whose last pass keeps only half the team busy,
+        // measured faster with team_fft from the t + T e layout.)
+        constexpr bool XP = T <= 512 && S::PADDED;
         using HL = HbmLayout<N, E, XP>;
         cpx<real> xa[HL::IT][HL::R], xb[HL::IT][HL::R];
         auto elem = [&](int it, int r) { return HL::elem(t, it, r); };
@@ -651,14 +652,15 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   cpx<double> X[QB];
 #pragma unroll
   for (int q = 0; q < QB; ++q) X[q] = {0.0, 0.0};
-  // Up to 512-thread teams folds run the transposed transform (the column
-  // is loaded in the layout of its first butterflies) and lifts keep the
-  // last pass in registers (stored from there), each an LDS round trip
-  // fewer; 1024-thread teams, and the depth-lift variant, whose registers
-  // these forms would push past an occupancy step, use team_fft with LDS
-  // readouts.  Either way a fold's result is element t + T r in v[r]; base
-  // element q sits at padded (or base) position t + T base_slot(q).
-  constexpr bool XP = T <= 512 && !LIFTSYM, KEEP = XP;
+  // Padded passes up to 512-thread teams run folds on the transposed
+  // transform (the column is loaded in the layout of its first butterflies)
+  // and keep a lift's last pass in registers (stored from there), each an
+  // LDS round trip fewer; 1024-thread teams and base lengths (measured
+  // faster without) and the depth-lift variant (whose registers these forms
+  // would push past an occupancy step) use team_fft with LDS readouts.
+  // Either way a fold's result is element t + T r in v[r]; base element q
+  // sits at padded (or base) position t + T base_slot(q).
+  constexpr bool XP = T <= 512 && S::PADDED && !LIFTSYM, KEEP = XP;
   using HL = HbmLayout<N, E, XP>;
   using HO = HbmLayout<N, E, true>;
   auto base_slot = [](int q) { return q < S::KR ? q : q + (S::PADDED ? E / 3 : 0); };
