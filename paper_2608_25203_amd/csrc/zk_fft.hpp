@@ -5,8 +5,11 @@
 // butterfly entirely in registers (E = 3, 6 or 12 for the 3/2-padded lengths
 // 3*2^k, E = 2, 4 or 8 for the base lengths 2^k); the remaining radix-4/2
 // passes exchange through LDS (Stockham autosort: natural order in, natural
-// order out), and the result is left in LDS for the caller to read in
-// whatever element-to-thread mapping it needs.
+// order out).  team_fft leaves the result in LDS for the caller to read in
+// whatever element-to-thread mapping it needs; team_fft_keep leaves it in
+// registers in the last pass's layout, and team_fft_t (the transposed
+// algorithm) takes its input in that layout and returns the result in the
+// t + T*r layout, each one LDS round trip fewer.
 #pragma once
 #include <hip/hip_runtime.h>
 

@@ -595,8 +595,9 @@ __device__ __forceinline__ cpx<double> symval(uint32_t s, double kk, double g0, 
 // FT = kMaxFolds (fold teams): the block's FT teams share one column; team f
 // transforms fold f and sums a share of each output's terms, the parts are
 // summed through LDS in team order, so a task with several folds and long
-// term lists runs them side by side instead of in sequence.  Thread t owns base-band rows b = t + T q, q < QB (q = KR at
-// t = 0 is the ky Nyquist row, kept zero).
+// term lists runs them side by side instead of in sequence.  Thread t owns
+// base-band rows b = t + T q, q < QB (q = KR at t = 0 is the ky Nyquist row,
+// kept zero).
 template <int T, int FT>
 struct ColBlock {
   static constexpr int BS = FT == 1 ? (T > 256 ? T : 256) : FT * T;  // threads per block
@@ -901,7 +902,7 @@ __global__ __launch_bounds__(T > 256 ? T : 256) void col_kernel_batch(const ColA
   col_body<real, T, E, LIFTSYM>(a, it.index, blockIdx.x);
 }
 // Fold teams: kMaxFolds teams of T threads per block, one column per block
-// (tasks whose folds and outputs run side by side).
+// (tasks whose folds and terms run side by side).
 template <typename real, int T, int E>
 __global__ __launch_bounds__(kMaxFolds * T) void col_kernel_folds(const ColArgs<real> *__restrict__ args,
                                                              const BatchItem *__restrict__ items, PhysArgs) {
