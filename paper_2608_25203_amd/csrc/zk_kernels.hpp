@@ -285,6 +285,25 @@ __device__ __forceinline__ Tp uniform_load(const Tp *p) {
   return v;
 }
 
+// Stage a shape's twiddle table (n entries) in LDS with BS threads: each
+// thread issues all its loads before its first store, so the copy costs one
+// global latency rather than one per entry a thread copies.
+template <int BS, int n, typename R>
+__device__ __forceinline__ void stage_twiddles(cpx<R> *dst, const cpx<R> *src) {
+  constexpr int K = (n + BS - 1) / BS;
+  cpx<R> v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = threadIdx.x + BS * k;
+    if (i < n) v[k] = gload(src, i);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = threadIdx.x + BS * k;
+    if (i < n) dst[i] = v[k];
+  }
+}
+
 // One entry of a batched launch: the tile's argument record and the
 // program (row pass) or task (column pass) its blocks run.
 struct BatchItem {
@@ -311,7 +330,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   const RowProg pg = uniform_load(a.progs + prog);
   const cpx<real> *tw = a.tw + tw_slot(E) * N;  // this shape's pass-ordered table
   if constexpr (TWL) {
-    for (int i = threadIdx.x; i < N - E; i += S::BS) twl[i] = gload(tw, i);
+    stage_twiddles<S::BS, N - E>(twl, tw);
     tw = twl;
   }
   __syncthreads();
@@ -628,7 +647,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   const int ny = a.ny;
   const cpx<real> *tw = a.tw + tw_slot(E) * N;  // this shape's pass-ordered table
   if constexpr (TWL) {
-    for (int i = threadIdx.x; i < N - E; i += CB::BS) twl[i] = gload(tw, i);
+    stage_twiddles<CB::BS, N - E>(twl, tw);
     tw = twl;
   }
   __syncthreads();
