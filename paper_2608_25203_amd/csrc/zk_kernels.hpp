@@ -333,7 +333,8 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
     stage_twiddles<S::BS, N - E>(twl, tw);
     tw = twl;
   }
-  __syncthreads();
+  // No barrier here: every transform form opens with one before its first
+  // twiddle read, which publishes the staged table.
 
   // Register sets: u = z[].x, v = z[].y (the FFT buffer), then A, o0, o1, o2.
   cpx<real> z[E];
@@ -650,7 +651,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
     stage_twiddles<CB::BS, N - E>(twl, tw);
     tw = twl;
   }
-  __syncthreads();
+  // (no barrier: the first transform's opening barrier publishes the table)
 
   auto my_of = [&](int q) {
     const int b = t + T * q;
