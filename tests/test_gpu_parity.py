@@ -82,25 +82,27 @@ def test_dtn_rhs_parity_small(torch, M, shape):
     assert rel(host(a), a0) < 1e-10 and rel(host(b), b0) < 1e-10
 
 
-@pytest.mark.parametrize("M", [2, 6])
-def test_fold_team_column_parity(torch, M):
+@pytest.mark.parametrize("M,precision", [(2, 64), (6, 64), (4, 32)])
+def test_fold_team_column_parity(torch, M, precision):
     """256 x 256 (128-thread column teams): the last level's G task runs with
     fold teams (three folds side by side, terms split over the teams) and the
     padded passes with the transposed and register-output transforms; G psi,
-    the RHS and one RK4 step against the oracle at 1e-10."""
+    the RHS and one RK4 step against the oracle at 1e-10 (FP64), or at the
+    FP32 form's 2e-5 / 2e-6."""
     n, L, h = 256, 4.0, 0.8
     kmax = math.hypot(math.pi * n / L, math.pi * n / L)
     eta, psi = random_band_fields(n, n, 40 + M, n // 2 - 1, amplitude=0.1 / kmax)
-    s = solver(torch, n, n, L, L, h, M)
+    s = solver(torch, n, n, L, L, h, M, precision=precision)
     m = HOSModel(Grid(n, n, L, L, h), M)
     e, p = dev(torch, eta), dev(torch, psi)
-    assert rel(host(s.dtn(e, p)), m.dtn(eta, psi)) < 1e-10
+    tol, tol_step = (1e-10, 1e-10) if precision == 64 else (2e-5, 2e-6)
+    assert rel(host(s.dtn(e, p)), m.dtn(eta, psi)) < tol
     a, b = s.rhs(e, p)
     a0, b0 = m.rhs(eta, psi)
-    assert rel(host(a), a0) < 1e-10 and rel(host(b), b0) < 1e-10
+    assert rel(host(a), a0) < tol and rel(host(b), b0) < tol
     s.step(e, p, 1e-3, 1)
     e0, p0 = m.step(eta, psi, 1e-3, 1)
-    assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
+    assert rel(host(e), e0) < tol_step and rel(host(p), p0) < tol_step
 
 
 @pytest.mark.parametrize("eps,taper,filt", [(0.3, True, True), (1.0, False, False), (0.0, True, True)])
