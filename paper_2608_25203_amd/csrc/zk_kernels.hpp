@@ -288,6 +288,25 @@ __device__ __forceinline__ Tp uniform_load(const Tp *p) {
 // Stage a shape's twiddle table (n entries) in LDS with BS threads: each
 // thread issues all its loads before its first store, so the copy costs one
 // global latency rather than one per entry a thread copies.
+// Stage the table by direct global-to-LDS loads instead (16 bytes per lane,
+// one wavefront-wide chunk per load): no registers, and the wave goes on at
+// once, its later loads overlapping these.  Each wave must wait for its
+// vector memory counter (twiddles_landed) before the barrier that opens its
+// first transform, and before it ends.
+template <int BS, int n, typename R>
+__device__ __forceinline__ void stage_twiddles_async(cpx<R> *dst, const cpx<R> *src) {
+  constexpr int EPL = 16 / (int)sizeof(cpx<R>), CH = 64 * EPL, NW = BS / 64;
+  static_assert(BS % 64 == 0 && EPL >= 1, "whole wavefronts, 16-byte lanes");
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64)), lane = threadIdx.x % 64;
+  for (int c = w; c * CH < n; c += NW) {
+    const int i = c * CH + lane * EPL;
+    if (i < n)
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(src + i),
+                                       (__attribute__((address_space(3))) void *)(dst + c * CH), 16, 0, 0);
+  }
+}
+__device__ __forceinline__ void twiddles_landed() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 template <int BS, int n, typename R>
 __device__ __forceinline__ void stage_twiddles(cpx<R> *dst, const cpx<R> *src) {
   constexpr int K = (n + BS - 1) / BS;
@@ -319,7 +338,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   constexpr int N = S::N, L = S::L, NB = S::template nbuf<real>();
   constexpr bool TWL = S::template tw_in_lds<real>();
   __shared__ cpx<real> smem[S::TPB * NB * L];
-  __shared__ cpx<real> twl[TWL ? N : 1];
+  __shared__ __attribute__((aligned(16))) cpx<real> twl[TWL ? N : 1];
   __shared__ float red[2 * (S::BS / 64)];
   const int team = threadIdx.x / T;
   const int t = threadIdx.x % T;
@@ -330,11 +349,19 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   const RowProg pg = uniform_load(a.progs + prog);
   const cpx<real> *tw = a.tw + tw_slot(E) * N;  // this shape's pass-ordered table
   if constexpr (TWL) {
-    stage_twiddles<S::BS, N - E>(twl, tw);
+    stage_twiddles_async<S::BS, N - E>(twl, tw);
     tw = twl;
   }
   // No barrier here: every transform form opens with one before its first
-  // twiddle read, which publishes the staged table.
+  // twiddle read, which publishes the staged table once each wave has
+  // waited for its share (settle_tw, before the first transform).
+  bool tw_pending = TWL;
+  auto settle_tw = [&]() {
+    if (tw_pending) {
+      twiddles_landed();
+      tw_pending = false;
+    }
+  };
 
   // Register sets: u = z[].x, v = z[].y (the FFT buffer), then A, o0, o1, o2.
   cpx<real> z[E];
@@ -427,6 +454,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
             }
             xa[it][r] = {za.x * sa - zbr.y * sb, za.y * sa + zbr.x * sb};
           }
+        settle_tw();
         fft_in<real, N, E, NB, +1, XP>(xa, z, b0, b1, tw, t);
         const real ia = (real)pa.y, ib = (real)pb.y;
 #pragma unroll
@@ -522,6 +550,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         const real sx = (real)px.x, sy = (real)py.x;
 #pragma unroll
         for (int e = 0; e < E; ++e) z[e] = {z[e].x * sx, z[e].y * sy};
+        settle_tw();
         const cpx<real> *res = team_fft<real, N, E, NB, -1>(z, b0, b1, tw, t);
         cpx<real> *Fa = a.mix + (long long)op.fa * a.mix_stride;
         cpx<real> *Fb = a.mix + (long long)(op.fb >= 0 ? op.fb : 0) * a.mix_stride;
@@ -551,6 +580,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         break;
     }
   }
+  settle_tw();  // no load into LDS may outlive the block
 }
 
 // ---------------------------------------------------------------------------
@@ -632,7 +662,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   constexpr int NB = FT == 1 ? S::template nbuf<real>() : 2;
   constexpr bool TWL = FT == 1 ? S::template tw_in_lds<real>() : true;
   __shared__ cpx<real> smem[(FT == 1 ? CB::TPB : FT) * NB * L];
-  __shared__ cpx<real> twl[TWL ? N : 1];
+  __shared__ __attribute__((aligned(16))) cpx<real> twl[TWL ? N : 1];
   __shared__ float red[2 * (CB::BS / 64)];
   __shared__ cpx<double> xs[FT == 1 ? 1 : FT * QB * T];  // fold teams: each team's part of X
   // fold teams are whole wavefronts: the team index is wave-uniform (scalar)
@@ -648,10 +678,18 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   const int ny = a.ny;
   const cpx<real> *tw = a.tw + tw_slot(E) * N;  // this shape's pass-ordered table
   if constexpr (TWL) {
-    stage_twiddles<CB::BS, N - E>(twl, tw);
+    stage_twiddles_async<CB::BS, N - E>(twl, tw);
     tw = twl;
   }
-  // (no barrier: the first transform's opening barrier publishes the table)
+  // (no barrier: the first transform's opening barrier publishes the table,
+  // once each wave has waited for its share in settle_tw)
+  bool tw_pending = TWL;
+  auto settle_tw = [&]() {
+    if (tw_pending) {
+      twiddles_landed();
+      tw_pending = false;
+    }
+  };
 
   auto my_of = [&](int q) {
     const int b = t + T * q;
@@ -707,6 +745,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   // transform x (HBM-side layout) and fold it: XP from registers, else
   // read from LDS as it is needed
   auto transform_fold = [&](HbmRegs<real, N, E, XP> &x, uint32_t fsym, double fcoef, bool use) {
+    settle_tw();
     if constexpr (XP) {
       cpx<real> v[E];
       team_fft_t<real, N, E, NB, -1>(x, v, b0, b1, tw, t);
@@ -865,6 +904,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
         m = fmaxf(m, fmaxf(fabsf((float)w.x), fabsf((float)w.y)));
       };
       // fold teams: every team transformed the same combination, team 0 writes
+      settle_tw();
       if constexpr (KEEP) {
         cpx<real> o[HO::IT][HO::R];
         team_fft_keep<real, N, E, NB, +1>(z, b0, b1, tw, t, o);
@@ -884,6 +924,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
       if (t == 0 && writer) gstore1(a.colmax, (long long)out.dst_mixed * (a.nx / 2) + col, m);
     }
   }
+  settle_tw();  // no load into LDS may outlive the block
 }
 
 // Caller fields of a single-grid call; they replace the argument record's
