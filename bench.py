@@ -59,8 +59,9 @@ def cpu_baseline(w, eta, psi, nsteps):
 
 
 def kernel_source_hash():
-    """Hash of the HIP kernel sources and the planner that schedules them: a
-    counter record applies to the sources it was taken on."""
+    """Hash of the HIP kernel sources, the planner that schedules them and the
+    build script that holds the compiler flags: a counter record applies to
+    the build it was taken on."""
     import hashlib
 
     h = hashlib.sha256()
@@ -69,6 +70,8 @@ def kernel_source_hash():
         if f.endswith((".hip", ".hpp")) or f == "zk_plan.cpp":
             with open(os.path.join(csrc, f), "rb") as fh:
                 h.update(f.encode() + fh.read())
+    with open(os.path.join(HERE, "paper_2608_25203_amd", "build.py"), "rb") as fh:
+        h.update(b"build.py" + fh.read())
     return h.hexdigest()[:16]
 
 
