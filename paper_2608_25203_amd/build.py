@@ -9,7 +9,7 @@ _build/, then linked into paper_2608_25203_amd/libzk.so.  Flags:
                                         cases of the row program interpreter
                                         apart, so register arrays stay in
                                         registers instead of private memory
-  -mllvm -amdgpu-kernarg-preload-count=3
+  -mllvm -amdgpu-kernarg-preload-count=4
                                         the first kernel arguments arrive in
                                         SGPRs (no dependent kernarg load)
 """
@@ -33,9 +33,10 @@ CXX_UNITS = ["zk_plan.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 HIP_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-mllvm", "-simplifycfg-sink-common=false",
-             # the first kernel arguments (the record and item pointers) arrive
-             # preloaded in SGPRs: one dependent scalar load fewer per block
-             "-mllvm", "-amdgpu-kernarg-preload-count=3"]
+             # the first kernel arguments (the record and item pointers, a
+             # single grid's record index and first item) arrive preloaded in
+             # SGPRs: no dependent scalar load before a block's first work
+             "-mllvm", "-amdgpu-kernarg-preload-count=4"]
 
 
 def _run(cmd):

@@ -938,11 +938,17 @@ struct PhysArgs {
 // The row and column kernels: blockIdx.y selects an item (argument record
 // and program or task); every item of one launch shares the team shape
 // (T, E), so blockIdx.x spans the same rows or columns for each.  A single
-// grid is the batch of one tile.
+// grid is the batch of one tile; it passes no item table (items = null) but
+// its record index and first program or task (tile0, first0), which arrive
+// preloaded in registers, so a block's first loads do not wait on an item.
+__device__ __forceinline__ BatchItem item_of(const BatchItem *items, int tile0, int first0) {
+  return items ? items[blockIdx.y] : BatchItem{tile0, first0 + (int)blockIdx.y};
+}
 template <typename real, int T, int E>
 __global__ __launch_bounds__(T > 256 ? T : 256) void row_kernel_batch(const RowArgs<real> *__restrict__ args,
-                                                        const BatchItem *__restrict__ items, PhysArgs ph) {
-  const BatchItem it = items[blockIdx.y];
+                                                        const BatchItem *__restrict__ items, int tile0, int first0,
+                                                        PhysArgs ph) {
+  const BatchItem it = item_of(items, tile0, first0);
   RowArgs<real> a = args[it.tile];
   if (ph.use) {
     a.pin0 = ph.in0;
@@ -957,8 +963,9 @@ __global__ __launch_bounds__(T > 256 ? T : 256) void row_kernel_batch(const RowA
 // lift's column launches); the plain passes never carry its exponentials.
 template <typename real, int T, int E, bool LIFTSYM = false>
 __global__ __launch_bounds__(T > 256 ? T : 256) void col_kernel_batch(const ColArgs<real> *__restrict__ args,
-                                                        const BatchItem *__restrict__ items, PhysArgs) {
-  const BatchItem it = items[blockIdx.y];
+                                                        const BatchItem *__restrict__ items, int tile0, int first0,
+                                                        PhysArgs) {
+  const BatchItem it = item_of(items, tile0, first0);
   const ColArgs<real> a = args[it.tile];
   col_body<real, T, E, LIFTSYM>(a, it.index, blockIdx.x);
 }
@@ -966,8 +973,9 @@ __global__ __launch_bounds__(T > 256 ? T : 256) void col_kernel_batch(const ColA
 // (tasks whose folds and terms run side by side).
 template <typename real, int T, int E>
 __global__ __launch_bounds__(kMaxFolds * T) void col_kernel_folds(const ColArgs<real> *__restrict__ args,
-                                                             const BatchItem *__restrict__ items, PhysArgs) {
-  const BatchItem it = items[blockIdx.y];
+                                                             const BatchItem *__restrict__ items, int tile0,
+                                                             int first0, PhysArgs) {
+  const BatchItem it = item_of(items, tile0, first0);
   const ColArgs<real> a = args[it.tile];
   col_body<real, T, E, false, kMaxFolds>(a, it.index, blockIdx.x);
 }
@@ -994,27 +1002,27 @@ const void *batch_col_kernel<float>(int T, int E);
 // Launch the kernel of shape (T, E) (hipErrorInvalidValue if not built).
 template <typename real>
 hipError_t launch_batch_row(int T, int E, dim3 grid, hipStream_t s, const RowArgs<real> *args, const BatchItem *items,
-                            PhysArgs ph);
+                            int tile0, int first0, PhysArgs ph);
 template <typename real>
 hipError_t launch_batch_col(int T, int E, dim3 grid, hipStream_t s, const ColArgs<real> *args, const BatchItem *items,
-                            PhysArgs ph);
+                            int tile0, int first0, PhysArgs ph);
 template <>
-hipError_t launch_batch_row<double>(int, int, dim3, hipStream_t, const RowArgs<double> *, const BatchItem *, PhysArgs);
+hipError_t launch_batch_row<double>(int, int, dim3, hipStream_t, const RowArgs<double> *, const BatchItem *, int, int, PhysArgs);
 template <>
-hipError_t launch_batch_row<float>(int, int, dim3, hipStream_t, const RowArgs<float> *, const BatchItem *, PhysArgs);
+hipError_t launch_batch_row<float>(int, int, dim3, hipStream_t, const RowArgs<float> *, const BatchItem *, int, int, PhysArgs);
 template <>
-hipError_t launch_batch_col<double>(int, int, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *, PhysArgs);
+hipError_t launch_batch_col<double>(int, int, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *, int, int, PhysArgs);
 template <>
-hipError_t launch_batch_col<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *, PhysArgs);
+hipError_t launch_batch_col<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *, int, int, PhysArgs);
 // The lift_sym variant of the base-length column kernel (E in {2, 4, 8}).
 template <typename real>
 hipError_t launch_batch_col_lift(int T, int E, dim3 grid, hipStream_t s, const ColArgs<real> *args,
-                                 const BatchItem *items, PhysArgs ph);
+                                 const BatchItem *items, int tile0, int first0, PhysArgs ph);
 template <>
-hipError_t launch_batch_col_lift<double>(int, int, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *,
+hipError_t launch_batch_col_lift<double>(int, int, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *, int, int,
                                          PhysArgs);
 template <>
-hipError_t launch_batch_col_lift<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *,
+hipError_t launch_batch_col_lift<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *, int, int,
                                         PhysArgs);
 
 // Fold-team column kernel (T in {64, 128, 256}, E in {2, 3}); grid.x = one
@@ -1024,12 +1032,12 @@ __host__ __device__ constexpr bool fold_team_shape(int T, int E) {
 }
 template <typename real>
 hipError_t launch_batch_col_folds(int T, int E, dim3 grid, hipStream_t s, const ColArgs<real> *args,
-                                  const BatchItem *items, PhysArgs ph);
+                                  const BatchItem *items, int tile0, int first0, PhysArgs ph);
 template <>
-hipError_t launch_batch_col_folds<double>(int, int, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *,
+hipError_t launch_batch_col_folds<double>(int, int, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *, int, int,
                                           PhysArgs);
 template <>
-hipError_t launch_batch_col_folds<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *,
+hipError_t launch_batch_col_folds<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *, int, int,
                                          PhysArgs);
 
 // Reflecting walls (zk_bc.hip): dst [2ny][2nx] = even extension of src
