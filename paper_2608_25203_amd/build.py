@@ -9,7 +9,7 @@ _build/, then linked into paper_2608_25203_amd/libzk.so.  Flags:
                                         cases of the row program interpreter
                                         apart, so register arrays stay in
                                         registers instead of private memory
-  -mllvm -amdgpu-kernarg-preload-count=4
+  -mllvm -amdgpu-kernarg-preload-count=5
                                         the first kernel arguments arrive in
                                         SGPRs (no dependent kernarg load)
 """
@@ -34,9 +34,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I
 HIP_FLAGS = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-mllvm", "-simplifycfg-sink-common=false",
              # the first kernel arguments (the record and item pointers, a
-             # single grid's record index and first item) arrive preloaded in
-             # SGPRs: no dependent scalar load before a block's first work
-             "-mllvm", "-amdgpu-kernarg-preload-count=4"]
+             # single grid's record index, first item and schedule table)
+             # arrive preloaded in SGPRs: no dependent scalar load before a
+             # block's first work
+             "-mllvm", "-amdgpu-kernarg-preload-count=5"]
 
 
 def _run(cmd):

@@ -25,32 +25,32 @@ for kind in ("row", "col"):
         lines += ["  return nullptr;", "}", "",
                   "template <>",
                   f"hipError_t launch_batch_{kind}<{real}>(int T, int E, dim3 grid, hipStream_t s, const {'RowArgs' if kind == 'row' else 'ColArgs'}<{real}> *args,",
-                  "                                   const BatchItem *items, int tile0, int first0, PhysArgs ph) {"]
+                  "                                   const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {"]
         for T, E in SHAPES:
             lines.append(f"  if (T == {T} && E == {E}) {{")
-            lines.append(f"    hipLaunchKernelGGL(({kind}_kernel_batch<{real}, {T}, {E}>), grid, dim3({bs(T)}), 0, s, args, items, tile0, first0, ph);")
+            lines.append(f"    hipLaunchKernelGGL(({kind}_kernel_batch<{real}, {T}, {E}>), grid, dim3({bs(T)}), 0, s, args, items, tile0, first0, sched0, ph);")
             lines.append("    return hipGetLastError();")
             lines.append("  }")
         lines += ["  return hipErrorInvalidValue;", "}", ""]
         if kind == "col":  # the lift_sym variant, base-length shapes only
             lines += ["template <>",
                       f"hipError_t launch_batch_col_lift<{real}>(int T, int E, dim3 grid, hipStream_t s, const ColArgs<{real}> *args,",
-                      "                                        const BatchItem *items, int tile0, int first0, PhysArgs ph) {"]
+                      "                                        const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {"]
             for T, E in SHAPES:
                 if E % 3 == 0:
                     continue
                 lines.append(f"  if (T == {T} && E == {E}) {{")
-                lines.append(f"    hipLaunchKernelGGL((col_kernel_batch<{real}, {T}, {E}, true>), grid, dim3({bs(T)}), 0, s, args, items, tile0, first0, ph);")
+                lines.append(f"    hipLaunchKernelGGL((col_kernel_batch<{real}, {T}, {E}, true>), grid, dim3({bs(T)}), 0, s, args, items, tile0, first0, sched0, ph);")
                 lines.append("    return hipGetLastError();")
                 lines.append("  }")
             lines += ["  return hipErrorInvalidValue;", "}", ""]
             # fold teams: kMaxFolds teams of T threads, one column per block
             lines += ["template <>",
                       f"hipError_t launch_batch_col_folds<{real}>(int T, int E, dim3 grid, hipStream_t s, const ColArgs<{real}> *args,",
-                      "                                         const BatchItem *items, int tile0, int first0, PhysArgs ph) {"]
+                      "                                         const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {"]
             for T, E in FOLD_SHAPES:
                 lines.append(f"  if (T == {T} && E == {E}) {{")
-                lines.append(f"    hipLaunchKernelGGL((col_kernel_folds<{real}, {T}, {E}>), grid, dim3(kMaxFolds * {T}), 0, s, args, items, tile0, first0, ph);")
+                lines.append(f"    hipLaunchKernelGGL((col_kernel_folds<{real}, {T}, {E}>), grid, dim3(kMaxFolds * {T}), 0, s, args, items, tile0, first0, sched0, ph);")
                 lines.append("    return hipGetLastError();")
                 lines.append("  }")
             lines += ["  return hipErrorInvalidValue;", "}", ""]

@@ -326,22 +326,25 @@ int run_seq_t(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
       const bool pad = l.kind == L_ROW_PAD || l.kind == L_COL_PAD;
       const TeamShape sh = ctx_team(c, row, pad);
       // a single grid passes no item table: block row y runs program or task
-      // l.first + y of argument record 0 (padded passes) or 1 (base passes)
+      // l.first + y of argument record 0 (padded passes) or 1 (base passes),
+      // from the program or task table passed with the launch
       const BatchItem *items = nullptr;
       const int tile0 = pad ? 0 : 1, first0 = l.first;
+      const void *sched0 = ws + (row ? c->off_progs : c->off_tasks);
       const PhysArgs pa{ph.in0, ph.in1, ph.in2, ph.out0, ph.out1, 1};
       const dim3 grid(sh.blocks, l.count);
       const ColArgs<real> *cargs = reinterpret_cast<const ColArgs<real> *>(ws + c->off_cargs);
       if (row)
         e = launch_batch_row<real>(sh.T, sh.E, grid, c->stream,
-                                   reinterpret_cast<const RowArgs<real> *>(ws + c->off_rargs), items, tile0, first0, pa);
+                                   reinterpret_cast<const RowArgs<real> *>(ws + c->off_rargs), items, tile0, first0,
+                                   sched0, pa);
       else if (l.c2 == 1)
-        e = launch_batch_col_lift<real>(sh.T, sh.E, grid, c->stream, cargs, items, tile0, first0, pa);
+        e = launch_batch_col_lift<real>(sh.T, sh.E, grid, c->stream, cargs, items, tile0, first0, sched0, pa);
       else if (l.d2 == kMaxFolds && fold_team_shape(sh.T, sh.E))  // one block per column
         e = launch_batch_col_folds<real>(sh.T, sh.E, dim3(nx / 2, l.count), c->stream, cargs, items, tile0, first0,
-                                         pa);
+                                         sched0, pa);
       else
-        e = launch_batch_col<real>(sh.T, sh.E, grid, c->stream, cargs, items, tile0, first0, pa);
+        e = launch_batch_col<real>(sh.T, sh.E, grid, c->stream, cargs, items, tile0, first0, sched0, pa);
     } else {
       double *red = reinterpret_cast<double *>(ws + c->off_red);
       e = launch_parseval(base + (long long)l.first * c->base_stride, base + (long long)l.count * c->base_stride,

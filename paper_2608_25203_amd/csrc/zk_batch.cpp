@@ -178,7 +178,8 @@ int launch(zk_batch *b, const BL &l) {
   if (!fn) return fail(b, ZK_EINVAL, "team shape not built");
   PhysArgs ph{};
   int tile0 = 0, first0 = 0;  // unused: batches pass their item table
-  void *params[] = {&args, &it, &tile0, &first0, &ph};
+  const void *sched0 = nullptr;  // and read each tile's schedule from its record
+  void *params[] = {&args, &it, &tile0, &first0, &sched0, &ph};
   HIP_TRY(b, hipLaunchKernel(fn, dim3(l.blocks, l.nitems), dim3(std::max(256, l.T)), params, 0, b->stream));
   return ZK_OK;
 }
@@ -205,7 +206,8 @@ int build_graph(zk_batch *b, int s) {
       }
       PhysArgs ph{};
       int tile0 = 0, first0 = 0;  // unused: batches pass their item table
-      void *params[] = {&args, &it, &tile0, &first0, &ph};
+      const void *sched0 = nullptr;  // and read each tile's schedule from its record
+      void *params[] = {&args, &it, &tile0, &first0, &sched0, &ph};
       hipKernelNodeParams p{};
       p.func = const_cast<void *>(fn);
       p.gridDim = dim3(l.blocks, l.nitems);

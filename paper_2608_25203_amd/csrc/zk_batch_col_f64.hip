@@ -41,125 +41,125 @@ const void *batch_col_kernel<double>(int T, int E) {
 
 template <>
 hipError_t launch_batch_col<double>(int T, int E, dim3 grid, hipStream_t s, const ColArgs<double> *args,
-                                   const BatchItem *items, int tile0, int first0, PhysArgs ph) {
+                                   const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {
   if (T == 32 && E == 2) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 32, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 32, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 32 && E == 3) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 32, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 32, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 32 && E == 4) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 32, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 32, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 32 && E == 6) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 32, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 32, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 32 && E == 8) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 32, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 32, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 32 && E == 12) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 32, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 32, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 2) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 64, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 64, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 3) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 64, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 64, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 4) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 64, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 64, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 6) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 64, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 64, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 8) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 64, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 64, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 12) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 64, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 64, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 2) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 128, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 128, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 3) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 128, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 128, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 4) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 128, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 128, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 6) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 128, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 128, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 8) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 128, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 128, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 12) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 128, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 128, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 2) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 256, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 256, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 3) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 256, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 256, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 4) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 256, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 256, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 6) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 256, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 256, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 8) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 256, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 256, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 12) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 256, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 256, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 512 && E == 2) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 512, 2>), grid, dim3(512), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 512, 2>), grid, dim3(512), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 512 && E == 3) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 512, 3>), grid, dim3(512), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 512, 3>), grid, dim3(512), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 512 && E == 4) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 512, 4>), grid, dim3(512), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 512, 4>), grid, dim3(512), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 512 && E == 6) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 512, 6>), grid, dim3(512), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 512, 6>), grid, dim3(512), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 1024 && E == 2) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 1024, 2>), grid, dim3(1024), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 1024, 2>), grid, dim3(1024), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 1024 && E == 3) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 1024, 3>), grid, dim3(1024), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 1024, 3>), grid, dim3(1024), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
@@ -167,65 +167,65 @@ hipError_t launch_batch_col<double>(int T, int E, dim3 grid, hipStream_t s, cons
 
 template <>
 hipError_t launch_batch_col_lift<double>(int T, int E, dim3 grid, hipStream_t s, const ColArgs<double> *args,
-                                        const BatchItem *items, int tile0, int first0, PhysArgs ph) {
+                                        const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {
   if (T == 32 && E == 2) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 32, 2, true>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 32, 2, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 32 && E == 4) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 32, 4, true>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 32, 4, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 32 && E == 8) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 32, 8, true>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 32, 8, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 2) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 64, 2, true>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 64, 2, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 4) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 64, 4, true>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 64, 4, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 8) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 64, 8, true>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 64, 8, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 2) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 128, 2, true>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 128, 2, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 4) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 128, 4, true>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 128, 4, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 8) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 128, 8, true>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 128, 8, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 2) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 256, 2, true>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 256, 2, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 4) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 256, 4, true>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 256, 4, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 8) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 256, 8, true>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 256, 8, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 512 && E == 2) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 512, 2, true>), grid, dim3(512), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 512, 2, true>), grid, dim3(512), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 512 && E == 4) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 512, 4, true>), grid, dim3(512), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 512, 4, true>), grid, dim3(512), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 1024 && E == 2) {
-    hipLaunchKernelGGL((col_kernel_batch<double, 1024, 2, true>), grid, dim3(1024), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_batch<double, 1024, 2, true>), grid, dim3(1024), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;
@@ -233,29 +233,29 @@ hipError_t launch_batch_col_lift<double>(int T, int E, dim3 grid, hipStream_t s,
 
 template <>
 hipError_t launch_batch_col_folds<double>(int T, int E, dim3 grid, hipStream_t s, const ColArgs<double> *args,
-                                         const BatchItem *items, int tile0, int first0, PhysArgs ph) {
+                                         const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {
   if (T == 64 && E == 2) {
-    hipLaunchKernelGGL((col_kernel_folds<double, 64, 2>), grid, dim3(kMaxFolds * 64), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_folds<double, 64, 2>), grid, dim3(kMaxFolds * 64), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 3) {
-    hipLaunchKernelGGL((col_kernel_folds<double, 64, 3>), grid, dim3(kMaxFolds * 64), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_folds<double, 64, 3>), grid, dim3(kMaxFolds * 64), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 2) {
-    hipLaunchKernelGGL((col_kernel_folds<double, 128, 2>), grid, dim3(kMaxFolds * 128), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_folds<double, 128, 2>), grid, dim3(kMaxFolds * 128), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 3) {
-    hipLaunchKernelGGL((col_kernel_folds<double, 128, 3>), grid, dim3(kMaxFolds * 128), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_folds<double, 128, 3>), grid, dim3(kMaxFolds * 128), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 2) {
-    hipLaunchKernelGGL((col_kernel_folds<double, 256, 2>), grid, dim3(kMaxFolds * 256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_folds<double, 256, 2>), grid, dim3(kMaxFolds * 256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 3) {
-    hipLaunchKernelGGL((col_kernel_folds<double, 256, 3>), grid, dim3(kMaxFolds * 256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((col_kernel_folds<double, 256, 3>), grid, dim3(kMaxFolds * 256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;

@@ -41,125 +41,125 @@ const void *batch_row_kernel<double>(int T, int E) {
 
 template <>
 hipError_t launch_batch_row<double>(int T, int E, dim3 grid, hipStream_t s, const RowArgs<double> *args,
-                                   const BatchItem *items, int tile0, int first0, PhysArgs ph) {
+                                   const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {
   if (T == 32 && E == 2) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 32, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 32, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 32 && E == 3) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 32, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 32, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 32 && E == 4) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 32, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 32, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 32 && E == 6) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 32, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 32, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 32 && E == 8) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 32, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 32, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 32 && E == 12) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 32, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 32, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 2) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 64, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 64, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 3) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 64, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 64, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 4) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 64, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 64, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 6) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 64, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 64, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 8) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 64, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 64, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 12) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 64, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 64, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 2) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 128, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 128, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 3) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 128, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 128, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 4) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 128, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 128, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 6) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 128, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 128, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 8) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 128, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 128, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 12) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 128, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 128, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 2) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 256, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 256, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 3) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 256, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 256, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 4) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 256, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 256, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 6) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 256, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 256, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 8) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 256, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 256, 8>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 12) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 256, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 256, 12>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 512 && E == 2) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 512, 2>), grid, dim3(512), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 512, 2>), grid, dim3(512), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 512 && E == 3) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 512, 3>), grid, dim3(512), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 512, 3>), grid, dim3(512), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 512 && E == 4) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 512, 4>), grid, dim3(512), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 512, 4>), grid, dim3(512), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 512 && E == 6) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 512, 6>), grid, dim3(512), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 512, 6>), grid, dim3(512), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 1024 && E == 2) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 1024, 2>), grid, dim3(1024), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 1024, 2>), grid, dim3(1024), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 1024 && E == 3) {
-    hipLaunchKernelGGL((row_kernel_batch<double, 1024, 3>), grid, dim3(1024), 0, s, args, items, tile0, first0, ph);
+    hipLaunchKernelGGL((row_kernel_batch<double, 1024, 3>), grid, dim3(1024), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;

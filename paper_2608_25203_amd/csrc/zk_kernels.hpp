@@ -333,10 +333,20 @@ struct BatchItem {
 // Row pass body: TPB teams per block, one row each (block blk of the
 // pass), all running program progs[prog].
 template <typename real, int T, int E>
-__device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int blk) {
+__device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int blk, const RowProg *progs0) {
   using S = Shape<T, E>;
   constexpr int N = S::N, L = S::L, NB = S::template nbuf<real>();
   constexpr bool TWL = S::template tw_in_lds<real>();
+  // A single grid passes its program table as a kernel argument, so the
+  // program record loads alongside the argument record, not after it (the
+  // empty asm keeps that path a branch of its own).
+  RowProg pg;
+  if (progs0) {
+    asm volatile("");
+    pg = uniform_load(progs0 + prog);
+  } else {
+    pg = uniform_load(a.progs + prog);
+  }
   __shared__ cpx<real> smem[S::TPB * NB * L];
   __shared__ __attribute__((aligned(16))) cpx<real> twl[TWL ? N : 1];
   __shared__ float red[2 * (S::BS / 64)];
@@ -346,7 +356,6 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   const int row = (S::TPB == 1 ? xcd_unit(blk, a.rows, 2) : blk) * S::TPB + team;
   cpx<real> *b0 = smem + team * NB * L;
   cpx<real> *b1 = b0 + (NB - 1) * L;
-  const RowProg pg = uniform_load(a.progs + prog);
   const cpx<real> *tw = a.tw + tw_slot(E) * N;  // this shape's pass-ordered table
   if constexpr (TWL) {
     stage_twiddles_async<S::BS, N - E>(twl, tw);
@@ -654,13 +663,21 @@ struct ColBlock {
   static constexpr int TPB = FT == 1 ? BS / T : 1;                    // columns per block
 };
 template <typename real, int T, int E, bool LIFTSYM = false, int FT = 1>
-__device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index, int blk) {
+__device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index, int blk, const ColTask *tasks0) {
   using S = Shape<T, E>;
   using CB = ColBlock<T, FT>;
   static_assert(FT == 1 || (T >= 64 && FT * T <= 1024), "fold teams: whole wavefronts, one block");
   constexpr int N = S::N, L = S::L, QB = S::QB;
   constexpr int NB = FT == 1 ? S::template nbuf<real>() : 2;
   constexpr bool TWL = FT == 1 ? S::template tw_in_lds<real>() : true;
+  // (a single grid passes its task table too: see row_body)
+  ColTask task;
+  if (tasks0) {
+    asm volatile("");
+    task = uniform_load(tasks0 + task_index);
+  } else {
+    task = uniform_load(a.tasks + task_index);
+  }
   __shared__ cpx<real> smem[(FT == 1 ? CB::TPB : FT) * NB * L];
   __shared__ __attribute__((aligned(16))) cpx<real> twl[TWL ? N : 1];
   __shared__ float red[2 * (CB::BS / 64)];
@@ -674,7 +691,6 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
                           : xcd_unit(blk, a.nx / 2, CBMAX);
   cpx<real> *b0 = smem + team * NB * L;
   cpx<real> *b1 = b0 + (NB - 1) * L;
-  const ColTask task = uniform_load(a.tasks + task_index);
   const int ny = a.ny;
   const cpx<real> *tw = a.tw + tw_slot(E) * N;  // this shape's pass-ordered table
   if constexpr (TWL) {
@@ -939,15 +955,16 @@ struct PhysArgs {
 // and program or task); every item of one launch shares the team shape
 // (T, E), so blockIdx.x spans the same rows or columns for each.  A single
 // grid is the batch of one tile; it passes no item table (items = null) but
-// its record index and first program or task (tile0, first0), which arrive
-// preloaded in registers, so a block's first loads do not wait on an item.
+// its record index and first program or task (tile0, first0) and its program
+// or task table (sched0), which arrive preloaded in registers, so a block's
+// first loads wait neither on an item nor on the argument record.
 __device__ __forceinline__ BatchItem item_of(const BatchItem *items, int tile0, int first0) {
   return items ? items[blockIdx.y] : BatchItem{tile0, first0 + (int)blockIdx.y};
 }
 template <typename real, int T, int E>
 __global__ __launch_bounds__(T > 256 ? T : 256) void row_kernel_batch(const RowArgs<real> *__restrict__ args,
                                                         const BatchItem *__restrict__ items, int tile0, int first0,
-                                                        PhysArgs ph) {
+                                                        const void *sched0, PhysArgs ph) {
   const BatchItem it = item_of(items, tile0, first0);
   RowArgs<real> a = args[it.tile];
   if (ph.use) {
@@ -957,27 +974,27 @@ __global__ __launch_bounds__(T > 256 ? T : 256) void row_kernel_batch(const RowA
     a.pout0 = ph.out0;
     a.pout1 = ph.out1;
   }
-  row_body<real, T, E>(a, it.index, blockIdx.x);
+  row_body<real, T, E>(a, it.index, blockIdx.x, static_cast<const RowProg *>(sched0));
 }
 // LIFTSYM: the variant that applies ColOut.lift_sym (the bulk velocity
 // lift's column launches); the plain passes never carry its exponentials.
 template <typename real, int T, int E, bool LIFTSYM = false>
 __global__ __launch_bounds__(T > 256 ? T : 256) void col_kernel_batch(const ColArgs<real> *__restrict__ args,
                                                         const BatchItem *__restrict__ items, int tile0, int first0,
-                                                        PhysArgs) {
+                                                        const void *sched0, PhysArgs) {
   const BatchItem it = item_of(items, tile0, first0);
   const ColArgs<real> a = args[it.tile];
-  col_body<real, T, E, LIFTSYM>(a, it.index, blockIdx.x);
+  col_body<real, T, E, LIFTSYM>(a, it.index, blockIdx.x, static_cast<const ColTask *>(sched0));
 }
 // Fold teams: kMaxFolds teams of T threads per block, one column per block
 // (tasks whose folds and terms run side by side).
 template <typename real, int T, int E>
 __global__ __launch_bounds__(kMaxFolds * T) void col_kernel_folds(const ColArgs<real> *__restrict__ args,
                                                              const BatchItem *__restrict__ items, int tile0,
-                                                             int first0, PhysArgs) {
+                                                             int first0, const void *sched0, PhysArgs) {
   const BatchItem it = item_of(items, tile0, first0);
   const ColArgs<real> a = args[it.tile];
-  col_body<real, T, E, false, kMaxFolds>(a, it.index, blockIdx.x);
+  col_body<real, T, E, false, kMaxFolds>(a, it.index, blockIdx.x, static_cast<const ColTask *>(sched0));
 }
 
 // Team shapes (T, E) compiled for the batched kernels: T in {32, 64, 128,
@@ -1002,28 +1019,32 @@ const void *batch_col_kernel<float>(int T, int E);
 // Launch the kernel of shape (T, E) (hipErrorInvalidValue if not built).
 template <typename real>
 hipError_t launch_batch_row(int T, int E, dim3 grid, hipStream_t s, const RowArgs<real> *args, const BatchItem *items,
-                            int tile0, int first0, PhysArgs ph);
+                            int tile0, int first0, const void *sched0, PhysArgs ph);
 template <typename real>
 hipError_t launch_batch_col(int T, int E, dim3 grid, hipStream_t s, const ColArgs<real> *args, const BatchItem *items,
-                            int tile0, int first0, PhysArgs ph);
+                            int tile0, int first0, const void *sched0, PhysArgs ph);
 template <>
-hipError_t launch_batch_row<double>(int, int, dim3, hipStream_t, const RowArgs<double> *, const BatchItem *, int, int, PhysArgs);
+hipError_t launch_batch_row<double>(int, int, dim3, hipStream_t, const RowArgs<double> *, const BatchItem *, int, int,
+                                   const void *, PhysArgs);
 template <>
-hipError_t launch_batch_row<float>(int, int, dim3, hipStream_t, const RowArgs<float> *, const BatchItem *, int, int, PhysArgs);
+hipError_t launch_batch_row<float>(int, int, dim3, hipStream_t, const RowArgs<float> *, const BatchItem *, int, int,
+                                  const void *, PhysArgs);
 template <>
-hipError_t launch_batch_col<double>(int, int, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *, int, int, PhysArgs);
+hipError_t launch_batch_col<double>(int, int, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *, int, int,
+                                   const void *, PhysArgs);
 template <>
-hipError_t launch_batch_col<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *, int, int, PhysArgs);
+hipError_t launch_batch_col<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *, int, int,
+                                  const void *, PhysArgs);
 // The lift_sym variant of the base-length column kernel (E in {2, 4, 8}).
 template <typename real>
 hipError_t launch_batch_col_lift(int T, int E, dim3 grid, hipStream_t s, const ColArgs<real> *args,
-                                 const BatchItem *items, int tile0, int first0, PhysArgs ph);
+                                 const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph);
 template <>
 hipError_t launch_batch_col_lift<double>(int, int, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *, int, int,
-                                         PhysArgs);
+                                        const void *, PhysArgs);
 template <>
 hipError_t launch_batch_col_lift<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *, int, int,
-                                        PhysArgs);
+                                       const void *, PhysArgs);
 
 // Fold-team column kernel (T in {64, 128, 256}, E in {2, 3}); grid.x = one
 // block per column.  hipErrorInvalidValue for a shape without an instance.
@@ -1032,13 +1053,13 @@ __host__ __device__ constexpr bool fold_team_shape(int T, int E) {
 }
 template <typename real>
 hipError_t launch_batch_col_folds(int T, int E, dim3 grid, hipStream_t s, const ColArgs<real> *args,
-                                  const BatchItem *items, int tile0, int first0, PhysArgs ph);
+                                  const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph);
 template <>
 hipError_t launch_batch_col_folds<double>(int, int, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *, int, int,
-                                          PhysArgs);
+                                         const void *, PhysArgs);
 template <>
 hipError_t launch_batch_col_folds<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *, int, int,
-                                         PhysArgs);
+                                        const void *, PhysArgs);
 
 // Reflecting walls (zk_bc.hip): dst [2ny][2nx] = even extension of src
 // [ny][nx]; crop: dst [ny][nx] = the physical quarter of src [2ny][2nx].
