@@ -213,3 +213,20 @@ def test_batch_create_host_checks():
     b = L.zk_batch_create(2, good, 9.81, 64)
     assert L.zk_batch_step(b, 0.01, 1) == zk.ZK_ENOWS
     L.zk_batch_destroy(b)
+
+
+def test_generated_kernel_units_are_current(tmp_path):
+    """The committed kernel-instance units equal what gen_batch_units.py
+    writes now (a generator change must come with its units)."""
+    import shutil
+    import subprocess
+    import sys
+
+    csrc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2608_25203_amd", "csrc")
+    shutil.copy(os.path.join(csrc, "gen_batch_units.py"), tmp_path)
+    subprocess.run([sys.executable, str(tmp_path / "gen_batch_units.py")], check=True)
+    for kind in ("row", "col"):
+        for tag in ("f64", "f32"):
+            name = f"zk_batch_{kind}_{tag}.hip"
+            with open(os.path.join(csrc, name)) as a, open(tmp_path / name) as b:
+                assert a.read() == b.read(), name
