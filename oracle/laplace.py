@@ -50,8 +50,11 @@ def fourier_diff(n, L):
     return D1, D2
 
 
-def dno_direct(eta, psi, Lx, Ly, h, nz):
-    """G(eta) psi by the dense direct solve; eta, psi are [ny][nx] (ny may be 1)."""
+def _solve(eta, psi, Lx, Ly, h, nz):
+    """The harmonic extension u(x, s) on the collocation grid: returns u as
+    [nz + 1][ny][nx] (s descending from 1 at the surface to 0 at the bed), the
+    Chebyshev nodes s, the s-derivative of u at the surface, and the surface
+    slopes and potential gradient."""
     ny, nx = eta.shape
     Dx1, Dx2 = fourier_diff(nx, Lx)
     Dy1, Dy2 = fourier_diff(ny, Ly)
@@ -104,4 +107,44 @@ def dno_direct(eta, psi, Lx, Ly, h, nz):
 
     u = scipy.linalg.solve(A, rhs, overwrite_a=True, check_finite=False)
     us_top = (Ks[top, :] @ u).reshape(ny, nx)
+    return u.reshape(ns, ny, nx), s, us_top, (ex, ey, px, py, D)
+
+
+def dno_direct(eta, psi, Lx, Ly, h, nz):
+    """G(eta) psi by the dense direct solve; eta, psi are [ny][nx] (ny may be 1)."""
+    _, _, us_top, (ex, ey, px, py, D) = _solve(eta, psi, Lx, Ly, h, nz)
     return (1.0 + ex ** 2 + ey ** 2) * us_top / D - ex * px - ey * py
+
+
+def cheb_interp(s_nodes, f, s):
+    """Value at s of the polynomial through (s_nodes[j], f[j]) on the
+    Chebyshev-Gauss-Lobatto nodes of cheb() mapped to [0, 1] (barycentric
+    form, weights (-1)^j halved at both ends)."""
+    n = len(s_nodes) - 1
+    w = (-1.0) ** np.arange(n + 1)
+    w[0] *= 0.5
+    w[-1] *= 0.5
+    d = s - s_nodes
+    hit = np.flatnonzero(d == 0.0)
+    if hit.size:
+        return float(f[hit[0]])
+    q = w / d
+    return float(np.dot(q, f) / np.sum(q))
+
+
+def potential_at_depths(eta, psi, Lx, Ly, h, nz, depths):
+    """The exact potential Phi(x, z = -y) on horizontal planes y in `depths`
+    below the reference level z = 0 (each plane inside the fluid, -y < min eta),
+    by the dense direct solve and interpolation along each mapped column:
+    z = -y is s = (h - y) / (h + eta(x)).  Returns [len(depths)][ny][nx]."""
+    u, s, _, _ = _solve(eta, psi, Lx, Ly, h, nz)
+    ny, nx = eta.shape
+    out = np.empty((len(depths), ny, nx))
+    for i, y in enumerate(depths):
+        sy = (h - y) / (h + eta)
+        if np.any(sy <= 0.0) or np.any(sy >= 1.0):
+            raise ValueError("plane z = -y must lie strictly inside the fluid")
+        for iy in range(ny):
+            for ix in range(nx):
+                out[i, iy, ix] = cheb_interp(s, u[:, iy, ix], sy[iy, ix])
+    return out

@@ -586,3 +586,34 @@ def test_depth_velocity_deep_limit():
     a = HOSModel(Grid(n, n, L, L, None), 2).depth_velocity(eta, psi, [0.0, 0.1, 0.4])
     b = HOSModel(Grid(n, n, L, L, 200.0), 2).depth_velocity(eta, psi, [0.0, 0.1, 0.4])
     assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
+
+
+def test_depth_lift_first_order_potential_against_direct_solve():
+    """Pins the depth lift's surface potential Phi|0 = psi - eps P(eta, G0 psi)
+    (eq:phi1) without the series: the dense Laplace solve gives the exact
+    potential on the plane z = -y (inside the fluid), and below that plane
+    the exact velocities follow from it through the harmonic strip (x and y
+    derivatives, and |k| tanh(|k|(h - y)) for the upward one), times the
+    coupling taper.  The lift drops only the O(eta^2) terms of the Taylor
+    expansion of Phi about z = 0, so its error must fall ~4x per halving of
+    eta; a flipped sign, a misplaced operand, a wrong factor or a missing
+    eps (checked at eps = 1/2 against the surface eps * eta) leaves an O(eta)
+    error that falls only ~2x.  Products are exact here (modes |m| <= 1)
+    and the product taper is off."""
+    from oracle.laplace import potential_at_depths
+
+    n, L, h, y = 12, TWO_PI, 1.0, 0.3
+    fe, psi = random_band_fields(n, n, 23, 1, amplitude=1.0)
+    g = Grid(n, n, L, L, h)
+    kn = np.pi * n / L
+    Tc = np.exp(-(np.abs(g.kx) / (0.5 * kn)) ** 8 - (np.abs(g.ky) / (0.5 * kn)) ** 8)
+    for eps in (1.0, 0.5):
+        errs = []
+        for a in (0.02, 0.01):
+            V = HOSModel(g, 2, eps=eps, taper=False).depth_velocity(a * fe, psi, [y])[0]
+            F = g.spec(potential_at_depths(eps * a * fe, psi, L, L, h, 16, [y])[0])
+            exact = np.stack([g.phys(1j * g.kx * Tc * F), g.phys(g.kk * np.tanh(g.kk * (h - y)) * Tc * F),
+                              g.phys(1j * g.ky * Tc * F)])
+            errs.append(np.max(np.abs(V - exact)) / np.max(np.abs(exact)))
+        assert 3.6 < errs[0] / errs[1] < 4.4, (eps, errs)
+        assert errs[1] < 1e-4, (eps, errs)
