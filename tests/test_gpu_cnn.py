@@ -1,12 +1,14 @@
 """GPU parity of the closure network's kernels (through the C ABI) against
 the CPU reference oracle/cnn.py.
 
-Two references: the FP64 network with the same bf16 rounding points as the
-kernels (bf16=True: operands rounded, FP64 products), which must agree to
-FP32-accumulation level (a rare one-ulp bf16 flip aside), and the plain
-FP64 network, which bounds the total effect of bf16 storage.  Tolerances are
-max-norm relative per tensor: forward 2e-3 (bf16-emulated) / 3e-2 (FP64);
-gradients 2e-3 / 6e-2 per parameter tensor.
+Two references.  The independent one is the plain FP64 network: the bf16
+mode of the network (bf16 weights and activations, FP32 accumulation) must
+stay within 2e-2 relative of it, forward and per gradient tensor.  The
+second is the FP64 network with bf16 rounding at the points where the
+kernels store bf16 MFMA operands (bf16=True: operands rounded, FP64
+products); it is shaped to the kernels, so it only localises a failure and
+must agree to FP32-accumulation level (2e-3; a rare one-ulp bf16 flip
+aside).  Tolerances are max-norm relative per tensor.
 """
 import numpy as np
 import pytest
@@ -62,7 +64,7 @@ def test_forward_parity(torch, B, H, W):
     yq, _ = C.CNN(pref, bf16=True).forward(x)
     y64, _ = C.CNN(pref).forward(x)
     assert rel(y, yq[:, 0]) < 2e-3
-    assert rel(y, y64[:, 0]) < 3e-2
+    assert rel(y, y64[:, 0]) < 2e-2
 
 
 @pytest.mark.parametrize("B,H,W,halo", [(2, 12, 64, 4), (1, 16, 128, 4)])
@@ -90,7 +92,7 @@ def test_gradient_parity(torch, B, H, W, halo):
     for i, name in enumerate(names):
         print(f" {name}", flush=True)
         assert rel(gg[i], ref[True][1][i]) < 2e-3, name
-        assert rel(gg[i], ref[False][1][i]) < 6e-2, name
+        assert rel(gg[i], ref[False][1][i]) < 2e-2, name
 
 
 def test_adam_step_and_training(torch):
