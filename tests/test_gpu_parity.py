@@ -376,6 +376,23 @@ def test_paper_tank_workload_parity(torch, M):
     assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
 
 
+def test_paper_tank_deep_order2_eps_reading_parity(torch):
+    """The deep Order-2 tank at eps = 0.85, the largest eps (0.05 steps)
+    under which its 2000 frames stay finite (at eps = 1 the collapsing bump
+    forms a central jet that overflows at frame 66 in the oracle and on the
+    GPU alike): 150 IF-AB2 steps, through the collapse, against the oracle."""
+    from oracle.hos import ReflectingModel
+    from paper_2608_25203_amd.inputs import tank_bump
+
+    n, L = 128, 20.0
+    eta, psi = tank_bump(n, n, L, L, 2.0)
+    s = solver(torch, n, n, L, L, 20.0, 2, boundary="reflect", integrator="ifab2", eps=0.85)
+    e, p = dev(torch, eta), dev(torch, psi)
+    s.step(e, p, 0.01, 150)
+    e0, p0 = ReflectingModel(n, n, L, L, 20.0, 2, eps=0.85).step_ifab2(eta, psi, 0.01, 150)
+    assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
+
+
 @pytest.mark.parametrize("M,boundary", [(3, "periodic"), (5, "periodic"), (2, "reflect")])
 def test_inverse_dtn_parity(torch, M, boundary):
     """Inverse DNO map (eq:psi_inverse) against the oracle's iteration after
