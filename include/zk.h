@@ -182,6 +182,25 @@ int zk_rhs(zk_ctx *ctx, const double *eta, const double *psi, double *eta_t, dou
  * NaN or Inf (that check synchronises the stream). */
 int zk_step(zk_ctx *ctx, double *eta, double *psi, double dt, int nsteps);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): zk_step
+ * with the workspace taken from a fixed device array inside the library,
+ * ZK_STATIC_WS_BYTES (64 MiB) per GPU, held from its first use until the
+ * process ends, instead of a bound caller workspace.  ctx needs zk_create
+ * (and any zk_set_option) but no zk_bind; eta, psi, dt and nsteps are as in
+ * zk_step; stream is the HIP stream to run on (NULL: the null stream).
+ * Returns ZK_ENOWS, with the sizes in zk_last_error, when
+ * zk_workspace_bytes(ctx) exceeds ZK_STATIC_WS_BYTES (FP64: up to about
+ * 256 x 256 at M = 6).  Every call re-uploads the context's tables and
+ * schedules into the array (it keeps the last call's contents, which no
+ * kernel reads before writing), synchronising the stream for that upload;
+ * no call allocates device memory.  All calls on one GPU share the array:
+ * calls that overlap in time on one GPU (other threads, other streams) race.
+ * A context bound with zk_bind keeps that binding for its other calls.
+ * Kernel statistics (ZK_OPT_PROFILE) are not recorded inside this call. */
+#define ZK_STATIC_WS_BYTES (64u << 20)
+int zk_step_static(zk_ctx *ctx, double *eta, double *psi, double dt, int nsteps, void *stream);
+
 /* Hamiltonian H = 1/2 int psi G^[M](eta) psi dx + 1/2 g int eta^2 dx
  * (Sec. 3.1, eq:hamiltonian), reduced in FP64 in a fixed order by Parseval on
  * the half spectrum.  Synchronises the stream; writes the value to *H_host. */

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -869,3 +870,69 @@ int zk_set_team_shape(zk_ctx *c, int row, int pad, int T) {
 const char *zk_last_error(const zk_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 }  // extern "C"
+
+// ---- allocation-free stepping ----------------------------------------------
+// A file-scope device array stands in for the caller's workspace.  Each GPU
+// that runs zk_step_static holds its own copy until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns on
+// that device (the array's name in host code is not a device address).
+namespace {
+__device__ __align__(256) char scratch[ZK_STATIC_WS_BYTES];
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[kMaxDevices] = {};
+
+int scratch_on_device(zk_ctx *c, int dev, char **out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(c, ZK_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(c, e, "hipGetSymbolAddress(scratch)");
+    if (!p || ((uintptr_t)p % kAlign) != 0) return fail(c, ZK_EDEVICE, "scratch array is not 256-byte aligned");
+    scratch_ptr[dev] = p;
+  }
+  *out = static_cast<char *>(scratch_ptr[dev]);
+  return ZK_OK;
+}
+}  // namespace
+
+extern "C" int zk_step_static(zk_ctx *c, double *eta, double *psi, double dt, int nsteps, void *stream) {
+  if (!c) return ZK_EINVAL;
+  c->err.clear();
+  if (c->total > (size_t)ZK_STATIC_WS_BYTES)
+    return fail(c, ZK_ENOWS, "grid needs " + std::to_string(c->total) + " workspace bytes; the static scratch holds " +
+                                 std::to_string((size_t)ZK_STATIC_WS_BYTES) + " (use zk_bind and zk_step)");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(c, e, "hipGetDevice");
+  char *ws = nullptr;
+  int rc = scratch_on_device(c, dev, &ws);
+  if (rc) return rc;
+  // Borrow the scratch for this call: the context's tables and schedules are
+  // uploaded into it (another context may have left its own there), then the
+  // caller's own binding, if any, is restored and marked for re-upload.
+  char *ws0 = c->ws;
+  const size_t bytes0 = c->ws_bytes;
+  hipStream_t stream0 = c->stream;
+  const int dev0 = c->device;
+  const bool bound0 = c->bound, prof0 = c->prof;
+  c->ws = ws;
+  c->ws_bytes = ZK_STATIC_WS_BYTES;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->device = dev;
+  c->bound = true;
+  c->dirty = true;
+  c->have_plan = false;
+  c->prof = false;  // no timing events inside this call
+  rc = zk_step(c, eta, psi, dt, nsteps);
+  c->ws = ws0;
+  c->ws_bytes = bytes0;
+  c->stream = stream0;
+  c->device = dev0;
+  c->bound = bound0;
+  c->prof = prof0;
+  c->dirty = true;
+  c->have_plan = false;
+  return rc;
+}

@@ -22,7 +22,7 @@ ZK_KERNEL_ROW_PAD, ZK_KERNEL_ROW_BASE, ZK_KERNEL_COL_PAD, ZK_KERNEL_COL_BASE, ZK
 KERNEL_NAMES = {0: "row_pad", 1: "row_base", 2: "col_pad", 3: "col_base", 4: "reduce"}
 
 EXPORTS = ("zk_create", "zk_destroy", "zk_set_option", "zk_workspace_bytes", "zk_bind", "zk_dtn",
-           "zk_rhs", "zk_step", "zk_hamiltonian", "zk_kernel_stats", "zk_autotune", "zk_team_shape", "zk_inverse_dtn",
+           "zk_rhs", "zk_step", "zk_step_static", "zk_hamiltonian", "zk_kernel_stats", "zk_autotune", "zk_team_shape", "zk_inverse_dtn",
            "zk_depth_velocity", "zk_set_team_shape", "zk_last_error",
            "zk_cnn_create", "zk_cnn_destroy", "zk_cnn_workspace_bytes", "zk_cnn_bind", "zk_cnn_set_params",
            "zk_cnn_get_params", "zk_cnn_forward", "zk_cnn_gradient", "zk_cnn_train_step", "zk_cnn_last_error",
@@ -33,6 +33,7 @@ EXPORTS = ("zk_create", "zk_destroy", "zk_set_option", "zk_workspace_bytes", "zk
            "zk_batch_set_option", "zk_batch_step", "zk_batch_autotune", "zk_batch_tuning", "zk_batch_stats",
            "zk_batch_last_error")
 ZK_BATCH_OPT_GRAPH = 1
+ZK_STATIC_WS_BYTES = 64 << 20  # size of the library's fixed device scratch (zk.h)
 
 
 class ZkTile(ctypes.Structure):
@@ -74,6 +75,8 @@ def lib():
     L.zk_rhs.restype = i
     L.zk_step.argtypes = [vp, vp, vp, d, i]
     L.zk_step.restype = i
+    L.zk_step_static.argtypes = [vp, vp, vp, d, i, vp]
+    L.zk_step_static.restype = i
     L.zk_hamiltonian.argtypes = [vp, vp, vp, ctypes.POINTER(d)]
     L.zk_hamiltonian.restype = i
     L.zk_kernel_stats.argtypes = [vp, i, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d),
@@ -189,6 +192,11 @@ def zk_rhs(ctx, eta_ptr, psi_ptr, eta_t_ptr, psi_t_ptr):
 
 def zk_step(ctx, eta_ptr, psi_ptr, dt, nsteps):
     return _check(ctx, lib().zk_step(ctx, eta_ptr, psi_ptr, float(dt), int(nsteps)))
+
+
+def zk_step_static(ctx, eta_ptr, psi_ptr, dt, nsteps, stream_ptr):
+    """zk_step with the library's fixed device scratch as workspace (no zk_bind, no allocation)."""
+    return _check(ctx, lib().zk_step_static(ctx, eta_ptr, psi_ptr, float(dt), int(nsteps), stream_ptr))
 
 
 def zk_hamiltonian(ctx, eta_ptr, psi_ptr):
