@@ -290,8 +290,26 @@ def batch_form(nsteps=100, seq_steps=20, ntiles=256):
     tb = time.perf_counter() - t0
     print(f"# batch form: {nsteps} batched steps in {tb:.2f} s", file=sys.stderr, flush=True)
     st_b = b.stats()
-    b.close()
-    del b, es, ps
+    # the persistent form: one launch per step, the same tiles and steps
+    bp = Batch(tiles, g=g, precision=32, device=dev, persistent=True)
+    ep = [torch.tensor(e, dtype=torch.float64, device=dev) for e, _ in states]
+    pp = [torch.tensor(p, dtype=torch.float64, device=dev) for _, p in states]
+    bp.set_fields(ep, pp)
+    tuning_p = bp.autotune(dt, reps=2)
+    bp.step(dt, 2)
+    for k, (e, p) in enumerate(states):
+        ep[k].copy_(torch.from_numpy(e))
+        pp[k].copy_(torch.from_numpy(p))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bp.step(dt, nsteps)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    print(f"# batch form: {nsteps} persistent steps in {tp:.2f} s", file=sys.stderr, flush=True)
+    pdiff = max(rel_max(ep[k], es[k]) for k in range(ntiles))
+    st_p = bp.stats()
+    bp.close()
+    del b, es, ps, bp, ep, pp
     torch.cuda.empty_cache()
     # the same tiles one context after another (seq_steps steps, same start)
     solvers, es2, ps2 = [], [], []
@@ -328,7 +346,10 @@ def batch_form(nsteps=100, seq_steps=20, ntiles=256):
             "sequential_value": round(pts * seq_steps / ts, 1), "sequential_steps": seq_steps,
             "speedup_vs_sequential": round((pts * nsteps / tb) / (pts * seq_steps / ts), 3),
             "phases_per_step": st_b["phases_per_step"], "launches_per_step": st_b["launches_per_step"],
-            "graph": True, "tuning": tuning, "max_rel_diff_vs_sequential_eta": diff}
+            "graph": True, "tuning": tuning, "max_rel_diff_vs_sequential_eta": diff,
+            "persistent": {"value": round(pts * nsteps / tp, 1), "ms_per_step": round(1e3 * tp / nsteps, 3),
+                           "launches_per_step": st_p["launches_per_step"], "speedup_vs_graph": round(tb / tp, 3),
+                           "max_rel_diff_vs_graph_eta": pdiff, "tuning": tuning_p}}
 
 
 def ifab2_form(w, warmup, nsteps, rk4_value, rk4_eta):

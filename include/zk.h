@@ -25,9 +25,10 @@
  *   Errors     0 on success, a negative ZK_E* code otherwise, with a message
  *              in zk_last_error.  No exception crosses the ABI.
  *   Threads    a context is not thread-safe; use one context per stream.
- *   Sizes      nx and ny must be powers of two in [64, 2048]; nx is the fast
- *              (row) axis.  The dealiased products run on the 3nx/2 x 3ny/2
- *              grid.  Spectra keep their Nyquist row and column at zero, so
+ *   Sizes      nx and ny must each be a power of two in [64, 2048] or three
+ *              times one in [96, 1536] (96, 192, 384, 768, 1536); nx is the
+ *              fast (row) axis.  The dealiased products run on the
+ *              3nx/2 x 3ny/2 grid.  Spectra keep their Nyquist row and column at zero, so
  *              input fields are projected onto |m_x| < nx/2, |m_y| < ny/2.
  */
 #ifndef ZK_H
@@ -216,7 +217,7 @@ int zk_kernel_stats(zk_ctx *ctx, int kind, double *ms, double *bytes, double *fl
 
 /* Autotuner: for each pass kind (row / column, padded / base transform),
  * time every compiled team shape (T threads per transform, first-pass radix
- * E = N / T, T a power of two in [32, 1024]) on the passes of one RK4 step of this
+ * E = N / T, T a power of two in [16, 1024]) on the passes of one RK4 step of this
  * context (reps timed repetitions each; the context's internal spectra are
  * overwritten, no caller field is touched) and keep the fastest for later
  * calls.  Results are identical up to FP64 (or FP32) rounding order.
@@ -231,8 +232,9 @@ int zk_team_shape(const zk_ctx *ctx, int row, int pad, int *T, int *E);
  * T threads per transform, first-pass radix E = N / T for the pass's
  * transform length N (3n/2 padded, n base).  T = 0 restores the default.
  * ZK_EINVAL if T does not divide N into a compiled shape (T a power of two
- * in [32, 1024]; E in {3, 6, 12} padded or {2, 4, 8} base, and the pair
- * built for the context's precision).  Host only; applies from the next call. */
+ * in [16, 1024]; power-of-two axes: E in {3, 6, 12} padded or {2, 4, 8} base;
+ * axes of 3 2^k points: E = 9 padded, 6 base; and the pair built for the
+ * context's precision).  Host only; applies from the next call. */
 int zk_set_team_shape(zk_ctx *ctx, int row, int pad, int T);
 
 /* Text of the last error on this context ("" if none).  Valid until the next
@@ -362,15 +364,25 @@ const char *zk_closure_last_error(const zk_closure *clo);
  * batch itself and keeps the fastest.  Tile sizes follow zk_create's rule.
  * ------------------------------------------------------------------------- */
 typedef struct zk_tile {
-    int nx, ny;           /* grid points (powers of two in [64, 2048])      */
+    int nx, ny;           /* grid points (as zk_create)                     */
     double Lx, Ly, depth; /* domain size and still-water depth (<= 0: deep) */
     int M;                /* HOS order, 1..8                               */
 } zk_tile;
 typedef struct zk_batch zk_batch;
 
 enum {
-    ZK_BATCH_OPT_GRAPH = 1  /* 1: replay each step as a HIP graph (default);
-                               0: launch the phases one by one           */
+    ZK_BATCH_OPT_GRAPH = 1,      /* 1: replay each step as a HIP graph (default);
+                                    0: launch the phases one by one           */
+    ZK_BATCH_OPT_PERSISTENT = 2  /* 1: each step is one persistent launch: its
+                                    workers take (tile, pass, item, block
+                                    chunk) units in phase order from a device
+                                    queue and wait on per-tile completion
+                                    counters (bounded waits: one that runs out
+                                    makes zk_batch_step return ZK_EDEVICE, and
+                                    the call synchronises to read that flag).
+                                    Tiles of 128 to 1024 points per axis only,
+                                    transforms with the smallest first-pass
+                                    radix.  0 (default): as ZK_BATCH_OPT_GRAPH */
 };
 
 /* precision: 64 (FP64 transforms) or 32 (FP32 transforms, FP64 series,

@@ -26,7 +26,7 @@ LIB = os.path.join(HERE, "libzk.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 HIP_UNITS = ["zk_reduce.hip", "zk_bc.hip", "zk_cnn.hip", "zk_closure.hip", "zk_batch_row_f64.hip", "zk_batch_row_f32.hip", "zk_batch_col_f64.hip",
-             "zk_batch_col_f32.hip"]
+             "zk_batch_col_f32.hip", "zk_persist.hip"]
 HIP_HOST_UNITS = ["zk_api.cpp", "zk_cnn_api.cpp", "zk_closure_api.cpp", "zk_batch.cpp"]
 CXX_UNITS = ["zk_plan.cpp"]
 

@@ -1,11 +1,15 @@
 """Writes the batched-kernel instantiation units zk_batch_{row,col}_{f64,f32}.hip
-(one function per unit mapping a team shape (T, E) to its kernel).  Run from
-any directory; the units are committed, this script regenerates them."""
+(one function per unit mapping a team shape (T, E, padded) to its kernel).  Run
+from any directory; the units are committed, this script regenerates them."""
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SHAPES = ([(T, E) for T in (32, 64, 128, 256) for E in (2, 3, 4, 6, 8, 12)] + [(512, E) for E in (2, 3, 4, 6)]
-          + [(1024, E) for E in (2, 3)])
+# power-of-two axes: padded iff E % 3 == 0
+POW2 = ([(T, E) for T in (32, 64, 128, 256) for E in (2, 3, 4, 6, 8, 12)] + [(512, E) for E in (2, 3, 4, 6)]
+        + [(1024, E) for E in (2, 3)])
+SHAPES = [(T, E, E % 3 == 0) for T, E in POW2]
+# axes of n = 3 2^k points: padded transforms with E = 9, base transforms with E = 6
+SHAPES += [(T, 9, True) for T in (16, 32, 64, 128, 256)] + [(T, 6, False) for T in (16, 32, 64, 128, 256)]
 
 
 FOLD_SHAPES = [(T, E) for T in (64, 128, 256) for E in (2, 3)]  # as fold_team_shape() in zk_kernels.hpp
@@ -14,21 +18,36 @@ FOLD_SHAPES = [(T, E) for T in (64, 128, 256) for E in (2, 3)]  # as fold_team_s
 def bs(T):
     return max(256, T)
 
+
+def targs(kind, T, E, pad, lift=False):
+    """template arguments of a kernel instance after its real type: row
+    kernels (T, E[, PAD]), column kernels (T, E[, LIFTSYM[, PAD]]); the padded
+    flag is written only where it differs from its default, E % 3 == 0"""
+    out = [str(T), str(E)]
+    odd = pad != (E % 3 == 0)
+    if kind == "col" and (lift or odd):
+        out.append("true" if lift else "false")
+    if odd:
+        out.append("true" if pad else "false")
+    return ", ".join(out)
+
 for kind in ("row", "col"):
     for real, tag in (("double", "f64"), ("float", "f32")):
         lines = [f"// zk_batch_{kind}_{tag}.hip -- batched {kind}-pass kernel instances ({real} transforms);",
                  "// written by gen_batch_units.py.",
                  '#include "zk_kernels.hpp"', "", "namespace zk {", "", "template <>",
-                 f"const void *batch_{kind}_kernel<{real}>(int T, int E) {{"]
-        for T, E in SHAPES:
-            lines.append(f"  if (T == {T} && E == {E}) return reinterpret_cast<const void *>(&{kind}_kernel_batch<{real}, {T}, {E}>);")
+                 f"const void *batch_{kind}_kernel<{real}>(int T, int E, bool pad) {{"]
+        for T, E, pad in SHAPES:
+            ta = targs(kind, T, E, pad)
+            lines.append(f"  if (T == {T} && E == {E} && pad == {'true' if pad else 'false'}) return reinterpret_cast<const void *>(&{kind}_kernel_batch<{real}, {ta}>);")
         lines += ["  return nullptr;", "}", "",
                   "template <>",
-                  f"hipError_t launch_batch_{kind}<{real}>(int T, int E, dim3 grid, hipStream_t s, const {'RowArgs' if kind == 'row' else 'ColArgs'}<{real}> *args,",
+                  f"hipError_t launch_batch_{kind}<{real}>(int T, int E, bool pad, dim3 grid, hipStream_t s, const {'RowArgs' if kind == 'row' else 'ColArgs'}<{real}> *args,",
                   "                                   const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {"]
-        for T, E in SHAPES:
-            lines.append(f"  if (T == {T} && E == {E}) {{")
-            lines.append(f"    hipLaunchKernelGGL(({kind}_kernel_batch<{real}, {T}, {E}>), grid, dim3({bs(T)}), 0, s, args, items, tile0, first0, sched0, ph);")
+        for T, E, pad in SHAPES:
+            ta = targs(kind, T, E, pad)
+            lines.append(f"  if (T == {T} && E == {E} && pad == {'true' if pad else 'false'}) {{")
+            lines.append(f"    hipLaunchKernelGGL(({kind}_kernel_batch<{real}, {ta}>), grid, dim3({bs(T)}), 0, s, args, items, tile0, first0, sched0, ph);")
             lines.append("    return hipGetLastError();")
             lines.append("  }")
         lines += ["  return hipErrorInvalidValue;", "}", ""]
@@ -36,11 +55,11 @@ for kind in ("row", "col"):
             lines += ["template <>",
                       f"hipError_t launch_batch_col_lift<{real}>(int T, int E, dim3 grid, hipStream_t s, const ColArgs<{real}> *args,",
                       "                                        const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {"]
-            for T, E in SHAPES:
-                if E % 3 == 0:
+            for T, E, pad in SHAPES:
+                if pad:
                     continue
                 lines.append(f"  if (T == {T} && E == {E}) {{")
-                lines.append(f"    hipLaunchKernelGGL((col_kernel_batch<{real}, {T}, {E}, true>), grid, dim3({bs(T)}), 0, s, args, items, tile0, first0, sched0, ph);")
+                lines.append(f"    hipLaunchKernelGGL((col_kernel_batch<{real}, {targs('col', T, E, pad, True)}>), grid, dim3({bs(T)}), 0, s, args, items, tile0, first0, sched0, ph);")
                 lines.append("    return hipGetLastError();")
                 lines.append("  }")
             lines += ["  return hipErrorInvalidValue;", "}", ""]

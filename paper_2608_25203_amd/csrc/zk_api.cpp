@@ -21,7 +21,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-bool pow2_in(int n) { return n >= 64 && n <= 2048 && (n & (n - 1)) == 0; }
+
 
 int fail(zk_ctx *c, int code, const std::string &m) {
   if (c) c->err = m;
@@ -140,9 +140,12 @@ template <typename real>
 std::vector<cpx<real>> twiddles(int n) {
   std::vector<cpx<real>> t((size_t)kTwSlots * n, cpx<real>{(real)0, (real)0});
   const long double two_pi = 2.0L * 3.14159265358979323846264338327950288L;
-  const bool pad = n % 3 == 0;
+  // candidate first-pass radices of this length, one per slot (tw_slot)
+  const int cand[kTwSlots] = {n % 9 == 0 ? 9 : (n % 3 == 0 ? 3 : 2), n % 9 == 0 ? 18 : (n % 3 == 0 ? 6 : 4),
+                              n % 9 == 0 ? 0 : (n % 3 == 0 ? 12 : 8)};
   for (int s = 0; s < kTwSlots; ++s) {
-    const int E = pad ? 3 << s : 2 << s;
+    const int E = cand[s];
+    if (E == 0) continue;
     const int T = n / E;
     if (n % E || T < 2 || (T & (T - 1)) || num_passes(T) < 2) continue;
     cpx<real> *tab = t.data() + (size_t)s * n;
@@ -193,11 +196,13 @@ int upload(zk_ctx *c, double dt) {
     {
       const long double pi = 3.14159265358979323846264338327950288L;
       const long double kxs = 2 * pi / c->pp.Lx, kys = 2 * pi / c->pp.Ly;
-      const long double kc = 2.0L / 3.0L * std::min(pi * nx / c->pp.Lx, pi * ny / c->pp.Ly);
+      // kNyq over the axes that have one (a 1D grid, ny = 1, has only x)
+      const long double kc =
+          2.0L / 3.0L * (ny > 1 ? std::min(pi * nx / c->pp.Lx, pi * ny / c->pp.Ly) : pi * nx / c->pp.Lx);
       std::vector<SymEl> tab((size_t)(nx / 2) * ny);
       for (int col = 0; col < nx / 2; ++col)
         for (int b = 0; b < ny; ++b) {
-          const int my = b < ny / 2 ? b : b - ny;
+          const int my = (b < ny / 2 || ny == 1) ? b : b - ny;  // a 1D grid's one row is ky = 0
           const long double kx = kxs * col, ky = kys * my;
           const long double kk = sqrtl(kx * kx + ky * ky);
           const long double r = kk / kc, r2 = r * r, r4 = r2 * r2;
@@ -213,7 +218,7 @@ int upload(zk_ctx *c, double dt) {
       };
       std::vector<double> fx(nx / 2), fy(ny);
       for (int col = 0; col < nx / 2; ++col) fx[col] = f1(col, nx);
-      for (int b = 0; b < ny; ++b) fy[b] = f1(b < ny / 2 ? b : b - ny, ny);
+      for (int b = 0; b < ny; ++b) fy[b] = f1((b < ny / 2 || ny == 1) ? b : b - ny, ny);
       HIP_TRY(c, put(c->off_sym, tab.data(), tab.size() * sizeof(SymEl)));
       HIP_TRY(c, put(c->off_fx, fx.data(), fx.size() * sizeof(double)));
       HIP_TRY(c, put(c->off_fy, fy.data(), fy.size() * sizeof(double)));
@@ -274,7 +279,7 @@ int upload(zk_ctx *c, double dt) {
     std::vector<double> tab((size_t)(nx / 2) * ny * kIfCoefs);
     for (int col = 0; col < nx / 2; ++col)
       for (int b = 0; b < ny; ++b) {
-        const int my = b < ny / 2 ? b : b - ny;
+        const int my = (b < ny / 2 || ny == 1) ? b : b - ny;
         const long double kx = kxs * col, ky = kys * my, kk = sqrtl(kx * kx + ky * ky);
         const long double G0 = c->pp.depth > 0 ? kk * tanhl(kk * c->pp.depth) : kk;
         const long double om = sqrtl(g * G0);
@@ -335,8 +340,10 @@ int run_seq_t(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
       const PhysArgs pa{ph.in0, ph.in1, ph.in2, ph.out0, ph.out1, 1};
       const dim3 grid(sh.blocks, l.count);
       const ColArgs<real> *cargs = reinterpret_cast<const ColArgs<real> *>(ws + c->off_cargs);
-      if (row)
-        e = launch_batch_row<real>(sh.T, sh.E, grid, c->stream,
+      if (!row && c->pp.ny == 1)  // 1D grid: one element per column, no y transform
+        e = launch_col_1d<real>(l.c2 == 1, dim3((nx / 2 + 255) / 256, l.count), c->stream, cargs, tile0, first0);
+      else if (row)
+        e = launch_batch_row<real>(sh.T, sh.E, pad, grid, c->stream,
                                    reinterpret_cast<const RowArgs<real> *>(ws + c->off_rargs), items, tile0, first0,
                                    sched0, pa);
       else if (l.c2 == 1)
@@ -345,7 +352,7 @@ int run_seq_t(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
         e = launch_batch_col_folds<real>(sh.T, sh.E, dim3(nx / 2, l.count), c->stream, cargs, items, tile0, first0,
                                          sched0, pa);
       else
-        e = launch_batch_col<real>(sh.T, sh.E, grid, c->stream, cargs, items, tile0, first0, sched0, pa);
+        e = launch_batch_col<real>(sh.T, sh.E, pad, grid, c->stream, cargs, items, tile0, first0, sched0, pa);
     } else {
       double *red = reinterpret_cast<double *>(ws + c->off_red);
       e = launch_parseval(base + (long long)l.first * c->base_stride, base + (long long)l.count * c->base_stride,
@@ -405,10 +412,17 @@ TeamShape ctx_team(const zk_ctx *c, bool row, bool pad) {
   const int n = row ? c->pp.nx : c->pp.ny;
   const int N = pad ? 3 * n / 2 : n;
   TeamShape sh;
-  sh.T = c->tuneT[row][pad] ? c->tuneT[row][pad] : N / (pad ? 3 : 2);
+  if (!row && n == 1) {  // a 1D grid's columns: one thread per column (col_kernel_1d)
+    sh.T = 1;
+    sh.E = 1;
+    sh.blocks = (c->pp.nx / 2 + 255) / 256;
+    return sh;
+  }
+  sh.T = c->tuneT[row][pad] ? c->tuneT[row][pad] : N / default_radix(n, pad);
   sh.E = N / sh.T;
   const int tpb = sh.T < 256 ? 256 / sh.T : 1;
-  sh.blocks = row ? (pad ? 3 * c->pp.ny / 2 : c->pp.ny) / tpb : (c->pp.nx / 2) / tpb;
+  // (rows of a 1D grid: 1, in a block whose other teams idle)
+  sh.blocks = row ? ((pad ? 3 * c->pp.ny / 2 : c->pp.ny) + tpb - 1) / tpb : (c->pp.nx / 2) / tpb;
   return sh;
 }
 
@@ -438,7 +452,7 @@ template <typename real>
 ColArgs<real> ctx_col_args(const zk_ctx *c, bool pad, int task0) {
   char *ws = c->ws;
   const int nx = c->pp.nx, ny = c->pp.ny;
-  const double kc = 2.0 / 3.0 * std::min(M_PI * nx / c->pp.Lx, M_PI * ny / c->pp.Ly);
+  const double kc = 2.0 / 3.0 * (ny > 1 ? std::min(M_PI * nx / c->pp.Lx, M_PI * ny / c->pp.Ly) : M_PI * nx / c->pp.Lx);
   ColArgs<real> a{};
   a.tasks = reinterpret_cast<const ColTask *>(ws + c->off_tasks);
   a.task0 = task0;
@@ -486,7 +500,7 @@ int ctx_run(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) { return 
 extern "C" {
 
 zk_ctx *zk_create(int nx, int ny, double Lx, double Ly, double depth, double g, int M) {
-  if (!pow2_in(nx) || !pow2_in(ny)) return nullptr;
+  if (!axis_len_ok(nx) || !(axis_len_ok(ny) || ny == 1)) return nullptr;  // ny = 1: a 1D grid
   if (!(Lx > 0) || !(Ly > 0) || !(g > 0) || M < 1 || M > 8) return nullptr;
   zk_ctx *c = new (std::nothrow) zk_ctx();
   if (!c) return nullptr;
@@ -546,8 +560,8 @@ int zk_set_option(zk_ctx *c, int key, double v) {
     case ZK_OPT_BOUNDARY:
       if (v != ZK_BC_PERIODIC && v != ZK_BC_REFLECT) return fail(c, ZK_EINVAL, "unknown boundary");
       if (c->bound && (int)v != c->bc) return fail(c, ZK_EINVAL, "set the boundary before zk_bind");
-      if (v == ZK_BC_REFLECT && (2 * c->unx > 2048 || 2 * c->uny > 2048))
-        return fail(c, ZK_EINVAL, "reflecting walls need nx, ny <= 1024 (the grid is doubled)");
+      if (v == ZK_BC_REFLECT && (!axis_len_ok(2 * c->unx) || !axis_len_ok(2 * c->uny)))
+        return fail(c, ZK_EINVAL, "reflecting walls double the grid: 2 nx and 2 ny must be built lengths");
       c->bc = (int)v;
       c->pp.nx = c->bc ? 2 * c->unx : c->unx;
       c->pp.ny = c->bc ? 2 * c->uny : c->uny;
@@ -803,16 +817,20 @@ int zk_autotune(zk_ctx *c, double dt, int reps) {
         const bool lp = l.kind == L_ROW_PAD || l.kind == L_COL_PAD;
         if (l.kind != L_PARSEVAL && lr == (bool)row && lp == (bool)pad) sub.push_back(l);
       }
-      if (sub.empty()) continue;
+      if (sub.empty() || (!row && c->pp.ny == 1)) continue;  // a 1D grid's columns have one shape
       const int n = row ? c->pp.nx : c->pp.ny;
       const int N = pad ? 3 * n / 2 : n;
       float best = 1e30f;
       int bestT = 0;
-      for (int E : pad ? std::vector<int>{3, 6, 12} : std::vector<int>{2, 4, 8}) {
+      int cand[3];
+      const int ncand = radix_candidates(n, pad, cand);
+      for (int ci = 0; ci < ncand; ++ci) {
+        const int E = cand[ci];
         const int T = N / E;
-        if (N % E || T < 32 || T > 1024 || (T & (T - 1))) continue;
-        const void *fn = c->precision == 32 ? (row ? batch_row_kernel<float>(T, E) : batch_col_kernel<float>(T, E))
-                                            : (row ? batch_row_kernel<double>(T, E) : batch_col_kernel<double>(T, E));
+        if (N % E || T < 16 || T > 1024 || (T & (T - 1))) continue;
+        const void *fn = c->precision == 32
+                             ? (row ? batch_row_kernel<float>(T, E, pad) : batch_col_kernel<float>(T, E, pad))
+                             : (row ? batch_row_kernel<double>(T, E, pad) : batch_col_kernel<double>(T, E, pad));
         if (!fn) continue;
         c->tuneT[row][pad] = T;
         float tot = 0.f;
@@ -857,12 +875,14 @@ int zk_set_team_shape(zk_ctx *c, int row, int pad, int T) {
   }
   const int n = row ? c->pp.nx : c->pp.ny;
   const int N = pad ? 3 * n / 2 : n;
-  if (T < 32 || T > 1024 || (T & (T - 1)) || N % T) return fail(c, ZK_EINVAL, "team size must divide the transform length");
+  if (!row && n == 1) return fail(c, ZK_EINVAL, "a 1D grid's column passes have no team shape");
+  if (T < 16 || T > 1024 || (T & (T - 1)) || N % T) return fail(c, ZK_EINVAL, "team size must divide the transform length");
   const int E = N / T;
-  const void *fn = c->precision == 32 ? (row ? batch_row_kernel<float>(T, E) : batch_col_kernel<float>(T, E))
-                                      : (row ? batch_row_kernel<double>(T, E) : batch_col_kernel<double>(T, E));
-  if (!fn || !(pad ? (E == 3 || E == 6 || E == 12) : (E == 2 || E == 4 || E == 8)))
-    return fail(c, ZK_EINVAL, "team shape not built");
+  const void *fn = c->precision == 32 ? (row ? batch_row_kernel<float>(T, E, pad) : batch_col_kernel<float>(T, E, pad))
+                                      : (row ? batch_row_kernel<double>(T, E, pad) : batch_col_kernel<double>(T, E, pad));
+  int cand[3];
+  const int ncand = radix_candidates(n, pad, cand);
+  if (!fn || std::find(cand, cand + ncand, E) == cand + ncand) return fail(c, ZK_EINVAL, "team shape not built");
   c->tuneT[row][pad] = T;
   return ZK_OK;
 }

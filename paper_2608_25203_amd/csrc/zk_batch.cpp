@@ -8,7 +8,10 @@
 // launches left needs.  Within a phase, tiles of one size share one batched
 // launch: blockIdx.y runs over (tile, program or task) items, each reading
 // its tile's argument record from a device table.  The phases of one RK4
-// step are recorded once as a HIP graph (kernel nodes only) and replayed.
+// step are recorded once as a HIP graph (kernel nodes only) and replayed;
+// or (ZK_BATCH_OPT_PERSISTENT) each merged segment runs as one persistent
+// launch whose workers take (tile, pass, item, block chunk) units in phase
+// order and wait on per-tile completion counters (zk_persist.hpp).
 // The team shape (T threads, radix E) of each pass and size is chosen by an
 // empirical autotuner among the compiled shapes.
 #include <hip/hip_runtime.h>
@@ -24,6 +27,7 @@
 #include "zk.h"
 #include "zk_ctx_internal.hpp"
 #include "zk_kernels.hpp"
+#include "zk_persist.hpp"
 
 using namespace zk;
 
@@ -61,6 +65,14 @@ struct zk_batch {
   std::vector<Phase> seg[kSegs];
   std::vector<BatchItem> items;
   hipGraphExec_t exec[kSegs] = {};
+  // persistent form
+  bool persistent = false;
+  size_t off_units = 0, units_cap = 0, off_ctr = 0;
+  std::vector<PUnit> units;
+  size_t useg0[kSegs] = {}, usegn[kSegs] = {};
+  int useg_lds[kSegs] = {};
+  int workers = 0;
+  uint32_t spin_limit = 1u << 20;  // sleeps of ~0.1 us each: a wait gives up after about 0.1-1 s
   std::string err;
   long long launches_per_step = 0, phases_per_step = 0;
   ~zk_batch() {
@@ -90,20 +102,24 @@ int hip_fail(zk_batch *b, hipError_t e, const char *what) {
 
 bool is_row(int kind) { return kind == L_ROW_PAD || kind == L_ROW_BASE; }
 
-const void *kernel_for(const zk_batch *b, bool row, int T, int E) {
-  if (b->precision == 32) return row ? batch_row_kernel<float>(T, E) : batch_col_kernel<float>(T, E);
-  return row ? batch_row_kernel<double>(T, E) : batch_col_kernel<double>(T, E);
+const void *kernel_for(const zk_batch *b, bool row, int T, int E, bool pad) {
+  if (b->precision == 32) return row ? batch_row_kernel<float>(T, E, pad) : batch_col_kernel<float>(T, E, pad);
+  return row ? batch_row_kernel<double>(T, E, pad) : batch_col_kernel<double>(T, E, pad);
 }
 
-// Candidate team shapes of a transform of length N (padded: E in {3, 6, 12};
-// base: E in {2, 4, 8}), T in {32, ..., 1024} threads.
+// Candidate team shapes of a transform of an axis of n points (radix_candidates),
+// T in {16, ..., 1024} threads.
 std::vector<std::pair<int, int>> candidates(const zk_batch *b, bool row, bool pad, int n) {
   std::vector<std::pair<int, int>> out;
   const int N = pad ? 3 * n / 2 : n;
-  for (int E : pad ? std::vector<int>{3, 6, 12} : std::vector<int>{2, 4, 8}) {
+  int cand[3];
+  const int ncand = radix_candidates(n, pad, cand);
+  for (int ci = 0; ci < ncand; ++ci) {
+    const int E = cand[ci];
     if (N % E) continue;
     const int T = N / E;
-    if (T >= 32 && T <= 1024 && !(T & (T - 1)) && kernel_for(b, row, T, E)) out.push_back({T, E});
+    if (b->persistent && persist_shape(row, T, E) < 0) continue;  // not hosted by the persistent kernel
+    if (T >= 16 && T <= 1024 && !(T & (T - 1)) && kernel_for(b, row, T, E, pad)) out.push_back({T, E});
   }
   return out;
 }
@@ -113,7 +129,7 @@ std::pair<int, int> shape_of(zk_batch *b, bool row, bool pad, int nx, int ny) {
   auto it = b->tune.find(k);
   if (it != b->tune.end()) return it->second;
   const int n = row ? nx : ny;  // default: the smallest first-pass radix (as a single context)
-  const int E = pad ? 3 : 2;
+  const int E = default_radix(n, pad);
   return {(pad ? 3 * n / 2 : n) / E, E};
 }
 
@@ -165,7 +181,7 @@ void merge(zk_batch *b, const std::vector<std::vector<Launch>> &seqs, std::vecto
 }
 
 void kernel_params(const zk_batch *b, const BL &l, const void **fn, void **args_dev, BatchItem **items_dev) {
-  *fn = kernel_for(b, l.row, l.T, l.E);
+  *fn = kernel_for(b, l.row, l.T, l.E, l.pad);
   *args_dev = b->ws + (l.row ? b->off_rargs : b->off_cargs);
   *items_dev = reinterpret_cast<BatchItem *>(b->ws + b->off_items) + l.item0;
 }
@@ -234,6 +250,75 @@ int build_graph(zk_batch *b, int s) {
   return rc;
 }
 
+// Blocks of kPBlock threads (kPBlock / T teams each) covering a pass.
+int pblocks_of(bool row, bool pad, int nx, int ny, int T) {
+  const int per = kPBlock / T;
+  return row ? (pad ? 3 * ny / 2 : ny) / per : (nx / 2) / per;
+}
+
+// Units of the persistent form, segment by segment, in phase order: each
+// item of each batched launch is cut into at most kUnitsPerItem chunks of at
+// least kMinUnitBlocks consecutive blocks; a unit waits for every unit of
+// its tile's earlier phases in the same segment.
+constexpr int kUnitsPerItem = 32, kMinUnitBlocks = 2, kStagger = 1;
+int build_units(zk_batch *b) {
+  const int nt = (int)b->tiles.size();
+  b->units.clear();
+  int maxlds = 0;
+  std::vector<uint32_t> cum(nt), start(nt);
+  for (int s = 0; s < kSegs; ++s) {
+    b->useg0[s] = b->units.size();
+    b->useg_lds[s] = 0;
+    std::fill(cum.begin(), cum.end(), 0u);
+    std::vector<int> key;  // queue position: the phase, staggered by tile
+    int pi = 0;
+    for (const Phase &ph : b->seg[s]) {
+      start = cum;
+      for (const BL &l : ph) {
+        const int shape = persist_shape(l.row, l.T, l.E);
+        if (shape < 0)
+          return fail(b, ZK_EINVAL, "persistent form: the tiles' transforms must be 128 to 1024 points per axis "
+                                    "with the smallest first-pass radix");
+        const int lds = b->precision == 32 ? persist_lds_bytes<float>(shape) : persist_lds_bytes<double>(shape);
+        b->useg_lds[s] = std::max(b->useg_lds[s], lds);
+        const int nblk = pblocks_of(l.row, l.pad, l.nx, l.ny, l.T);
+        const int chunk = std::max(kMinUnitBlocks, (nblk + kUnitsPerItem - 1) / kUnitsPerItem);
+        for (int k = l.item0; k < l.item0 + l.nitems; ++k) {
+          const BatchItem it = b->items[k];
+          const int t = it.tile / 2;
+          for (int b0 = 0; b0 < nblk; b0 += chunk) {
+            b->units.push_back(PUnit{shape, it.tile, it.index, b0, std::min(chunk, nblk - b0), t, start[t], 0});
+            key.push_back(pi + t % kStagger);
+            ++cum[t];
+          }
+        }
+      }
+      ++pi;
+    }
+    // Tile t's phase p is queued at slot p + (t mod kStagger): a tile's next
+    // phase never follows its current one directly, while each tile's phases
+    // (all a unit waits on) stay in order, earlier in the queue.
+    {
+      const size_t u0 = b->useg0[s], nu = b->units.size() - u0;
+      std::vector<size_t> ord(nu);
+      for (size_t i = 0; i < nu; ++i) ord[i] = i;
+      std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return key[x] < key[y]; });
+      std::vector<PUnit> seg(nu);
+      for (size_t i = 0; i < nu; ++i) seg[i] = b->units[u0 + ord[i]];
+      std::copy(seg.begin(), seg.end(), b->units.begin() + u0);
+    }
+    b->usegn[s] = b->units.size() - b->useg0[s];
+    maxlds = std::max(maxlds, b->useg_lds[s]);
+  }
+  if (b->units.size() > b->units_cap) return fail(b, ZK_EINVAL, "persistent schedule exceeds its reserved capacity");
+  int cus = 0;
+  HIP_TRY(b, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+  const int per = b->precision == 32 ? persistent_blocks_per_cu<float>(maxlds) : persistent_blocks_per_cu<double>(maxlds);
+  if (per < 1 || cus < 1) return fail(b, ZK_EDEVICE, "persistent kernel does not fit a compute unit");
+  b->workers = per * cus;
+  return ZK_OK;
+}
+
 // Plans for dt, argument tables, merged schedules and graphs.
 int prepare(zk_batch *b, double dt) {
   if (b->ready && dt == b->dt) return ZK_OK;
@@ -291,13 +376,21 @@ int prepare(zk_batch *b, double dt) {
   b->phases_per_step = (long long)b->seg[1].size();
   b->launches_per_step = 0;
   for (auto &ph : b->seg[1]) b->launches_per_step += (long long)ph.size();
+  if (b->persistent) {
+    const int rc = build_units(b);
+    if (rc) return rc;
+    b->launches_per_step = 1;
+  }
   HIP_TRY(b, hipSetDevice(b->device));
   HIP_TRY(b, hipMemcpyAsync(b->ws + b->off_rargs, rtab.data(), rtab.size(), hipMemcpyHostToDevice, b->stream));
   HIP_TRY(b, hipMemcpyAsync(b->ws + b->off_cargs, ctab.data(), ctab.size(), hipMemcpyHostToDevice, b->stream));
   HIP_TRY(b, hipMemcpyAsync(b->ws + b->off_items, b->items.data(), b->items.size() * sizeof(BatchItem),
                             hipMemcpyHostToDevice, b->stream));
+  if (b->persistent && !b->units.empty())
+    HIP_TRY(b, hipMemcpyAsync(b->ws + b->off_units, b->units.data(), b->units.size() * sizeof(PUnit),
+                              hipMemcpyHostToDevice, b->stream));
   HIP_TRY(b, hipStreamSynchronize(b->stream));
-  if (b->use_graph)
+  if (b->use_graph && !b->persistent)
     for (int s = 0; s < kSegs; ++s) {
       const int rc = build_graph(b, s);
       if (rc) return rc;
@@ -308,6 +401,23 @@ int prepare(zk_batch *b, double dt) {
 }
 
 int run_seg(zk_batch *b, int s) {
+  if (b->persistent) {
+    if (!b->usegn[s]) return ZK_OK;
+    uint32_t *ctr = reinterpret_cast<uint32_t *>(b->ws + b->off_ctr);
+    const PUnit *u = reinterpret_cast<const PUnit *>(b->ws + b->off_units) + b->useg0[s];
+    HIP_TRY(b, launch_persist_reset(ctr, (int)b->tiles.size(), b->stream));
+    if (b->precision == 32)
+      HIP_TRY(b, launch_persistent<float>(b->workers, b->useg_lds[s], b->stream,
+                                          reinterpret_cast<const RowArgs<float> *>(b->ws + b->off_rargs),
+                                          reinterpret_cast<const ColArgs<float> *>(b->ws + b->off_cargs), u,
+                                          (int)b->usegn[s], ctr, b->spin_limit));
+    else
+      HIP_TRY(b, launch_persistent<double>(b->workers, b->useg_lds[s], b->stream,
+                                           reinterpret_cast<const RowArgs<double> *>(b->ws + b->off_rargs),
+                                           reinterpret_cast<const ColArgs<double> *>(b->ws + b->off_cargs), u,
+                                           (int)b->usegn[s], ctr, b->spin_limit));
+    return ZK_OK;
+  }
   if (b->use_graph) {
     HIP_TRY(b, hipGraphLaunch(b->exec[s], b->stream));
     return ZK_OK;
@@ -342,6 +452,10 @@ zk_batch *zk_batch_create(int ntiles, const zk_tile *tiles, double g, int precis
   size_t off = 0, items = 0;
   for (int t = 0; t < ntiles; ++t) {
     const zk_tile &d = tiles[t];
+    if (d.ny == 1) {  // 1D grids run as single contexts only
+      delete b;
+      return nullptr;
+    }
     zk_ctx *c = zk_create(d.nx, d.ny, d.Lx, d.Ly, d.depth, g, d.M);
     if (!c || zk_set_option(c, ZK_OPT_PRECISION, precision) || zk_set_option(c, ZK_OPT_CHECK, 0)) {
       if (c) zk_destroy(c);
@@ -371,6 +485,11 @@ zk_batch *zk_batch_create(int ntiles, const zk_tile *tiles, double g, int precis
   b->items_cap = items;
   b->off_items = off;
   off = align_up(off + items * sizeof(BatchItem));
+  b->units_cap = items * kUnitsPerItem;
+  b->off_units = off;
+  off = align_up(off + b->units_cap * sizeof(PUnit));
+  b->off_ctr = off;
+  off = align_up(off + (size_t)(kCtrDone + ntiles) * sizeof(uint32_t));
   b->total = off;
   b->eta.assign(ntiles, nullptr);
   b->psi.assign(ntiles, nullptr);
@@ -421,6 +540,12 @@ int zk_batch_set_option(zk_batch *b, int key, double value) {
     b->ready = false;
     return ZK_OK;
   }
+  if (key == ZK_BATCH_OPT_PERSISTENT) {
+    b->persistent = value != 0.0;
+    b->tune.clear();  // shapes are re-chosen among those the form hosts
+    b->ready = false;
+    return ZK_OK;
+  }
   return fail(b, ZK_EINVAL, "unknown batch option");
 }
 
@@ -430,11 +555,20 @@ int zk_batch_step(zk_batch *b, double dt, int nsteps) {
   if (!std::isfinite(dt) || nsteps < 0) return fail(b, ZK_EINVAL, "dt must be finite and nsteps >= 0");
   if (nsteps == 0) return ZK_OK;
   if ((rc = prepare(b, dt))) return rc;
+  uint32_t *ctr = reinterpret_cast<uint32_t *>(b->ws + b->off_ctr);
+  if (b->persistent) HIP_TRY(b, launch_persist_clear_flag(ctr, b->stream));
   if ((rc = run_seg(b, 0))) return rc;
   for (int i = 0; i + 1 < nsteps; ++i)
     if ((rc = run_seg(b, 1 + (i & 1)))) return rc;
   if ((rc = run_seg(b, 3 + ((nsteps - 1) & 1)))) return rc;
-  return run_seg(b, 5 + (nsteps & 1));
+  if ((rc = run_seg(b, 5 + (nsteps & 1)))) return rc;
+  if (b->persistent) {  // a dependency wait that ran out leaves the flag set
+    uint32_t flag = 0;
+    HIP_TRY(b, hipMemcpyAsync(&flag, ctr + 1, sizeof(flag), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(b, hipStreamSynchronize(b->stream));
+    if (flag) return fail(b, ZK_EDEVICE, "persistent batch: a dependency wait ran out");
+  }
+  return ZK_OK;
 }
 
 int zk_batch_autotune(zk_batch *b, double dt, int reps) {

@@ -75,7 +75,49 @@ __host__ __device__ constexpr double sin48(int j) {
   return tab[j];
 }
 
-// a * exp(DIR * 2 pi i * M / NN) for compile-time M, NN (48 % NN == 0)
+// cos and sin of 2 pi m / n for any compile-time m, n: the angle is reduced
+// exactly in integers to [0, pi/4] (octant symmetries), then a Taylor series
+// in long double, far below double rounding at |x| <= pi/4.
+constexpr long double kPiL = 3.14159265358979323846264338327950288L;
+constexpr long double taylor_cos(long double x) {
+  long double t = 1.0L, s = 1.0L;
+  for (int k = 1; k < 12; ++k) {
+    t *= -x * x / ((2 * k - 1) * (2 * k));
+    s += t;
+  }
+  return s;
+}
+constexpr long double taylor_sin(long double x) {
+  long double t = x, s = x;
+  for (int k = 1; k < 12; ++k) {
+    t *= -x * x / ((2 * k) * (2 * k + 1));
+    s += t;
+  }
+  return s;
+}
+// (cos, sin) of 2 pi m / n, 0 <= m < n: with 8m = o n + r (octant o, 0 <= r < n),
+// the angle is o pi/4 + (pi/4) r / n.
+constexpr double cos_sin_frac(int m, int n, bool want_sin) {
+  const long long a = 8LL * m;
+  const int o = (int)(a / n);
+  const long double x = kPiL / 4 * (long double)(a % n) / n;  // in [0, pi/4)
+  const long double c = taylor_cos(x), sn = taylor_sin(x);
+  const long double h = 0.70710678118654752440084436210484903928L;  // cos(pi/4)
+  long double cc = 0, ss = 0;
+  switch (o) {  // rotate (c, sn) by o pi/4
+    case 0: cc = c; ss = sn; break;
+    case 1: cc = h * (c - sn); ss = h * (c + sn); break;
+    case 2: cc = -sn; ss = c; break;
+    case 3: cc = -h * (c + sn); ss = h * (c - sn); break;
+    case 4: cc = -c; ss = -sn; break;
+    case 5: cc = -h * (c - sn); ss = -h * (c + sn); break;
+    case 6: cc = sn; ss = -c; break;
+    default: cc = h * (c + sn); ss = -h * (c - sn); break;
+  }
+  return (double)(want_sin ? ss : cc);
+}
+
+// a * exp(DIR * 2 pi i * M / NN) for compile-time M, NN
 template <int M, int NN, int DIR, typename R>
 __device__ __forceinline__ cpx<R> twc(cpx<R> a) {
   constexpr int mm = ((M % NN) + NN) % NN;
@@ -87,11 +129,16 @@ __device__ __forceinline__ cpx<R> twc(cpx<R> a) {
     return {-a.x, -a.y};
   } else if constexpr (4 * mm == 3 * NN) {
     return mul_diri<-DIR>(a);
-  } else {
-    static_assert(48 % NN == 0, "twiddle base must divide 48");
+  } else if constexpr (48 % NN == 0) {
     constexpr int j = mm * (48 / NN);
     constexpr double cd = cos48(j);
     constexpr double sd = DIR * sin48(j);
+    const R c = (R)cd;
+    const R s = (R)sd;
+    return {a.x * c - a.y * s, a.x * s + a.y * c};
+  } else {  // radix-9 and radix-18 steps
+    constexpr double cd = cos_sin_frac(mm, NN, false);
+    constexpr double sd = DIR * cos_sin_frac(mm, NN, true);
     const R c = (R)cd;
     const R s = (R)sd;
     return {a.x * c - a.y * s, a.x * s + a.y * c};
@@ -215,8 +262,12 @@ __host__ __device__ constexpr int lds_len(int N) { return N; }
 // host stores them at Ns_p - E + (r-1) Ns_p + k (N - E entries), so a lane's
 // consecutive k read adjacent words instead of a stride of r step_p.  Each
 // transform length keeps one table per candidate E, slot tw_slot(E).
+// Slots: E in {2, 3, 9} -> 0, {4, 6, 18} -> 1, {8, 12} -> 2 (a length uses at
+// most one E of each group).
 constexpr int kTwSlots = 3;
-__host__ __device__ constexpr int tw_slot(int E) { return (E == 2 || E == 3) ? 0 : ((E == 4 || E == 6) ? 1 : 2); }
+__host__ __device__ constexpr int tw_slot(int E) {
+  return (E == 2 || E == 3 || E == 9) ? 0 : ((E == 4 || E == 6 || E == 18) ? 1 : 2);
+}
 
 // Last pass of a team FFT of N = E T points: radix R, NB = N / R butterflies,
 // IT per thread.  Butterfly j = t + T it of that pass owns the elements

@@ -220,14 +220,14 @@ __device__ __forceinline__ float2 pow2_scale(float m) {
 // otherwise a base transform of N = n points, retained r < E/2 and r >= E/2.
 // In both cases the band has K = (E/3 or E/2) * T = n/2 positive modes, and
 // slot "first negative, t = 0" is the Nyquist mode (never stored).
-template <int T, int E>
+template <int T, int E, int BSZ = 0, bool PAD = (E % 3 == 0)>
 struct Shape {
-  static constexpr bool PADDED = (E % 3 == 0);
+  static constexpr bool PADDED = PAD;
   static constexpr int N = T * E;
   static constexpr int KR = PADDED ? E / 3 : E / 2;    // positive slots
   static constexpr int NEG0 = PADDED ? 2 * E / 3 : E / 2;  // first negative slot
   static constexpr int QB = PADDED ? 2 * E / 3 : E;    // base-band elements per thread
-  static constexpr int BS = T > 256 ? T : 256;          // threads per block
+  static constexpr int BS = BSZ ? BSZ : (T > 256 ? T : 256);  // threads per block (default max(T, 256))
   static constexpr int TPB = BS / T;                   // teams per block
   static constexpr int L = lds_len(N);
   // two LDS buffers per team when they fit comfortably, else one
@@ -323,6 +323,20 @@ __device__ __forceinline__ void stage_twiddles(cpx<R> *dst, const cpx<R> *src) {
   }
 }
 
+// LDS of a row or column body: the transform buffers, the staged twiddle
+// table (when it fits; else a 16-byte stub) and the reduction slots, in that order.  The
+// standalone kernels declare them as static arrays; the persistent batch
+// kernel (DYN) carves them from one dynamic region that every team shape it
+// hosts shares, sized on the host from these functions.
+template <typename real, int T, int E, int BSZ = 0, bool PAD = (E % 3 == 0)>
+struct BodyLds {
+  using S = Shape<T, E, BSZ, PAD>;
+  static constexpr int TWN = S::template tw_in_lds<real>() ? S::N : 16 / (int)sizeof(cpx<real>);
+  static constexpr int BUF = S::TPB * S::template nbuf<real>() * S::L;  // row and plain column bodies
+  static constexpr int RED = 2 * (S::BS / 64);
+  static constexpr int bytes() { return (BUF + TWN) * (int)sizeof(cpx<real>) + RED * (int)sizeof(float); }
+};
+
 // One entry of a batched launch: the tile's argument record and the
 // program (row pass) or task (column pass) its blocks run.
 struct BatchItem {
@@ -332,9 +346,9 @@ struct BatchItem {
 
 // Row pass body: TPB teams per block, one row each (block blk of the
 // pass), all running program progs[prog].
-template <typename real, int T, int E>
+template <typename real, int T, int E, bool DYN = false, int BSZ = 0, bool PAD = (E % 3 == 0)>
 __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int blk, const RowProg *progs0) {
-  using S = Shape<T, E>;
+  using S = Shape<T, E, BSZ, PAD>;
   constexpr int N = S::N, L = S::L, NB = S::template nbuf<real>();
   constexpr bool TWL = S::template tw_in_lds<real>();
   // A single grid passes its program table as a kernel argument, so the
@@ -347,13 +361,29 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   } else {
     pg = uniform_load(a.progs + prog);
   }
-  __shared__ cpx<real> smem[S::TPB * NB * L];
-  __shared__ __attribute__((aligned(16))) cpx<real> twl[TWL ? N : 1];
-  __shared__ float red[2 * (S::BS / 64)];
+  using LD = BodyLds<real, T, E, BSZ, PAD>;
+  cpx<real> *smem, *twl;
+  float *red;
+  if constexpr (DYN) {
+    extern __shared__ __attribute__((aligned(16))) char zk_dyn_lds[];
+    smem = reinterpret_cast<cpx<real> *>(zk_dyn_lds);
+    twl = smem + LD::BUF;
+    red = reinterpret_cast<float *>(twl + LD::TWN);
+  } else {
+    __shared__ cpx<real> s_smem[LD::BUF];
+    __shared__ __attribute__((aligned(16))) cpx<real> s_twl[LD::TWN];
+    __shared__ float s_red[LD::RED];
+    smem = s_smem;
+    twl = s_twl;
+    red = s_red;
+  }
   const int team = threadIdx.x / T;
   const int t = threadIdx.x % T;
   // rows y and y+1 share 128-byte lines of the tiled fields
   const int row = (S::TPB == 1 ? xcd_unit(blk, a.rows, 2) : blk) * S::TPB + team;
+  // A 1D grid has one row: the block's other teams run the transforms on
+  // zeros (they share its barriers) and touch no field.
+  const bool in_row = row < a.rows;
   cpx<real> *b0 = smem + team * NB * L;
   cpx<real> *b1 = b0 + (NB - 1) * L;
   const cpx<real> *tw = a.tw + tw_slot(E) * N;  // this shape's pass-ordered table
@@ -422,7 +452,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
             const bool pos = p < S::KR * T, neg = p > S::NEG0 * T;  // kept band, upper half by symmetry
             xa[it][r] = {(real)0, (real)0};
             xb[it][r] = {(real)0, (real)0};
-            if (live(it) && (pos || neg)) {
+            if (in_row && live(it) && (pos || neg)) {
               const int idx = mix_index<real>(pos ? p : N - p, row, a.rows);
               xa[it][r] = gload(Fa, idx);
               if (has_b) xb[it][r] = gload(Fb, idx);
@@ -477,8 +507,8 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         const long long off = (long long)row * a.nx;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          z[e].x = (real)gload1(pa, off + t + T * e);
-          z[e].y = op.fb >= 0 ? (real)gload1(pb, off + t + T * e) : (real)0;
+          z[e].x = in_row ? (real)gload1(pa, off + t + T * e) : (real)0;
+          z[e].y = in_row && op.fb >= 0 ? (real)gload1(pb, off + t + T * e) : (real)0;
         }
         break;
       }
@@ -570,8 +600,8 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
           const cpx<real> zk = res[lpad(k)];
           const cpx<real> zm = res[lpad(k == 0 ? 0 : N - k)];
           const int idx = mix_index<real>(k, row, a.rows);
-          gstore(Fa, idx, cpx<real>{hx * (zk.x + zm.x), hx * (zk.y - zm.y)});
-          if (op.fb >= 0) gstore(Fb, idx, cpx<real>{hy * (zk.y + zm.y), -hy * (zk.x - zm.x)});
+          if (in_row) gstore(Fa, idx, cpx<real>{hx * (zk.x + zm.x), hx * (zk.y - zm.y)});
+          if (in_row && op.fb >= 0) gstore(Fb, idx, cpx<real>{hy * (zk.y + zm.y), -hy * (zk.x - zm.x)});
         }
         break;
       }
@@ -581,7 +611,8 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         const long long off = ((long long)(op.fb > 0 ? op.fb : 0) * a.rows + row) * a.nx;
         with_any(op.a, [&](auto X) {
 #pragma unroll
-          for (int e = 0; e < E; ++e) gstore1(po, off + t + T * e, (double)reg(X, e));
+          for (int e = 0; e < E; ++e)
+            if (in_row) gstore1(po, off + t + T * e, (double)reg(X, e));
         });
         break;
       }
@@ -603,7 +634,7 @@ __device__ __forceinline__ double lift_factor(uint32_t s, double kk, int col, in
                                            const double *layer_y) {
   double f = 1.0;
   if (s & SYM_COUPLE) {
-    const int my = b < ny / 2 ? b : b - ny;
+    const int my = (b < ny / 2 || ny == 1) ? b : b - ny;  // a 1D grid's one row is ky = 0
     const double rx = 4.0 * col / nx, ry = 4.0 * (my < 0 ? -my : my) / ny;  // |k_a| / (kNyq_a / 2)
     const double rx2 = rx * rx, ry2 = ry * ry, rx4 = rx2 * rx2, ry4 = ry2 * ry2;
     f *= exp(-(rx4 * rx4) - (ry4 * ry4));
@@ -657,15 +688,17 @@ __device__ __forceinline__ cpx<double> symval(uint32_t s, double kk, double g0, 
 // term lists runs them side by side instead of in sequence.  Thread t owns
 // base-band rows b = t + T q, q < QB (q = KR at t = 0 is the ky Nyquist row,
 // kept zero).
-template <int T, int FT>
+template <int T, int FT, int BSZ = 0>
 struct ColBlock {
-  static constexpr int BS = FT == 1 ? (T > 256 ? T : 256) : FT * T;  // threads per block
+  static constexpr int BS = FT == 1 ? (BSZ ? BSZ : (T > 256 ? T : 256)) : FT * T;  // threads per block
   static constexpr int TPB = FT == 1 ? BS / T : 1;                    // columns per block
 };
-template <typename real, int T, int E, bool LIFTSYM = false, int FT = 1>
+template <typename real, int T, int E, bool LIFTSYM = false, int FT = 1, bool DYN = false, int BSZ = 0,
+          bool PAD = (E % 3 == 0)>
 __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index, int blk, const ColTask *tasks0) {
-  using S = Shape<T, E>;
-  using CB = ColBlock<T, FT>;
+  static_assert(BSZ == 0 || FT == 1, "a block size is set for plain column teams only");
+  using S = Shape<T, E, BSZ, PAD>;
+  using CB = ColBlock<T, FT, BSZ>;
   static_assert(FT == 1 || (T >= 64 && FT * T <= 1024), "fold teams: whole wavefronts, one block");
   constexpr int N = S::N, L = S::L, QB = S::QB;
   constexpr int NB = FT == 1 ? S::template nbuf<real>() : 2;
@@ -678,10 +711,28 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   } else {
     task = uniform_load(a.tasks + task_index);
   }
-  __shared__ cpx<real> smem[(FT == 1 ? CB::TPB : FT) * NB * L];
-  __shared__ __attribute__((aligned(16))) cpx<real> twl[TWL ? N : 1];
-  __shared__ float red[2 * (CB::BS / 64)];
-  __shared__ cpx<double> xs[FT == 1 ? 1 : FT * QB * T];  // fold teams: each team's part of X
+  static_assert(!DYN || FT == 1, "the persistent kernel hosts plain column teams only");
+  constexpr int TWN = TWL ? N : 16 / (int)sizeof(cpx<real>);
+  cpx<real> *smem, *twl;
+  float *red;
+  cpx<double> *xs;
+  if constexpr (DYN) {
+    using LD = BodyLds<real, T, E, BSZ, PAD>;
+    extern __shared__ __attribute__((aligned(16))) char zk_dyn_lds[];
+    smem = reinterpret_cast<cpx<real> *>(zk_dyn_lds);
+    twl = smem + LD::BUF;
+    red = reinterpret_cast<float *>(twl + LD::TWN);
+    xs = nullptr;
+  } else {
+    __shared__ cpx<real> s_smem[(FT == 1 ? CB::TPB : FT) * NB * L];
+    __shared__ __attribute__((aligned(16))) cpx<real> s_twl[TWN];
+    __shared__ float s_red[2 * (CB::BS / 64)];
+    __shared__ cpx<double> s_xs[FT == 1 ? 1 : FT * QB * T];  // fold teams: each team's part of X
+    smem = s_smem;
+    twl = s_twl;
+    red = s_red;
+    xs = s_xs;
+  }
   // fold teams are whole wavefronts: the team index is wave-uniform (scalar)
   const int team = FT == 1 ? (int)(threadIdx.x / T) : __builtin_amdgcn_readfirstlane((int)(threadIdx.x / T));
   const int t = threadIdx.x % T;
@@ -961,7 +1012,7 @@ struct PhysArgs {
 __device__ __forceinline__ BatchItem item_of(const BatchItem *items, int tile0, int first0) {
   return items ? items[blockIdx.y] : BatchItem{tile0, first0 + (int)blockIdx.y};
 }
-template <typename real, int T, int E>
+template <typename real, int T, int E, bool PAD = (E % 3 == 0)>
 __global__ __launch_bounds__(T > 256 ? T : 256) void row_kernel_batch(const RowArgs<real> *__restrict__ args,
                                                         const BatchItem *__restrict__ items, int tile0, int first0,
                                                         const void *sched0, PhysArgs ph) {
@@ -974,17 +1025,17 @@ __global__ __launch_bounds__(T > 256 ? T : 256) void row_kernel_batch(const RowA
     a.pout0 = ph.out0;
     a.pout1 = ph.out1;
   }
-  row_body<real, T, E>(a, it.index, blockIdx.x, static_cast<const RowProg *>(sched0));
+  row_body<real, T, E, false, 0, PAD>(a, it.index, blockIdx.x, static_cast<const RowProg *>(sched0));
 }
 // LIFTSYM: the variant that applies ColOut.lift_sym (the bulk velocity
 // lift's column launches); the plain passes never carry its exponentials.
-template <typename real, int T, int E, bool LIFTSYM = false>
+template <typename real, int T, int E, bool LIFTSYM = false, bool PAD = (E % 3 == 0)>
 __global__ __launch_bounds__(T > 256 ? T : 256) void col_kernel_batch(const ColArgs<real> *__restrict__ args,
                                                         const BatchItem *__restrict__ items, int tile0, int first0,
                                                         const void *sched0, PhysArgs) {
   const BatchItem it = item_of(items, tile0, first0);
   const ColArgs<real> a = args[it.tile];
-  col_body<real, T, E, LIFTSYM>(a, it.index, blockIdx.x, static_cast<const ColTask *>(sched0));
+  col_body<real, T, E, LIFTSYM, 1, false, 0, PAD>(a, it.index, blockIdx.x, static_cast<const ColTask *>(sched0));
 }
 // Fold teams: kMaxFolds teams of T threads per block, one column per block
 // (tasks whose folds and terms run side by side).
@@ -997,45 +1048,126 @@ __global__ __launch_bounds__(kMaxFolds * T) void col_kernel_folds(const ColArgs<
   col_body<real, T, E, false, kMaxFolds>(a, it.index, blockIdx.x, static_cast<const ColTask *>(sched0));
 }
 
-// Team shapes (T, E) compiled for the batched kernels: T in {32, 64, 128,
-// 256} threads with E in {2, 3, 4, 6, 8, 12}, and T = 512 (E in {2, 3, 4, 6})
-// and 1024 (E in {2, 3}) as blocks of their own, so that each power-of-two
-// length n in [64, 2048] has two to four candidate shapes for its padded
-// (3n/2) and base (n) transforms; the autotuner picks among them.  A block
-// has max(256, T) threads.  These return the kernel for (T, E), or nullptr if
-// that shape is not built.
+// Column pass of a 1D grid (ny = 1): a kx column holds the single ky = 0
+// element, so a fold is that element (a one-point transform, no truncation
+// in y and no ky Nyquist row) and a lift writes it back; one thread per
+// column, the same task records as col_body.
+template <typename real, bool LIFTSYM>
+__device__ __forceinline__ void col_body_1d(const ColArgs<real> &a, int task_index, int col) {
+  const ColTask task = uniform_load(a.tasks + task_index);
+  if (col >= a.nx / 2) return;  // no barriers in this body
+  const double *e = reinterpret_cast<const double *>(a.sym) + 4LL * base_index(col, 0, 1);
+  const double kk = gload1(e, 0), g0 = gload1(e, 1), tp = gload1(e, 2);
+  auto sym = [&](uint32_t s) { return symval(s, kk, g0, tp, col, 0, 0.0, a); };
+  auto cmac = [](cpx<double> &acc, cpx<double> x, cpx<double> sv) {
+    acc.x += x.x * sv.x - x.y * sv.y;
+    acc.y += x.x * sv.y + x.y * sv.x;
+  };
+  cpx<double> X = {0.0, 0.0};
+  for (int f = 0; f < kMaxFolds; ++f) {
+    if (task.fwd[f] < 0) break;
+    const cpx<real> w = gload(a.mix + (long long)task.fwd[f] * a.mix_stride, mix_index<real>(col, 0, a.rows));
+    cmac(X, cpx<double>{(double)w.x * task.fwd_coef[f], (double)w.y * task.fwd_coef[f]}, sym(task.fwd_sym[f]));
+  }
+  for (int o = 0; o < task.no; ++o) {
+    const ColOut out = uniform_load(a.outs + task.o0 + o);
+    cpx<double> acc = {0.0, 0.0};
+    for (int i = 0; i < out.nt; ++i) {
+      const ColTerm tm = uniform_load(a.terms + out.t0 + i);
+      const cpx<double> src =
+          tm.src >= 0 ? gload(a.base + (long long)tm.src * a.base_stride, base_index(col, 0, 1)) : X;
+      cpx<double> sv = sym(tm.sym);
+      cmac(acc, src, cpx<double>{sv.x * tm.coef, sv.y * tm.coef});
+    }
+    if (out.dst_base >= 0) gstore(a.base + (long long)out.dst_base * a.base_stride, base_index(col, 0, 1), acc);
+    if (out.dst_mixed >= 0) {
+      double f = out.lift_coef;
+      if constexpr (LIFTSYM)
+        if (out.lift_sym) f *= lift_factor(out.lift_sym, kk, col, 0, a.nx, 1, a.depth, a.layer_y);
+      const cpx<real> w = {(real)(acc.x * f), (real)(acc.y * f)};
+      gstore(a.mix + (long long)out.dst_mixed * a.mix_stride, mix_index<real>(col, 0, a.rows), w);
+      gstore1(a.colmax, (long long)out.dst_mixed * (a.nx / 2) + col, fmaxf(fabsf((float)w.x), fabsf((float)w.y)));
+    }
+  }
+}
+template <typename real, bool LIFTSYM>
+__global__ __launch_bounds__(256) void col_kernel_1d(const ColArgs<real> *__restrict__ args, int rec, int first0) {
+  col_body_1d<real, LIFTSYM>(args[rec], first0 + (int)blockIdx.y, (int)(blockIdx.x * blockDim.x + threadIdx.x));
+}
+// Column pass of a 1D grid: grid.x covers the nx/2 columns with 256 threads
+// per block, grid.y the launch's tasks; args[rec] is the pass's record.
 template <typename real>
-const void *batch_row_kernel(int T, int E);
+hipError_t launch_col_1d(bool liftsym, dim3 grid, hipStream_t s, const ColArgs<real> *args, int rec, int first0) {
+  if (liftsym)
+    hipLaunchKernelGGL((col_kernel_1d<real, true>), grid, dim3(256), 0, s, args, rec, first0);
+  else
+    hipLaunchKernelGGL((col_kernel_1d<real, false>), grid, dim3(256), 0, s, args, rec, first0);
+  return hipGetLastError();
+}
+
+// Team shapes (T, E) compiled for the batched kernels.  Power-of-two axes
+// (n = 2^k in [64, 2048]): T in {32, 64, 128, 256} threads with E in
+// {2, 3, 4, 6, 8, 12}, and T = 512 (E in {2, 3, 4, 6}) and 1024 (E in {2, 3})
+// as blocks of their own, so each length has two to four candidates for its
+// padded (3n/2, E in {3, 6, 12}) and base (n, E in {2, 4, 8}) transforms;
+// the autotuner picks among them.  Axes with a factor 3 (n = 3 2^k in [96,
+// 1536]): the padded transform of 9 2^(k-1) points with E = 9 and the base
+// transform with E = 6, T in {16, ..., 256}.  `pad` tells a base transform
+// with E = 6 from a padded one.  A block has max(256, T) threads.  These
+// return the kernel for (T, E, pad), or nullptr if that shape is not built.
 template <typename real>
-const void *batch_col_kernel(int T, int E);
-template <>
-const void *batch_row_kernel<double>(int T, int E);
-template <>
-const void *batch_row_kernel<float>(int T, int E);
-template <>
-const void *batch_col_kernel<double>(int T, int E);
-template <>
-const void *batch_col_kernel<float>(int T, int E);
-// Launch the kernel of shape (T, E) (hipErrorInvalidValue if not built).
+const void *batch_row_kernel(int T, int E, bool pad);
 template <typename real>
-hipError_t launch_batch_row(int T, int E, dim3 grid, hipStream_t s, const RowArgs<real> *args, const BatchItem *items,
-                            int tile0, int first0, const void *sched0, PhysArgs ph);
+const void *batch_col_kernel(int T, int E, bool pad);
+template <>
+const void *batch_row_kernel<double>(int T, int E, bool pad);
+template <>
+const void *batch_row_kernel<float>(int T, int E, bool pad);
+template <>
+const void *batch_col_kernel<double>(int T, int E, bool pad);
+template <>
+const void *batch_col_kernel<float>(int T, int E, bool pad);
+// The default first-pass radix of an axis of n base points: the smallest
+// compiled one (n = 2^k: 3 padded, 2 base; n = 3 2^k: 9 padded, 6 base).
+inline int default_radix(int n, bool pad) { return n % 3 ? (pad ? 3 : 2) : (pad ? 9 : 6); }
+// The compiled first-pass radices of that axis's padded or base transform
+// (the autotuner's candidates): writes up to three into e, returns the count.
+inline int radix_candidates(int n, bool pad, int *e) {
+  if (n % 3 == 0) {
+    e[0] = pad ? 9 : 6;
+    return 1;
+  }
+  e[0] = pad ? 3 : 2;
+  e[1] = pad ? 6 : 4;
+  e[2] = pad ? 12 : 8;
+  return 3;
+}
+// Axis lengths the kernels are built for: 2^k in [64, 2048] and 3 2^k in [96, 1536].
+inline bool axis_len_ok(int n) {
+  const int m = n % 3 ? n : n / 3;
+  const bool pow2 = m > 0 && (m & (m - 1)) == 0;
+  return pow2 && (n % 3 ? (n >= 64 && n <= 2048) : (n >= 96 && n <= 1536));
+}
+// Launch the kernel of shape (T, E, pad) (hipErrorInvalidValue if not built).
 template <typename real>
-hipError_t launch_batch_col(int T, int E, dim3 grid, hipStream_t s, const ColArgs<real> *args, const BatchItem *items,
-                            int tile0, int first0, const void *sched0, PhysArgs ph);
+hipError_t launch_batch_row(int T, int E, bool pad, dim3 grid, hipStream_t s, const RowArgs<real> *args,
+                            const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph);
+template <typename real>
+hipError_t launch_batch_col(int T, int E, bool pad, dim3 grid, hipStream_t s, const ColArgs<real> *args,
+                            const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph);
 template <>
-hipError_t launch_batch_row<double>(int, int, dim3, hipStream_t, const RowArgs<double> *, const BatchItem *, int, int,
-                                   const void *, PhysArgs);
+hipError_t launch_batch_row<double>(int, int, bool, dim3, hipStream_t, const RowArgs<double> *, const BatchItem *, int,
+                                   int, const void *, PhysArgs);
 template <>
-hipError_t launch_batch_row<float>(int, int, dim3, hipStream_t, const RowArgs<float> *, const BatchItem *, int, int,
+hipError_t launch_batch_row<float>(int, int, bool, dim3, hipStream_t, const RowArgs<float> *, const BatchItem *, int, int,
                                   const void *, PhysArgs);
 template <>
-hipError_t launch_batch_col<double>(int, int, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *, int, int,
-                                   const void *, PhysArgs);
+hipError_t launch_batch_col<double>(int, int, bool, dim3, hipStream_t, const ColArgs<double> *, const BatchItem *, int,
+                                   int, const void *, PhysArgs);
 template <>
-hipError_t launch_batch_col<float>(int, int, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *, int, int,
+hipError_t launch_batch_col<float>(int, int, bool, dim3, hipStream_t, const ColArgs<float> *, const BatchItem *, int, int,
                                   const void *, PhysArgs);
-// The lift_sym variant of the base-length column kernel (E in {2, 4, 8}).
+// The lift_sym variant of the base-length column kernel (E in {2, 4, 8, 6}).
 template <typename real>
 hipError_t launch_batch_col_lift(int T, int E, dim3 grid, hipStream_t s, const ColArgs<real> *args,
                                  const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph);

@@ -56,8 +56,9 @@ class Builder {
  public:
   explicit Builder(const PlanParams &pp) : pp_(pp) {
     M = pp.M;
+    // a 1D grid (ny = 1) is not padded along y: its products have ky = 0 only
     const double N = (double)pp.nx * pp.ny;
-    const double Np = (1.5 * pp.nx) * (1.5 * pp.ny);
+    const double Np = (1.5 * pp.nx) * (pp.ny > 1 ? 1.5 * pp.ny : 1.0);
     inv_n = 1.0 / N;
     fold = N / Np;
   }
@@ -310,7 +311,7 @@ Plan build_plan(const PlanParams &pp, double dt) {
   // slopes), the W products divided by kref.  The factors are undone in the
   // product and fold coefficients.  kref = kNyq / 3, a fixed mid-band
   // wavenumber.
-  const double kref = std::min(M_PI * pp.nx / pp.Lx, M_PI * pp.ny / pp.Ly) / 3.0;
+  const double kref = (pp.ny > 1 ? std::min(M_PI * pp.nx / pp.Lx, M_PI * pp.ny / pp.Ly) : M_PI * pp.nx / pp.Lx) / 3.0;
   auto kpow = [&](int l) { return std::pow(kref, (double)l); };
 
   // ---- field ids -------------------------------------------------------------
@@ -789,7 +790,7 @@ Plan build_plan(const PlanParams &pp, double dt) {
   // base spectra of its terms and writes its stores and lifts.
   {
     const double rb = pp.real_bytes, cb = 2.0 * rb, K = pp.nx / 2;
-    const double rows_pad = 1.5 * pp.ny, rows_base = pp.ny;
+    const double rows_pad = pp.ny > 1 ? 1.5 * pp.ny : 1.0, rows_base = pp.ny;
     auto fft_flops = [](double n) { return 5.0 * n * std::log2(n); };
     auto annotate = [&](std::vector<Launch> &seq) {
       for (auto &l : seq) {

@@ -33,6 +33,7 @@ EXPORTS = ("zk_create", "zk_destroy", "zk_set_option", "zk_workspace_bytes", "zk
            "zk_batch_set_option", "zk_batch_step", "zk_batch_autotune", "zk_batch_tuning", "zk_batch_stats",
            "zk_batch_last_error")
 ZK_BATCH_OPT_GRAPH = 1
+ZK_BATCH_OPT_PERSISTENT = 2
 ZK_STATIC_WS_BYTES = 64 << 20  # size of the library's fixed device scratch (zk.h)
 
 
@@ -505,7 +506,7 @@ class Batch:
     deep) and M; fields are registered once (contiguous float64 device
     tensors [ny, nx]) and stepped in place."""
 
-    def __init__(self, tiles, g=9.81, precision=32, device="cuda", graph=True):
+    def __init__(self, tiles, g=9.81, precision=32, device="cuda", graph=True, persistent=False):
         import math
 
         import torch
@@ -522,6 +523,7 @@ class Batch:
         if not self.b:
             raise ZKError(ZK_EINVAL, "zk_batch_create rejected the tiles")
         self._check(lib().zk_batch_set_option(self.b, ZK_BATCH_OPT_GRAPH, 1.0 if graph else 0.0))
+        self._check(lib().zk_batch_set_option(self.b, ZK_BATCH_OPT_PERSISTENT, 1.0 if persistent else 0.0))
         nbytes = int(lib().zk_batch_workspace_bytes(self.b))
         with torch.cuda.device(self.device):
             self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)

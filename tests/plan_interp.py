@@ -63,12 +63,12 @@ class Interp:
         self.dt = None
         kx = 2 * np.pi / Lx * np.arange(self.K)
         b = np.arange(ny)
-        my = np.where(b < ny // 2, b, b - ny)
+        my = np.where((b < ny // 2) | (ny == 1), b, b - ny)  # a 1D grid's one row is ky = 0
         self.kx, self.my = kx[None, :], my[:, None]
         self.ky = 2 * np.pi / Ly * self.my
         self.kk = np.sqrt(self.kx ** 2 + self.ky ** 2)
         self.th = np.tanh(self.kk * self.depth) if self.depth > 0 else np.ones_like(self.kk)
-        kc = 2.0 / 3.0 * min(np.pi * nx / Lx, np.pi * ny / Ly)
+        kc = 2.0 / 3.0 * (min(np.pi * nx / Lx, np.pi * ny / Ly) if ny > 1 else np.pi * nx / Lx)
         self.taper_sym = np.exp(-((self.kk / kc) ** 8))
 
         def f1(m, n):
@@ -215,7 +215,7 @@ class Interp:
                 V = np.fft.fft(self.mix[fwd][:rows, :], axis=0)
                 Xf = V[idx, :] * fcoef * self.sym(fsym)
                 X = Xf if X is None else X + Xf
-            if X is not None:
+            if X is not None and ny > 1:  # a 1D grid (ny = 1) has no ky Nyquist row
                 X[ny // 2, :] = 0
             for oi in range(o0, o0 + no):
                 dst_b, dst_m, t0, nt, lc, lsym = P["outs"][oi]
@@ -223,13 +223,14 @@ class Interp:
                 for src, s, coef in P["terms"][t0:t0 + nt]:
                     v = X if src < 0 else self.base[src]
                     acc = acc + coef * self.sym(s) * v
-                acc[ny // 2, :] = 0
+                if ny > 1:
+                    acc[ny // 2, :] = 0
                 if dst_b >= 0:
                     self.base[dst_b] = acc
                 if dst_m >= 0:
                     Z = np.zeros((rows, self.K), complex)
                     Z[idx, :] = acc * lc * (self.sym(lsym).real if lsym else 1.0)
-                    if pad:
+                    if pad and ny > 1:
                         Z[ny // 2 + (rows - ny), :] = 0  # the Nyquist slot mapped by idx is zero anyway
                     z = np.fft.ifft(Z, axis=0) * rows
                     self._mix_put(dst_m, rows, z)

@@ -12,7 +12,8 @@ import numpy as np
 import pytest
 
 SHAPES = ([(T, E) for T in (32, 64, 128, 256) for E in (2, 3, 4, 6, 8, 12)] + [(512, E) for E in (2, 3, 4, 6)]
-          + [(1024, 2), (1024, 3)])
+          + [(1024, 2), (1024, 3)] + [(T, E) for T in (16, 32, 64, 128, 256) for E in (6, 9)])
+SHAPES = sorted(set(SHAPES))
 
 
 def later_radix(T, p):

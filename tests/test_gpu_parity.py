@@ -62,6 +62,57 @@ def test_single_mode_flat_surface(torch):
         assert np.max(np.abs(G - k * math.tanh(k * h) * psi)) < 1e-11 * k
 
 
+@pytest.mark.parametrize("M", [2, 3, 5])
+@pytest.mark.parametrize("shape", [(96, 96), (64, 384), (384, 64), (128, 192), (64, 1536)])
+def test_non_power_of_two_grids(torch, M, shape):
+    """Axes of 3 2^k points (padded transforms of 9 2^(k-1) points with a
+    radix-9 first pass, base transforms with radix 6, teams down to 16
+    threads): G psi, the RHS and two RK4 steps at the FP64 bar, random data
+    filling the band, finite depth."""
+    ny, nx = shape
+    Lx, Ly, h = 2.0, 2.0 * ny / nx, 0.6
+    kmax = math.hypot(math.pi * nx / Lx, math.pi * ny / Ly)
+    eta, psi = random_band_fields(nx, ny, 70 + M, min(nx, ny) // 2 - 1, amplitude=0.1 / kmax)
+    s = solver(torch, nx, ny, Lx, Ly, h, M)
+    print(" ", s.team_shapes(), flush=True)
+    m = HOSModel(Grid(nx, ny, Lx, Ly, h), M)
+    e, p = dev(torch, eta), dev(torch, psi)
+    assert rel(host(s.dtn(e, p)), m.dtn(eta, psi)) < 1e-10
+    a, b = s.rhs(e, p)
+    a0, b0 = m.rhs(eta, psi)
+    assert rel(host(a), a0) < 1e-10 and rel(host(b), b0) < 1e-10
+    s.step(e, p, 0.002, 2)
+    e0, p0 = m.step(eta, psi, 0.002, 2)
+    assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
+
+
+def test_non_power_of_two_fp32_walls_and_lift(torch):
+    """A 3 2^k grid in the FP32 form (2e-5 per RHS against the FP64
+    oracle), with reflecting walls (its doubled axes 192 and 768 are 3 2^k
+    too; 1e-10), and the depth lift on it (1e-10)."""
+    from oracle.hos import ReflectingModel
+
+    nx, ny, L, h, M = 96, 384, 2.0, 0.8, 3
+    kmax = math.hypot(math.pi * nx / L, math.pi * ny / (4 * L))
+    eta, psi = random_band_fields(nx, ny, 81, nx // 2 - 1, amplitude=0.1 / kmax)
+    m = HOSModel(Grid(nx, ny, L, 4 * L, h), M)
+    s32 = solver(torch, nx, ny, L, 4 * L, h, M, precision=32)
+    a, b = s32.rhs(dev(torch, eta), dev(torch, psi))
+    a0, b0 = m.rhs(eta, psi)
+    assert rel(host(a), a0) < 2e-5 and rel(host(b), b0) < 2e-5
+    sw = solver(torch, nx, ny, L, 4 * L, h, M, boundary="reflect")
+    e, p = dev(torch, eta), dev(torch, psi)
+    sw.step(e, p, 0.002, 2)
+    e0, p0 = ReflectingModel(nx, ny, L, 4 * L, h, M).step(eta, psi, 0.002, 2)
+    assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
+    s64 = solver(torch, nx, ny, L, 4 * L, h, M)
+    ys = [0.0, 0.3]
+    uvw = host(s64.depth_velocity(dev(torch, eta), dev(torch, psi), ys))
+    ref = m.depth_velocity(eta, psi, ys)
+    for i in range(len(ys)):
+        assert rel(uvw[i], ref[i]) < 1e-10
+
+
 @pytest.mark.parametrize("M", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("shape", [(64, 64), (128, 64), (64, 256)])
 def test_dtn_rhs_parity_small(torch, M, shape):
@@ -549,3 +600,78 @@ def test_fp32_form_of_ifab2_inverse_and_depth_lift(torch):
         err = np.max(np.abs(uvw[i] - ref[i])) / np.max(np.abs(ref[i]))
         print(f"  layer y = {ys[i]}: rel err {err:.3e}", flush=True)
         assert err < 2e-5
+
+
+@pytest.mark.parametrize("nx,M", [(64, 2), (256, 3), (384, 5), (2048, 4)])
+def test_1d_grid_parity(torch, nx, M):
+    """A 1D grid (ny = 1: one row, columns of one element, no padding along
+    y): G psi, the RHS, two RK4 steps, one IF-AB2 step, H and the depth lift
+    at the FP64 bar against the oracle."""
+    L, h = 3.0, 0.7
+    kmax = math.pi * nx / L
+    eta, psi = random_band_fields(nx, 1, 90 + M, nx // 2 - 1, amplitude=0.1 / kmax)
+    m = HOSModel(Grid(nx, 1, L, 1.0, h), M)
+    s = solver(torch, nx, 1, L, 1.0, h, M)
+    e, p = dev(torch, eta), dev(torch, psi)
+    assert rel(host(s.dtn(e, p)), m.dtn(eta, psi)) < 1e-10
+    a, b = s.rhs(e, p)
+    a0, b0 = m.rhs(eta, psi)
+    assert rel(host(a), a0) < 1e-10 and rel(host(b), b0) < 1e-10
+    assert abs(s.hamiltonian(e, p) / m.hamiltonian(eta, psi) - 1) < 1e-12
+    ys = [0.0, 0.2]
+    uvw = host(s.depth_velocity(e, p, ys))
+    ref = m.depth_velocity(eta, psi, ys)
+    for i in range(len(ys)):
+        assert rel(uvw[i], ref[i]) < 1e-10
+    s.step(e, p, 0.002, 2)
+    e0, p0 = m.step(eta, psi, 0.002, 2)
+    assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
+    si = solver(torch, nx, 1, L, 1.0, h, M, integrator="ifab2")
+    e, p = dev(torch, eta), dev(torch, psi)
+    si.step(e, p, 0.004, 1)
+    e0, p0 = m.step_ifab2(eta, psi, 0.004, 1)
+    assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
+
+
+def _stokes_regimes():
+    import os
+
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "stokes_regimes.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                ka, kh, per = line.split()
+                rows.append((float(ka), float(kh)))
+    return rows
+
+
+@pytest.mark.parametrize("ka,kh", _stokes_regimes())
+def test_1d_stokes_regimes_through_c_abi(torch, ka, kh):
+    """The paper's Stokes-wave regimes (Sec. 8) on the GPU, 1D periodic
+    domain of length 2 pi, 64 points, order 3, eps = 1, no state filter, RK4
+    over 1.5 linear periods: the measured fundamental frequency carries the
+    third-order Stokes shift omega^2 = g k tanh(kh)(1 + delta) to within 5%
+    of the shift, and the final state equals the oracle's at the FP64 bar."""
+    nx, k, g0, nst = 64, 1.0, 9.81, 120
+    sg = math.tanh(kh)
+    w0 = math.sqrt(g0 * k * sg)
+    x = np.arange(nx) * TWO_PI / nx
+    a2 = k * ka * ka * (3 - sg * sg) / (4 * sg ** 3)
+    eta = (ka * np.cos(x) + a2 * np.cos(2 * x))[None, :]
+    b2 = 3 / 8 * ka * ka * w0 * math.cosh(2 * kh) / math.sinh(kh) ** 4 + ka * ka * w0 / 2
+    psi = ((ka * w0 / (k * sg)) * np.sin(x) + b2 * np.sin(2 * x))[None, :]
+    dt = 1.5 * TWO_PI / w0 / nst
+    s = solver(torch, nx, 1, TWO_PI, 1.0, kh, 3, filt=False)
+    e, p = dev(torch, eta), dev(torch, psi)
+    ph = [np.angle(np.fft.rfft(eta[0])[1])]
+    for _ in range(nst):
+        s.step(e, p, dt, 1)
+        ph.append(np.angle(np.fft.rfft(host(e)[0])[1]))
+    w = -np.polyfit(np.arange(nst + 1) * dt, np.unwrap(ph), 1)[0] / w0 - 1
+    delta = ka * ka * (9 - 10 * sg ** 2 + 9 * sg ** 4) / (8 * sg ** 4)
+    shift = math.sqrt(1 + delta) - 1
+    print(f"  ka {ka} kh {kh}: frequency shift {w:.6e} (third-order Stokes {shift:.6e})", flush=True)
+    assert abs(w - shift) < 0.05 * shift
+    m = HOSModel(Grid(nx, 1, TWO_PI, 1.0, kh), 3, filt=False)
+    e0, p0 = m.step(eta, psi, dt, nst)
+    assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10

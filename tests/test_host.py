@@ -22,7 +22,7 @@ def rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
-@pytest.mark.parametrize("nx,ny", [(64, 64), (128, 64), (512, 512), (2048, 2048)])
+@pytest.mark.parametrize("nx,ny", [(64, 64), (128, 64), (512, 512), (2048, 2048), (96, 96), (384, 64), (1536, 192)])
 @pytest.mark.parametrize("M", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_plan_builds_and_validates(nx, ny, M):
     p = load_plan(nx, ny, M)
@@ -48,6 +48,23 @@ def test_schedule_algebra_matches_oracle_jonswap(M):
     assert abs(I.hamiltonian(eta, psi) / m.hamiltonian(eta, psi) - 1) < 1e-13
     s, t = I.step(eta, psi, 0.01, 3)
     s0, t0 = m.step(eta, psi, 0.01, 3)
+    assert rel(s, s0) < 1e-13 and rel(t, t0) < 1e-13
+
+
+@pytest.mark.parametrize("M", [3, 5])
+def test_schedule_algebra_non_power_of_two_grid(M):
+    """Axes of 3 2^k points (96 x 192: padded lengths 144 and 288): the
+    schedule executed literally equals the oracle's G psi, RHS and steps."""
+    nx, ny = 96, 192
+    eta, psi = random_band_fields(nx, ny, 11, nx // 2 - 1, amplitude=0.02)
+    I = Interp(nx, ny, 3.0, 6.0, 1.2, 9.81, M)
+    m = HOSModel(Grid(nx, ny, 3.0, 6.0, 1.2), M)
+    assert rel(I.dtn(eta, psi), m.dtn(eta, psi)) < 1e-13
+    a, b = I.rhs(eta, psi)
+    a0, b0 = m.rhs(eta, psi)
+    assert rel(a, a0) < 1e-13 and rel(b, b0) < 1e-13
+    s, t = I.step(eta, psi, 0.002, 2)
+    s0, t0 = m.step(eta, psi, 0.002, 2)
     assert rel(s, s0) < 1e-13 and rel(t, t0) < 1e-13
 
 
@@ -157,7 +174,17 @@ def test_library_exports_every_declared_symbol():
 def test_library_host_side_argument_checks():
     from paper_2608_25203_amd import zk
     L = zk.lib()
-    assert not L.zk_create(63, 64, 1.0, 1.0, 1.0, 9.81, 3)       # not a power of two
+    assert not L.zk_create(63, 64, 1.0, 1.0, 1.0, 9.81, 3)       # neither 2^k nor 3 2^k
+    assert not L.zk_create(100, 64, 1.0, 1.0, 1.0, 9.81, 3)      # neither 2^k nor 3 2^k
+    assert not L.zk_create(48, 64, 1.0, 1.0, 1.0, 9.81, 3)       # 3 2^k below 96
+    assert not L.zk_create(3072, 64, 1.0, 1.0, 1.0, 9.81, 3)     # 3 2^k above 1536
+    for n in (96, 192, 384, 768, 1536):                            # 3 2^k axes are built
+        c3 = L.zk_create(n, 64, 1.0, 1.0, 1.0, 9.81, 3)
+        assert c3
+        T, E = ctypes.c_int(0), ctypes.c_int(0)
+        assert L.zk_team_shape(c3, 1, 1, ctypes.byref(T), ctypes.byref(E)) == 0 and (T.value, E.value) == (n // 6, 9)
+        assert L.zk_team_shape(c3, 1, 0, ctypes.byref(T), ctypes.byref(E)) == 0 and (T.value, E.value) == (n // 6, 6)
+        L.zk_destroy(c3)
     assert not L.zk_create(64, 4096, 1.0, 1.0, 1.0, 9.81, 3)     # too large
     assert not L.zk_create(64, 64, -1.0, 1.0, 1.0, 9.81, 3)      # bad length
     assert not L.zk_create(64, 64, 1.0, 1.0, 1.0, 9.81, 9)       # M out of range
@@ -230,3 +257,22 @@ def test_generated_kernel_units_are_current(tmp_path):
             name = f"zk_batch_{kind}_{tag}.hip"
             with open(os.path.join(csrc, name)) as a, open(tmp_path / name) as b:
                 assert a.read() == b.read(), name
+
+
+@pytest.mark.parametrize("M", [2, 3, 5])
+def test_schedule_algebra_1d_grid(M):
+    """A 1D grid (ny = 1, the paper's Stokes-wave setting): no padding or
+    transform along y, so the planner's fold factor is N / (3nx/2) and the
+    taper's kNyq is the x axis's; the schedule executed literally equals the
+    oracle's G psi, RHS and steps."""
+    nx, L = 128, TWO_PI
+    eta, psi = random_band_fields(nx, 1, 13, nx // 2 - 1, amplitude=0.02)
+    I = Interp(nx, 1, L, 1.0, 0.8, 9.81, M)
+    m = HOSModel(Grid(nx, 1, L, 1.0, 0.8), M)
+    assert rel(I.dtn(eta, psi), m.dtn(eta, psi)) < 1e-13
+    a, b = I.rhs(eta, psi)
+    a0, b0 = m.rhs(eta, psi)
+    assert rel(a, a0) < 1e-13 and rel(b, b0) < 1e-13
+    s, t = I.step(eta, psi, 0.002, 2)
+    s0, t0 = m.step(eta, psi, 0.002, 2)
+    assert rel(s, s0) < 1e-13 and rel(t, t0) < 1e-13
