@@ -260,7 +260,7 @@ int pblocks_of(bool row, bool pad, int nx, int ny, int T) {
 // item of each batched launch is cut into at most kUnitsPerItem chunks of at
 // least kMinUnitBlocks consecutive blocks; a unit waits for every unit of
 // its tile's earlier phases in the same segment.
-constexpr int kUnitsPerItem = 32, kMinUnitBlocks = 2, kStagger = 1;
+constexpr int kUnitsPerItem = 32, kMinUnitBlocks = 2, kStagger = 8;
 int build_units(zk_batch *b) {
   const int nt = (int)b->tiles.size();
   b->units.clear();
