@@ -60,31 +60,48 @@ def state(seed, steep, kmax_factor):
 
 
 def generate(torch, clo, full, seeds, steeps, snaps, every, crops, crop, kmax_factor, rng, tag):
-    """Crops [N, 4, crop, crop] float32 on the device from M = 6 trajectories."""
+    """Crops [N, 4, crop, crop] float32 on the device from M = 6 trajectories.
+
+    A run the order-6 solver cannot carry through its whole window (a wave
+    that steepens until the series diverges) is dropped with all of its
+    snapshots: the states just before the blow-up have no trustworthy
+    reference, and their targets can reach non-finite float32 values.  Returns the
+    crops and the number of snapshots kept."""
     from paper_2608_25203_amd.zk import ZKError
 
     n = GEOM["nx"]
     out = torch.empty((len(seeds) * snaps * crops, 4, crop, crop), dtype=torch.float32, device="cuda")
     k = 0
+    kept = dropped = 0
     t0 = time.time()
     for i, (seed, st) in enumerate(zip(seeds, steeps)):
         eta, psi = state(seed, st, kmax_factor)
         e = torch.tensor(eta, dtype=torch.float64, device="cuda")
         p = torch.tensor(psi, dtype=torch.float64, device="cuda")
+        k0 = k
         for j in range(snaps):
             if j:
                 try:
                     full.step(e, p, GEOM["dt"], every)
                 except ZKError:
-                    log(f"{tag}: run {seed} (steepness {st:.3f}) diverged at step {j * every}; kept {j} snapshots")
+                    log(f"{tag}: run {seed} (steepness {st:.3f}) diverged at step {j * every}; run dropped")
+                    k = k0
                     break
             smp = clo.features(e, p)
             offs = np.stack([rng.integers(0, n, crops), rng.integers(0, n, crops)], axis=1)
             out[k:k + crops] = clo.crops(smp, offs, crop, crop)
             k += crops
+        if k > k0 and not bool(torch.isfinite(out[k0:k]).all().item()):
+            log(f"{tag}: run {seed} (steepness {st:.3f}) gave non-finite samples; run dropped")
+            k = k0
+        if k > k0:
+            kept += (k - k0) // crops
+        else:
+            dropped += 1
         if (i + 1) % 10 == 0 or i + 1 == len(seeds):
-            log(f"{tag}: {i + 1}/{len(seeds)} runs, {k} crops, {time.time() - t0:.1f} s")
-    return out[:k]
+            log(f"{tag}: {i + 1}/{len(seeds)} runs ({dropped} dropped), {kept} snapshots, {k} crops, "
+                f"{time.time() - t0:.1f} s")
+    return out[:k], kept
 
 
 def dtn_errors(torch, clo, low, full, e, p):
@@ -144,13 +161,13 @@ def main():
     net.set_params(np.concatenate([q.ravel() for q in cnn_init_params(args.seed)]).astype(np.float32))
 
     steeps = rng.uniform(0.05, 0.2, args.runs)
-    train = generate(torch, clo, full, [1000 + i for i in range(args.runs)], steeps, args.snaps, args.every,
-                     args.crops, args.crop, args.kmax_factor, rng, "train")
+    train, nsnap = generate(torch, clo, full, [1000 + i for i in range(args.runs)], steeps, args.snaps, args.every,
+                            args.crops, args.crop, args.kmax_factor, rng, "train")
     vsteeps = rng.uniform(0.05, 0.2, args.val_runs)
-    val = generate(torch, clo, full, [9000 + i for i in range(args.val_runs)], vsteeps, args.snaps, args.every,
-                   2, args.crop, args.kmax_factor, rng, "val")
+    val, _ = generate(torch, clo, full, [9000 + i for i in range(args.val_runs)], vsteeps, args.snaps, args.every,
+                      2, args.crop, args.kmax_factor, rng, "val")
     tstd = float(train[:, 3].std().item())
-    log(f"data: {train.shape[0]} train crops, {val.shape[0]} val crops, target std {tstd:.3f}")
+    log(f"data: {nsnap} snapshots, {train.shape[0]} train crops, {val.shape[0]} val crops, target std {tstd:.3f}")
 
     def val_loss():
         tot, nb = 0.0, 0
@@ -186,7 +203,8 @@ def main():
     ev = evaluate(torch, clo, low, full, [42, 43], [0.05, 0.1, 0.15, 0.2], 50, args.kmax_factor)
     rec = {"k0": K0, "eta_scale": ETA_SCALE, "out_scale": OUT_SCALE, "halo": HALO,
            "geometry": GEOM, "kmax_factor": args.kmax_factor,
-           "data": {"runs": args.runs, "snaps": args.snaps, "every": args.every, "crops": args.crops,
+           "data": {"runs": args.runs, "snapshots": nsnap, "snaps": args.snaps, "every": args.every,
+                    "crops": args.crops,
                     "crop": args.crop, "train_crops": int(train.shape[0]), "val_crops": int(val.shape[0]),
                     "target_std": tstd},
            "training": {"steps": args.steps, "batch": args.batch, "lr": args.lr, "seconds": train_time,

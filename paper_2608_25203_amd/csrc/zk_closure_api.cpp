@@ -140,7 +140,7 @@ int audit(zk_closure *c, const double *eta, const double *psi, double *e) {
   *e = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
   c->n_audit += 1;
   c->last_err = *e;
-  c->max_err = std::max(c->max_err, *e);
+  c->max_err = (std::isnan(*e) || std::isnan(c->max_err)) ? *e + c->max_err : std::max(c->max_err, *e);  // NaN sticks
   return ZK_OK;
 }
 
