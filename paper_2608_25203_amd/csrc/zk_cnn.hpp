@@ -8,15 +8,21 @@
 //   xin      bf16   [P][4]   input channels 0..2, channel 3 zero
 //   z1..z3   float  [P][32]  pre-activations (kept for the backward pass)
 //   a1..a3   bf16   [P][32]  GELU(z)
+//   taps     float  [P][12]  layer 4's per-tap partial sums sum_c W4[tap][c] a3[p][c]
+//            (taps 0..8; slots 9..11 unused)
 //   y        float  [P]      output
 //   dz4      bf16   [P]      d loss / d y
 //   dz1..dz3 bf16   [P][32]  d loss / d z
 //   weights  master FP32 vector in the order W1 b1 W2 b2 W3 b3 W4 b4 with
 //            W (C_out, C_in, 3, 3); derived copies:
-//              w1f  float [tap][ci][co]   (bf16-rounded values)
+//              w1m  bf16  [co][48]        layer 1's MFMA operand, K = tap * 4 + ci
+//                                          (ci = 3 and taps 9..11 zero)
 //              w2f  bf16  [co][tap][ci]   forward operand of layer 2 (w3f: 3)
 //              w2b  bf16  [ci][tap'][co]  backward-data operand, tap' = 8 - tap
-//              w4f  float [tap][c]        (bf16-rounded values)
+//              w4f  float [tap][c]        (bf16-rounded values; backward)
+//              w4m  bf16  [32][2][16]     layer 4's MFMA operand: row = tap (rows
+//                                          9..31 zero), chunk q, K slot 8 h + j
+//                                          holding channel 16 q + 8 (j / 4) + 4 h + j % 4
 //   bf16 values are stored as their upper 16 bits (uint16_t).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -40,7 +46,7 @@ constexpr int NPARAM = OFF_B4 + NB4;
 constexpr int kPartBlocks = 256;  // blocks of the weight-gradient kernels (one partial row each)
 constexpr int kLossBlocks = 256;  // blocks of the loss kernel (one partial sum each)
 constexpr int kConvTileX = 128;   // pixels per block along x in the MFMA convolution
-constexpr int kConvRows = 8;      // rows per block in the MFMA convolution
+constexpr int kConvRows = 4;      // fewest rows per block in the MFMA convolution
 constexpr int kSegPx = 64;        // pixels per segment in the MFMA weight gradient
 
 struct Geo {
@@ -49,7 +55,7 @@ struct Geo {
 };
 
 hipError_t pack_samples(const float *samples, uint16_t *xin, Geo g, hipStream_t s);
-hipError_t conv1_fwd(const uint16_t *xin, const float *w1f, const float *b1, float *z1, uint16_t *a1, Geo g,
+hipError_t conv1_fwd(const uint16_t *xin, const uint16_t *w1m, const float *b1, float *z1, uint16_t *a1, Geo g,
                      hipStream_t s);
 // Layers 2 and 3 on MFMA.  Forward: out = bf16(GELU(conv(in) + bias)), z
 // (optional) = conv(in) + bias.  Backward-data: out = bf16(conv'(din) *
@@ -58,7 +64,11 @@ hipError_t conv32_fwd(const uint16_t *in, const uint16_t *wk, const float *bias,
                       hipStream_t s);
 hipError_t conv32_bwd(const uint16_t *din, const uint16_t *wkt, const float *zprev, uint16_t *dout, Geo g,
                       hipStream_t s);
-hipError_t conv4_fwd(const uint16_t *a3, const float *w4f, const float *b4, float *y, Geo g, hipStream_t s);
+// Layer 3 forward as conv32_fwd (out may be null: activations not kept) that
+// also writes layer 4's per-tap partial sums; layer 4 then sums them.
+hipError_t conv32_fwd_taps(const uint16_t *in, const uint16_t *wk, const float *bias, float *z, uint16_t *out,
+                           const uint16_t *w4m, float *taps, Geo g, hipStream_t s);
+hipError_t conv4_fwd(const float *taps, const float *b4, float *y, Geo g, hipStream_t s);
 hipError_t loss_grad(const float *y, const float *samples, int halo, double inv_n, uint16_t *dz4, double *partial,
                      Geo g, hipStream_t s);
 hipError_t conv4_bwd(const uint16_t *dz4, const float *w4f, const float *z3, uint16_t *dz3, Geo g, hipStream_t s);
@@ -70,8 +80,8 @@ hipError_t dw1(const uint16_t *dz1, const uint16_t *xin, float *part, Geo g, hip
 hipError_t reduce_parts(const float *part, int n, float *out, hipStream_t s);
 hipError_t adam(float *p, float *m, float *v, const float *g, float lr, float b1, float b2, float eps, float c1,
                 float c2, hipStream_t s);
-hipError_t prep_weights(const float *p, float *w1f, uint16_t *w2f, uint16_t *w2b, uint16_t *w3f, uint16_t *w3b,
-                        float *w4f, hipStream_t s);
+hipError_t prep_weights(const float *p, uint16_t *w1m, uint16_t *w2f, uint16_t *w2b, uint16_t *w3f, uint16_t *w3b,
+                        float *w4f, uint16_t *w4m, hipStream_t s);
 
 }  // namespace cnn
 }  // namespace zk

@@ -42,17 +42,19 @@ void layout(zk_cnn *n) {
   n->o_m = take(NPARAM * 4);
   n->o_v = take(NPARAM * 4);
   n->o_g = take(NPARAM * 4);
-  n->o_w1f = take(NW1 * 4);
+  n->o_w1m = take(CH * 48 * 2);
   n->o_w2f = take(NW2 * 2);
   n->o_w2b = take(NW2 * 2);
   n->o_w3f = take(NW3 * 2);
   n->o_w3b = take(NW3 * 2);
   n->o_w4f = take(NW4 * 4);
+  n->o_w4m = take(32 * 32 * 2);
   n->o_part = take((size_t)kPartBlocks * (NW2 + NB2) * 4);
   n->o_loss = take(kLossBlocks * 8);
   n->o_xin = take(P * 4 * 2);
   for (int l = 0; l < 3; ++l) n->o_z[l] = take(P * CH * 4);
   for (int l = 0; l < 3; ++l) n->o_a[l] = take(P * CH * 2);
+  n->o_taps = take(P * 12 * 4);
   n->o_y = take(P * 4);
   n->o_dz4 = take(P * 2);
   for (int l = 0; l < 3; ++l) n->o_dz[l] = take(P * CH * 2);
@@ -86,12 +88,12 @@ int forward_packed(zk_cnn *n, float *y, Geo g, bool keep) {
   auto f = [&](size_t o) { return reinterpret_cast<float *>(w + o); };
   auto h = [&](size_t o) { return reinterpret_cast<uint16_t *>(w + o); };
   const float *p = f(n->o_p);
-  HIP_TRY(n, conv1_fwd(h(n->o_xin), f(n->o_w1f), p + OFF_B1, keep ? f(n->o_z[0]) : nullptr, h(n->o_a[0]), g, n->stream));
+  HIP_TRY(n, conv1_fwd(h(n->o_xin), h(n->o_w1m), p + OFF_B1, keep ? f(n->o_z[0]) : nullptr, h(n->o_a[0]), g, n->stream));
   HIP_TRY(n, conv32_fwd(h(n->o_a[0]), h(n->o_w2f), p + OFF_B2, keep ? f(n->o_z[1]) : nullptr, h(n->o_a[1]), g,
                         n->stream));
-  HIP_TRY(n, conv32_fwd(h(n->o_a[1]), h(n->o_w3f), p + OFF_B3, keep ? f(n->o_z[2]) : nullptr, h(n->o_a[2]), g,
-                        n->stream));
-  HIP_TRY(n, conv4_fwd(h(n->o_a[2]), f(n->o_w4f), p + OFF_B4, y, g, n->stream));
+  HIP_TRY(n, conv32_fwd_taps(h(n->o_a[1]), h(n->o_w3f), p + OFF_B3, keep ? f(n->o_z[2]) : nullptr,
+                             keep ? h(n->o_a[2]) : nullptr, h(n->o_w4m), f(n->o_taps), g, n->stream));
+  HIP_TRY(n, conv4_fwd(f(n->o_taps), p + OFF_B4, y, g, n->stream));
   return ZK_OK;
 }
 
@@ -146,7 +148,7 @@ int prep(zk_cnn *n) {
   char *w = n->ws;
   auto f = [&](size_t o) { return reinterpret_cast<float *>(w + o); };
   auto h = [&](size_t o) { return reinterpret_cast<uint16_t *>(w + o); };
-  HIP_TRY(n, prep_weights(f(n->o_p), f(n->o_w1f), h(n->o_w2f), h(n->o_w2b), h(n->o_w3f), h(n->o_w3b), f(n->o_w4f),
+  HIP_TRY(n, prep_weights(f(n->o_p), h(n->o_w1m), h(n->o_w2f), h(n->o_w2b), h(n->o_w3f), h(n->o_w3b), f(n->o_w4f), h(n->o_w4m),
                           n->stream));
   return ZK_OK;
 }

@@ -19,8 +19,8 @@ struct zk_cnn {
   long long adam_t = 0;
   // workspace byte offsets (layouts in zk_cnn.hpp)
   size_t o_p = 0, o_m = 0, o_v = 0, o_g = 0;
-  size_t o_w1f = 0, o_w2f = 0, o_w2b = 0, o_w3f = 0, o_w3b = 0, o_w4f = 0;
-  size_t o_part = 0, o_loss = 0, o_xin = 0, o_z[3] = {0, 0, 0}, o_a[3] = {0, 0, 0}, o_y = 0, o_dz4 = 0,
+  size_t o_w1m = 0, o_w2f = 0, o_w2b = 0, o_w3f = 0, o_w3b = 0, o_w4f = 0, o_w4m = 0;
+  size_t o_part = 0, o_loss = 0, o_xin = 0, o_z[3] = {0, 0, 0}, o_a[3] = {0, 0, 0}, o_taps = 0, o_y = 0, o_dz4 = 0,
          o_dz[3] = {0, 0, 0};
   size_t total = 0;
 };
