@@ -70,10 +70,29 @@ enum {
                              changes the workspace size: set it before zk_bind */
     ZK_OPT_BOUNDARY = 8,  /* ZK_BC_PERIODIC (default) or ZK_BC_REFLECT; set
                              before zk_bind                                   */
+    ZK_OPT_ROW_FFT = 9,   /* form of the padded row passes' transforms:
+                             ZK_ROW_FFT_STOCKHAM (default) or ZK_ROW_FFT_LANES;
+                             zk_autotune times both at the chosen team shape
+                             and keeps the faster.  Same results to rounding. */
     ZK_OPT_PROFILE = 6    /* 1: bracket every kernel launch with HIP events on
                              the bound stream and accumulate per-kind times for
                              zk_kernel_stats (adds event records between
                              launches); 0: off (default)                      */
+};
+
+/* Row transform forms (ZK_OPT_ROW_FFT).  STOCKHAM: radix-E step in
+ * registers, then radix-4/2 Stockham passes through LDS, a block barrier
+ * each.  LANES (padded row passes of teams of 64 to 1024 threads whose two
+ * LDS buffers fit; other shapes keep STOCKHAM): the inverse transform leaves
+ * the physical row in a permuted order and the forward transform takes it
+ * back, so no pass reorders; only the stages that span wavefronts go through
+ * LDS behind barriers, and the 64-point stages over a wavefront's lanes
+ * exchange partners by DPP lane permutes and ds_bpermute, without LDS
+ * storage or barriers.  Pointwise products between the two do not see the
+ * order.  (Cooley-Tukey decimation in frequency and its transpose.) */
+enum {
+    ZK_ROW_FFT_STOCKHAM = 0,
+    ZK_ROW_FFT_LANES = 1
 };
 
 /* Integrators of zk_step (ZK_OPT_INTEGRATOR). */
@@ -128,6 +147,9 @@ void zk_destroy(zk_ctx *ctx);
 /* Set an option (keys above).  EPS, TAPER and FILTER may change at any time
  * and apply from the next call; PRECISION must be set before zk_bind. */
 int zk_set_option(zk_ctx *ctx, int key, double value);
+/* Current value of an option (as set, or as zk_autotune left it).  ZK_EINVAL
+ * for an unknown key or a null pointer. */
+int zk_get_option(const zk_ctx *ctx, int key, double *value);
 
 /* Bytes of device workspace the context needs for its current options. */
 size_t zk_workspace_bytes(const zk_ctx *ctx);

@@ -15,6 +15,12 @@ SHAPES += [(T, 9, True) for T in (16, 32, 64, 128, 256)] + [(T, 6, False) for T 
 FOLD_SHAPES = [(T, E) for T in (64, 128, 256) for E in (2, 3)]  # as fold_team_shape() in zk_kernels.hpp
 
 
+def lanes_ok(T, E, pad, real_bytes):
+    """as row_lanes_ok() in zk_kernels.hpp"""
+    N, tpb = T * E, max(T, 256) // T
+    return pad and T % 64 == 0 and T <= 1024 and (2 * tpb * N + N) * 2 * real_bytes <= 100 * 1024
+
+
 def bs(T):
     return max(256, T)
 
@@ -70,6 +76,22 @@ for kind in ("row", "col"):
             for T, E in FOLD_SHAPES:
                 lines.append(f"  if (T == {T} && E == {E}) {{")
                 lines.append(f"    hipLaunchKernelGGL((col_kernel_folds<{real}, {T}, {E}>), grid, dim3(kMaxFolds * {T}), 0, s, args, items, tile0, first0, sched0, ph);")
+                lines.append("    return hipGetLastError();")
+                lines.append("  }")
+            lines += ["  return hipErrorInvalidValue;", "}", ""]
+        if kind == "row":  # the permuted-layout form of the padded shapes that have one
+            rb = 8 if real == "double" else 4
+            lanes = [(T, E) for T, E, pad in SHAPES if lanes_ok(T, E, pad, rb)]
+            lines += ["template <>", f"const void *lanes_row_kernel<{real}>(int T, int E) {{"]
+            for T, E in lanes:
+                lines.append(f"  if (T == {T} && E == {E}) return reinterpret_cast<const void *>(&row_kernel_batch<{real}, {T}, {E}, true, true>);")
+            lines += ["  return nullptr;", "}", "",
+                      "template <>",
+                      f"hipError_t launch_lanes_row<{real}>(int T, int E, dim3 grid, hipStream_t s, const RowArgs<{real}> *args,",
+                      "                                   const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {"]
+            for T, E in lanes:
+                lines.append(f"  if (T == {T} && E == {E}) {{")
+                lines.append(f"    hipLaunchKernelGGL((row_kernel_batch<{real}, {T}, {E}, true, true>), grid, dim3({bs(T)}), 0, s, args, items, tile0, first0, sched0, ph);")
                 lines.append("    return hipGetLastError();")
                 lines.append("  }")
             lines += ["  return hipErrorInvalidValue;", "}", ""]

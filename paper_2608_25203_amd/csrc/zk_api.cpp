@@ -73,7 +73,7 @@ void compute_layout(zk_ctx *c) {
   const size_t cs = 2 * rs;
   const int lens[4] = {3 * nx / 2, nx, 3 * ny / 2, ny};
   size_t off = 0;
-  for (int i = 0; i < 4; ++i) {  // kTwSlots pass-ordered tables per transform length
+  for (int i = 0; i < 4; ++i) {  // kTwSlots twiddle tables per transform length
     c->off_tw[i] = off;
     off = align_up(off + (size_t)kTwSlots * lens[i] * cs);
   }
@@ -132,18 +132,23 @@ void compute_layout(zk_ctx *c) {
   c->total = off;
 }
 
-// The kTwSlots pass-ordered twiddle tables of transform length n, one per
-// first-pass radix E of slot tw_slot(E) (see stage order in zk_fft.hpp):
-// entry Ns_p - E + (r-1) Ns_p + k of table E is W_n^(r k step_p), in long
-// double on the host.  A slot whose E does not give a valid team is unused.
+// The kTwSlots twiddle tables of transform length n: one pass-ordered table
+// per first-pass radix E of slot tw_slot(E) (see stage order in zk_fft.hpp):
+// entry Ns_p - E + (r-1) Ns_p + k of table E is W_n^(r k step_p); a slot
+// whose E does not give a valid team is unused; and the natural table W_n^m,
+// m < n, in slot kTwNatural.  In long double on the host.
 template <typename real>
 std::vector<cpx<real>> twiddles(int n) {
   std::vector<cpx<real>> t((size_t)kTwSlots * n, cpx<real>{(real)0, (real)0});
   const long double two_pi = 2.0L * 3.14159265358979323846264338327950288L;
+  for (int m = 0; m < n; ++m) {
+    const long double a = -two_pi * (long double)m / (long double)n;
+    t[(size_t)kTwNatural * n + m] = {(real)cosl(a), (real)sinl(a)};
+  }
   // candidate first-pass radices of this length, one per slot (tw_slot)
-  const int cand[kTwSlots] = {n % 9 == 0 ? 9 : (n % 3 == 0 ? 3 : 2), n % 9 == 0 ? 18 : (n % 3 == 0 ? 6 : 4),
-                              n % 9 == 0 ? 0 : (n % 3 == 0 ? 12 : 8)};
-  for (int s = 0; s < kTwSlots; ++s) {
+  const int cand[kTwNatural] = {n % 9 == 0 ? 9 : (n % 3 == 0 ? 3 : 2), n % 9 == 0 ? 18 : (n % 3 == 0 ? 6 : 4),
+                                n % 9 == 0 ? 0 : (n % 3 == 0 ? 12 : 8)};
+  for (int s = 0; s < kTwNatural; ++s) {
     const int E = cand[s];
     if (E == 0) continue;
     const int T = n / E;
@@ -342,6 +347,10 @@ int run_seq_t(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) {
       const ColArgs<real> *cargs = reinterpret_cast<const ColArgs<real> *>(ws + c->off_cargs);
       if (!row && c->pp.ny == 1)  // 1D grid: one element per column, no y transform
         e = launch_col_1d<real>(l.c2 == 1, dim3((nx / 2 + 255) / 256, l.count), c->stream, cargs, tile0, first0);
+      else if (row && pad && c->row_fft == ZK_ROW_FFT_LANES && row_lanes_ok(sh.T, sh.E, true, (int)sizeof(real)))
+        e = launch_lanes_row<real>(sh.T, sh.E, grid, c->stream,
+                                   reinterpret_cast<const RowArgs<real> *>(ws + c->off_rargs), items, tile0, first0,
+                                   sched0, pa);
       else if (row)
         e = launch_batch_row<real>(sh.T, sh.E, pad, grid, c->stream,
                                    reinterpret_cast<const RowArgs<real> *>(ws + c->off_rargs), items, tile0, first0,
@@ -557,6 +566,10 @@ int zk_set_option(zk_ctx *c, int key, double v) {
     case ZK_OPT_PROFILE:
       c->prof = v != 0.0;
       return ZK_OK;
+    case ZK_OPT_ROW_FFT:
+      if (v != ZK_ROW_FFT_STOCKHAM && v != ZK_ROW_FFT_LANES) return fail(c, ZK_EINVAL, "unknown row transform form");
+      c->row_fft = (int)v;
+      return ZK_OK;
     case ZK_OPT_BOUNDARY:
       if (v != ZK_BC_PERIODIC && v != ZK_BC_REFLECT) return fail(c, ZK_EINVAL, "unknown boundary");
       if (c->bound && (int)v != c->bc) return fail(c, ZK_EINVAL, "set the boundary before zk_bind");
@@ -580,6 +593,23 @@ int zk_set_option(zk_ctx *c, int key, double v) {
   }
   c->dirty = true;
   c->have_plan = false;
+  return ZK_OK;
+}
+
+int zk_get_option(const zk_ctx *c, int key, double *v) {
+  if (!c || !v) return ZK_EINVAL;
+  switch (key) {
+    case ZK_OPT_EPS: *v = c->pp.eps; break;
+    case ZK_OPT_TAPER: *v = c->pp.taper ? 1.0 : 0.0; break;
+    case ZK_OPT_FILTER: *v = c->pp.filt ? 1.0 : 0.0; break;
+    case ZK_OPT_PRECISION: *v = c->precision; break;
+    case ZK_OPT_CHECK: *v = c->check ? 1.0 : 0.0; break;
+    case ZK_OPT_PROFILE: *v = c->prof ? 1.0 : 0.0; break;
+    case ZK_OPT_INTEGRATOR: *v = c->integrator; break;
+    case ZK_OPT_BOUNDARY: *v = c->bc; break;
+    case ZK_OPT_ROW_FFT: *v = c->row_fft; break;
+    default: return ZK_EINVAL;
+  }
   return ZK_OK;
 }
 
@@ -849,6 +879,22 @@ int zk_autotune(zk_ctx *c, double dt, int reps) {
         }
       }
       c->tuneT[row][pad] = bestT;
+      // padded rows: the permuted-layout transforms at the chosen shape, kept if faster
+      if (row && pad && bestT && row_lanes_ok(bestT, N / bestT, true, c->precision == 32 ? 4 : 8)) {
+        const int keep = c->row_fft;
+        c->row_fft = ZK_ROW_FFT_LANES;
+        float tot = 0.f;
+        for (int r = 0; r <= reps; ++r) {
+          HIP_TRY(c, hipEventRecord(e0, c->stream));
+          if ((rc = run_seq(c, sub, Phys{}))) return rc;
+          HIP_TRY(c, hipEventRecord(e1, c->stream));
+          HIP_TRY(c, hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+          if (r) tot += ms;
+        }
+        c->row_fft = tot < best ? ZK_ROW_FFT_LANES : (keep == ZK_ROW_FFT_LANES ? ZK_ROW_FFT_STOCKHAM : keep);
+      }
     }
   hipEventDestroy(e0);
   hipEventDestroy(e1);

@@ -215,4 +215,60 @@ hipError_t launch_batch_row<double>(int T, int E, bool pad, dim3 grid, hipStream
   return hipErrorInvalidValue;
 }
 
+template <>
+const void *lanes_row_kernel<double>(int T, int E) {
+  if (T == 64 && E == 3) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 3, true, true>);
+  if (T == 64 && E == 6) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 6, true, true>);
+  if (T == 128 && E == 3) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 3, true, true>);
+  if (T == 128 && E == 6) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 6, true, true>);
+  if (T == 256 && E == 3) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 3, true, true>);
+  if (T == 256 && E == 6) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 6, true, true>);
+  if (T == 512 && E == 3) return reinterpret_cast<const void *>(&row_kernel_batch<double, 512, 3, true, true>);
+  if (T == 64 && E == 9) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 9, true, true>);
+  if (T == 128 && E == 9) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 9, true, true>);
+  return nullptr;
+}
+
+template <>
+hipError_t launch_lanes_row<double>(int T, int E, dim3 grid, hipStream_t s, const RowArgs<double> *args,
+                                   const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {
+  if (T == 64 && E == 3) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 64, 3, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 64 && E == 6) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 64, 6, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 3) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 128, 3, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 6) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 128, 6, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 256 && E == 3) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 256, 3, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 256 && E == 6) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 256, 6, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 512 && E == 3) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 512, 3, true, true>), grid, dim3(512), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 64 && E == 9) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 64, 9, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 9) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 128, 9, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace zk

@@ -264,7 +264,10 @@ __host__ __device__ constexpr int lds_len(int N) { return N; }
 // transform length keeps one table per candidate E, slot tw_slot(E).
 // Slots: E in {2, 3, 9} -> 0, {4, 6, 18} -> 1, {8, 12} -> 2 (a length uses at
 // most one E of each group).
-constexpr int kTwSlots = 3;
+// Slot 3 holds the natural table W_N^m, m < N (the permuted-layout forms
+// below).
+constexpr int kTwSlots = 4;
+constexpr int kTwNatural = 3;
 __host__ __device__ constexpr int tw_slot(int E) {
   return (E == 2 || E == 3 || E == 9) ? 0 : ((E == 4 || E == 6 || E == 18) ? 1 : 2);
 }
@@ -478,6 +481,225 @@ __device__ __forceinline__ void fft_in(HbmRegs<R, N, E, LAST> &x, cpx<R> (&v)[E]
 #pragma unroll
     for (int r = 0; r < E; ++r) v[r] = res[lpad(t + (N / E) * r)];
   }
+}
+
+// ---- permuted-layout transforms --------------------------------------------
+// For a team of T = 64 W threads (W wavefronts, W a power of two up to 16)
+// and N = E T points.  perm_ifft takes v[r] = x[t + T r] (natural order) and
+// leaves the transform in a permuted order; perm_fft takes that permuted
+// order and returns natural order.  Between the two, pointwise products do
+// not care where a point sits, so neither form spends an LDS pass on
+// reordering, and only the stages whose butterflies span wavefronts meet at
+// block barriers.  With t = 64 w + l (wavefront w, lane l) and three digits
+// n = l + 64 w + 64 W r, k = k_a + E k_b + E W k_c, the inverse transform is
+//   a  = DFT_E over r (registers), times W_N^(64 w k_a);
+//   b  = DFT_W over w (wavefronts: radix-4/2 decimation-in-frequency stages
+//        through LDS, one barrier each; wave w ends up holding k_b =
+//        bitrev(w)), times W_N^(l (k_a + E k_b));
+//   X  = DFT_64 over l (lanes) for each (k_a, k_b): six radix-2
+//        decimation-in-frequency stages whose partners l ^ h are exchanged
+//        across lanes (DPP permutes, ds_bpermute), no LDS storage, no
+//        barrier; lane l ends up holding k_c = bitrev6(l).
+// Thread t then holds in v[s] the point s + E bitrev(w) + E W bitrev6(l).  perm_fft is
+// the same algorithm transposed (the DFT matrix is symmetric): the lane DFT
+// first, the twiddles, the wavefront stages as decimation-in-time, the
+// register DFT last.  Twiddles come from the natural table W_N^m (forward
+// sign; conjugated for DIR > 0).
+
+// LDS ordering inside one wavefront: its LDS operations complete in issue
+// order, so a compiler barrier is all a wavefront-private exchange needs
+// (a one-wavefront team's result readout).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int DIR, typename R>
+__device__ __forceinline__ cpx<R> twn(const cpx<R> *tw, int m) {
+  cpx<R> w = tw[m];
+  if constexpr (DIR > 0) w.y = -w.y;
+  return w;
+}
+
+__host__ __device__ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x / 2); }
+
+// Lane l ^ H's copy of a 32-bit value: DPP within rows of 16 lanes (H <= 8:
+// quad permutes, the half-row mirror followed by a quad reversal, a row
+// rotation by 8), ds_bpermute across rows.
+template <int H>
+__device__ __forceinline__ int lane_xor(int v) {
+  if constexpr (H == 1) return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  else if constexpr (H == 2) return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  else if constexpr (H == 4) {
+    const int m = __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror: i -> 7 - i
+    return __builtin_amdgcn_update_dpp(0, m, 0x1B, 0xF, 0xF, false);          // quad_perm [3,2,1,0]
+  } else if constexpr (H == 8) return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  else return __shfl_xor(v, H, 64);
+}
+template <int H>
+__device__ __forceinline__ double lane_xor(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lane_xor<H>((int)(unsigned)b), hi = lane_xor<H>((int)(unsigned)(b >> 32));
+  return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+template <int H>
+__device__ __forceinline__ float lane_xor(float v) {
+  return __int_as_float(lane_xor<H>(__float_as_int(v)));
+}
+
+// 64-point DFT over the lanes of one wavefront for each of its E sequences,
+// by radix-2 stages whose partners are exchanged across lanes (lane_xor):
+// DIF: natural order in, bit-reversed out (lane l holds X[bitrev6(l)]); DIT
+// (the transpose): bit-reversed in, natural out.  Stage h's factor
+// W_2h^(l mod h) multiplies the upper lane's difference (DIF) or its own
+// value before the exchange (DIT).
+template <typename R, int N, int E, int DIR, bool DIF>
+__device__ __forceinline__ void wave_dft64_x(cpx<R> (&v)[E], const cpx<R> *__restrict__ tw, int l) {
+  static_for<0, 6>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    constexpr int h = DIF ? (32 >> i) : (1 << i);
+    const bool B = (l & h) != 0;
+    const R sg = B ? (R)-1 : (R)1;
+    cpx<R> ws = {(R)1, (R)0};
+    if constexpr (h > 1) {
+      const cpx<R> wt = twn<DIR>(tw, (l & (h - 1)) * (N / (2 * h)));
+      if (B) ws = wt;
+    }
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      if constexpr (DIF) {
+        const cpx<R> p = {lane_xor<h>(v[q].x), lane_xor<h>(v[q].y)};
+        const cpx<R> d = {p.x + sg * v[q].x, p.y + sg * v[q].y};
+        v[q] = h > 1 ? cmul(d, ws) : d;
+      } else {
+        const cpx<R> c = h > 1 ? cmul(v[q], ws) : v[q];
+        const cpx<R> p = {lane_xor<h>(c.x), lane_xor<h>(c.y)};
+        v[q] = {p.x + sg * c.x, p.y + sg * c.y};
+      }
+    }
+  });
+}
+
+// Wavefront stages of the W-point DFT: spans in wavefronts, from the top,
+// radix 4 (spans hw, hw / 2) while two bits remain, else radix 2.
+__host__ __device__ constexpr int xw_stages(int W) {
+  int n = 0;
+  for (int hw = W / 2; hw >= 1; hw = hw >= 2 ? hw / 4 : hw / 2) ++n;
+  return n;
+}
+__host__ __device__ constexpr int xw_span(int W, int i) {  // top span of decimation-in-frequency stage i
+  int hw = W / 2;
+  for (int k = 0; k < i; ++k) hw = hw >= 2 ? hw / 4 : hw / 2;
+  return hw;
+}
+
+// One wavefront stage of the decimation-in-frequency DFT over w (FWD) or of
+// its transpose (decimation in time), on every register: v goes out through
+// buf (layout [E][T]), one block barrier, and the partners come back.  HW:
+// the stage's top span in wavefronts (radix 4 for HW >= 2: spans HW, HW / 2).
+// The butterfly's position bits are wavefront-uniform, so its branches are.
+template <typename R, int T, int E, int DIR, int HW, bool DIF>
+__device__ __forceinline__ void xw_stage(cpx<R> (&v)[E], cpx<R> *buf, const cpx<R> *__restrict__ tw, int t, int w) {
+  constexpr int N = T * E;
+#pragma unroll
+  for (int q = 0; q < E; ++q) buf[q * T + t] = v[q];
+  __syncthreads();
+  if constexpr (HW == 1) {
+    const bool B = (w & 1) != 0;
+    const int tp = t ^ 64;
+    // W_2^0 = 1: the one radix-2 stage with span one wavefront has no twiddle
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const cpx<R> p = buf[q * T + tp];
+      v[q] = B ? csub(p, v[q]) : cadd(v[q], p);
+    }
+  } else {
+    constexpr int H2 = HW / 2;
+    const int t0 = t & ~(96 * HW);
+    const int w0 = w & ~(HW | H2);
+    const bool B1 = (w & HW) != 0, B0 = (w & H2) != 0;
+    const cpx<R> w1 = twn<DIR>(tw, (w0 % HW) * (N / (2 * HW)));
+    const cpx<R> w2 = twn<DIR>(tw, (w0 % H2) * (N / HW));
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const cpx<R> i0 = buf[q * T + t0], i1 = buf[q * T + t0 + 32 * HW];
+      const cpx<R> i2 = buf[q * T + t0 + 64 * HW], i3 = buf[q * T + t0 + 96 * HW];
+      if constexpr (DIF) {
+        // positions t0 + {0, 32 HW, 64 HW, 96 HW} hold a0, a1, b0, b1
+        const cpx<R> x0 = B1 ? cmul(csub(i0, i2), w1) : cadd(i0, i2);
+        const cpx<R> x1 = B1 ? mul_diri<DIR>(cmul(csub(i1, i3), w1)) : cadd(i1, i3);
+        v[q] = B0 ? cmul(csub(x0, x1), w2) : cadd(x0, x1);
+      } else {
+        const cpx<R> m1 = cmul(i1, w2), m3 = cmul(i3, w2);
+        const cpx<R> c = B0 ? csub(i0, m1) : cadd(i0, m1);
+        const cpx<R> d = B0 ? csub(i2, m3) : cadd(i2, m3);
+        const cpx<R> fd = B0 ? mul_diri<DIR>(cmul(d, w1)) : cmul(d, w1);
+        v[q] = B1 ? csub(c, fd) : cadd(c, fd);
+      }
+    }
+  }
+}
+
+// x[t + T r] in v[r] -> v[s] = X[s + E bitrev(w) + E W bitrev6(l)] (sign DIR).  b0, b1:
+// the team's two LDS buffers of N entries; tw: the natural table.  Opens
+// with a block barrier when W > 1 (earlier readers of both buffers are done);
+// closes without one.  Every thread of the block must call it.
+template <typename R, int T, int E, int DIR>
+__device__ __forceinline__ void perm_ifft(cpx<R> (&v)[E], cpx<R> *b0, cpx<R> *b1, const cpx<R> *__restrict__ tw,
+                                          int t) {
+  constexpr int N = T * E, W = T / 64, NS = xw_stages(W);
+  static_assert(T % 64 == 0 && W <= 16, "team of whole wavefronts");
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6), l = t & 63;
+  DFT<E, DIR, R>::run(v);
+#pragma unroll
+  for (int q = 1; q < E; ++q) v[q] = cmul(v[q], twn<DIR>(tw, 64 * w * q));
+  if constexpr (W > 1) {
+    __syncthreads();
+    static_for<0, NS>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      xw_stage<R, T, E, DIR, xw_span(W, i), true>(v, i % 2 == 0 ? b0 : b1, tw, t, w);
+    });
+  }
+  const int kb = W > 1 ? (int)(__builtin_bitreverse32((unsigned)w) >> (32 - ilog2c(W))) : 0;
+#pragma unroll
+  for (int q = 0; q < E; ++q)
+    if (q > 0 || kb > 0) v[q] = cmul(v[q], twn<DIR>(tw, l * (q + E * kb)));
+  wave_dft64_x<R, N, E, DIR, true>(v, tw, l);
+}
+
+// v[s] = x[s + E bitrev(w) + E W bitrev6(l)] -> X[t + T r] in natural order in the
+// returned LDS buffer (sign DIR), after a closing block barrier (every thread
+// may read any element; W = 1: the team is one wavefront, which the closing
+// wavefront ordering covers).  OPEN: open with a block barrier (omit only
+// where one since the last read of the buffers precedes the call).
+template <typename R, int T, int E, int DIR, bool OPEN = true>
+__device__ __forceinline__ const cpx<R> *perm_fft(cpx<R> (&v)[E], cpx<R> *b0, cpx<R> *b1,
+                                                  const cpx<R> *__restrict__ tw, int t) {
+  constexpr int N = T * E, W = T / 64, NS = xw_stages(W);
+  static_assert(T % 64 == 0 && W <= 16, "team of whole wavefronts");
+  const int w = __builtin_amdgcn_readfirstlane(t >> 6), l = t & 63;
+  if constexpr (OPEN && W > 1) __syncthreads();
+  wave_dft64_x<R, N, E, DIR, false>(v, tw, l);
+  const int kb = W > 1 ? (int)(__builtin_bitreverse32((unsigned)w) >> (32 - ilog2c(W))) : 0;
+#pragma unroll
+  for (int q = 0; q < E; ++q)
+    if (q > 0 || kb > 0) v[q] = cmul(v[q], twn<DIR>(tw, l * (q + E * kb)));
+  // transposed wavefront stages in reverse order; the first writes b1 (other
+  // wavefronts may still read their regions of b0)
+  static_for<0, NS>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    xw_stage<R, T, E, DIR, xw_span(W, NS - 1 - i), false>(v, i % 2 == 0 ? b1 : b0, tw, t, w);
+  });
+#pragma unroll
+  for (int q = 1; q < E; ++q) v[q] = cmul(v[q], twn<DIR>(tw, 64 * w * q));
+  DFT<E, DIR, R>::run(v);
+  cpx<R> *out = NS % 2 == 1 ? b0 : b1;  // not read by the last stage
+#pragma unroll
+  for (int r = 0; r < E; ++r) out[t + T * r] = v[r];
+  if constexpr (W > 1) __syncthreads();
+  else wave_lds_sync();
+  return out;
 }
 
 }  // namespace zk

@@ -38,7 +38,7 @@ struct RowArgs {
   int nx;                // base-grid row length (physical fields)
   const double *pin0, *pin1, *pin2;  // OP_LDP slots 0..2
   double *pout0, *pout1;             // OP_STP slots 0..1
-  const cpx<real> *tw;    // kTwSlots pass-ordered twiddle tables of the row FFT length N
+  const cpx<real> *tw;    // kTwSlots twiddle tables (pass-ordered, natural) of the row FFT length N
   double kx_scale;        // 2 pi / Lx
   const float *colmax;    // [mixed field][nx/2]: per-column max |value| written by the lifts
 };
@@ -60,7 +60,7 @@ struct ColArgs {
   cpx<double> *base;
   long long base_stride;
   int ny, nx;
-  const cpx<real> *tw;  // kTwSlots pass-ordered twiddle tables of the column FFT length
+  const cpx<real> *tw;  // kTwSlots twiddle tables (pass-ordered, natural) of the column FFT length
   double kx_scale, ky_scale;
   double depth;   // <= 0: deep water
   double inv_kc;  // 1 / kc of the taper
@@ -220,6 +220,14 @@ __device__ __forceinline__ float2 pow2_scale(float m) {
 // otherwise a base transform of N = n points, retained r < E/2 and r >= E/2.
 // In both cases the band has K = (E/3 or E/2) * T = n/2 positive modes, and
 // slot "first negative, t = 0" is the Nyquist mode (never stored).
+// Whether a row team shape (T threads, E elements, default block of
+// max(T, 256) threads) has the permuted-layout transforms: padded, whole
+// wavefronts, and two LDS buffers per team (the rule of Shape::nbuf).
+__host__ __device__ constexpr bool row_lanes_ok(int T, int E, bool padded, int real_bytes) {
+  const int N = T * E, tpb = (T > 256 ? T : 256) / T;
+  return padded && T % 64 == 0 && T <= 1024 && (2 * tpb * N + N) * 2 * real_bytes <= 100 * 1024;
+}
+
 template <int T, int E, int BSZ = 0, bool PAD = (E % 3 == 0)>
 struct Shape {
   static constexpr bool PADDED = PAD;
@@ -238,6 +246,13 @@ struct Shape {
   template <typename real>
   static constexpr bool tw_in_lds() {
     return (nbuf<real>() * TPB * L + N) * (int)sizeof(cpx<real>) <= 100 * 1024;
+  }
+  // Padded row passes of whole-wavefront teams with two buffers can also run
+  // their transforms in the permuted layout with lane-exchange butterflies
+  // (perm_ifft / perm_fft); the caller picks the form at run time.
+  template <typename real>
+  static constexpr bool lanes_ok() {
+    return row_lanes_ok(T, E, PADDED, (int)sizeof(real));
   }
 };
 
@@ -346,11 +361,14 @@ struct BatchItem {
 
 // Row pass body: TPB teams per block, one row each (block blk of the
 // pass), all running program progs[prog].
-template <typename real, int T, int E, bool DYN = false, int BSZ = 0, bool PAD = (E % 3 == 0)>
+// LANES: run the transforms in the permuted layout (only for a shape whose
+// lanes_ok() holds).
+template <typename real, int T, int E, bool DYN = false, int BSZ = 0, bool PAD = (E % 3 == 0), bool LANES = false>
 __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int blk, const RowProg *progs0) {
   using S = Shape<T, E, BSZ, PAD>;
   constexpr int N = S::N, L = S::L, NB = S::template nbuf<real>();
   constexpr bool TWL = S::template tw_in_lds<real>();
+  static_assert(!LANES || S::template lanes_ok<real>(), "no permuted-layout form for this shape");
   // A single grid passes its program table as a kernel argument, so the
   // program record loads alongside the argument record, not after it (the
   // empty asm keeps that path a branch of its own).
@@ -386,18 +404,23 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   const bool in_row = row < a.rows;
   cpx<real> *b0 = smem + team * NB * L;
   cpx<real> *b1 = b0 + (NB - 1) * L;
-  const cpx<real> *tw = a.tw + tw_slot(E) * N;  // this shape's pass-ordered table
+  // the permuted forms read the natural table, the others this shape's
+  // pass-ordered table
+  const cpx<real> *tw = a.tw + (LANES ? kTwNatural : tw_slot(E)) * N;
   if constexpr (TWL) {
-    stage_twiddles_async<S::BS, N - E>(twl, tw);
+    stage_twiddles_async<S::BS, LANES ? N : N - E>(twl, tw);
     tw = twl;
   }
-  // No barrier here: every transform form opens with one before its first
-  // twiddle read, which publishes the staged table once each wave has
-  // waited for its share (settle_tw, before the first transform).
+  // No barrier here: every pass-ordered transform form opens with one before
+  // its first twiddle read, which publishes the staged table once each wave
+  // has waited for its share (settle_tw, before the first transform).  The
+  // permuted forms need not open with one, so settle_tw publishes the table
+  // with a barrier of its own.
   bool tw_pending = TWL;
   auto settle_tw = [&]() {
     if (tw_pending) {
       twiddles_landed();
+      if constexpr (LANES) __syncthreads();
       tw_pending = false;
     }
   };
@@ -438,66 +461,78 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         // p = j + NB r of butterfly j = t + T it); its result arrives in z[]
         // as element t + T e without an LDS readout.  (1024-thread teams, and
         // base lengths, whose last pass keeps only half the team busy,
-        // measured faster with team_fft from the t + T e layout.)
-        constexpr bool XP = T <= 512 && S::PADDED;
-        using HL = HbmLayout<N, E, XP>;
-        cpx<real> xa[HL::IT][HL::R], xb[HL::IT][HL::R];
-        auto elem = [&](int it, int r) { return HL::elem(t, it, r); };
-        auto live = [&](int it) { return HL::live(t, it); };
+        // measured faster with team_fft from the t + T e layout.)  The
+        // permuted form loads element t + T e and leaves in z[s] the point
+        // s + E bitrev(t / 64) + E (T / 64) bitrev6(t % 64) of the row.
+        auto ld2 = [&](auto xp_c, auto lanes_c) {
+          constexpr bool XP = decltype(xp_c)::value, PERMUTED = decltype(lanes_c)::value;
+          using HL = HbmLayout<N, E, XP>;
+          cpx<real> xa[HL::IT][HL::R], xb[HL::IT][HL::R];
+          auto elem = [&](int it, int r) { return HL::elem(t, it, r); };
+          auto live = [&](int it) { return HL::live(t, it); };
 #pragma unroll
-        for (int it = 0; it < HL::IT; ++it)
+          for (int it = 0; it < HL::IT; ++it)
 #pragma unroll
-          for (int r = 0; r < HL::R; ++r) {
-            const int p = elem(it, r);
-            const bool pos = p < S::KR * T, neg = p > S::NEG0 * T;  // kept band, upper half by symmetry
-            xa[it][r] = {(real)0, (real)0};
-            xb[it][r] = {(real)0, (real)0};
-            if (in_row && live(it) && (pos || neg)) {
-              const int idx = mix_index<real>(pos ? p : N - p, row, a.rows);
-              xa[it][r] = gload(Fa, idx);
-              if (has_b) xb[it][r] = gload(Fb, idx);
-            }
-          }
-        float ma = 0.f, mb = 0.f;
-        {
-          constexpr int NC = S::KR * T;  // nx / 2 columns
-          const float *ca = a.colmax + (long long)op.fa * NC;
-          const float *cb = a.colmax + (long long)(has_b ? op.fb : op.fa) * NC;
-          const int lane = threadIdx.x & 63;
-#pragma unroll
-          for (int c = lane; c < NC; c += 64) {
-            ma = fmaxf(ma, gload1(ca, c));
-            mb = fmaxf(mb, gload1(cb, c));
-          }
-          ma = wave_max(ma);
-          mb = wave_max(mb);
-        }
-        const float2 pa = pow2_scale(ma);
-        const float2 pb = has_b ? pow2_scale(mb) : make_float2(1.f, 1.f);
-        const real sa = (real)pa.x, sb = (real)pb.x;
-#pragma unroll
-        for (int it = 0; it < HL::IT; ++it)
-#pragma unroll
-          for (int r = 0; r < HL::R; ++r) {
-            const int p = elem(it, r);
-            const bool pos = p < S::KR * T, neg = p > S::NEG0 * T;
-            cpx<real> za = xa[it][r], zbr = xb[it][r];
-            if (pos || neg) {
-              const real kxv = (real)(a.kx_scale * (pos ? p : N - p));
-              if (dxa) za = {-kxv * za.y, kxv * za.x};
-              if (dxb) zbr = {-kxv * zbr.y, kxv * zbr.x};
-              if (neg) {
-                za.y = -za.y;
-                zbr.y = -zbr.y;
+            for (int r = 0; r < HL::R; ++r) {
+              const int p = elem(it, r);
+              const bool pos = p < S::KR * T, neg = p > S::NEG0 * T;  // kept band, upper half by symmetry
+              xa[it][r] = {(real)0, (real)0};
+              xb[it][r] = {(real)0, (real)0};
+              if (in_row && live(it) && (pos || neg)) {
+                const int idx = mix_index<real>(pos ? p : N - p, row, a.rows);
+                xa[it][r] = gload(Fa, idx);
+                if (has_b) xb[it][r] = gload(Fb, idx);
               }
             }
-            xa[it][r] = {za.x * sa - zbr.y * sb, za.y * sa + zbr.x * sb};
-          }
-        settle_tw();
-        fft_in<real, N, E, NB, +1, XP>(xa, z, b0, b1, tw, t);
-        const real ia = (real)pa.y, ib = (real)pb.y;
+          float ma = 0.f, mb = 0.f;
+          {
+            constexpr int NC = S::KR * T;  // nx / 2 columns
+            const float *ca = a.colmax + (long long)op.fa * NC;
+            const float *cb = a.colmax + (long long)(has_b ? op.fb : op.fa) * NC;
+            const int lane = threadIdx.x & 63;
 #pragma unroll
-        for (int e = 0; e < E; ++e) z[e] = {z[e].x * ia, z[e].y * ib};
+            for (int c = lane; c < NC; c += 64) {
+              ma = fmaxf(ma, gload1(ca, c));
+              mb = fmaxf(mb, gload1(cb, c));
+            }
+            ma = wave_max(ma);
+            mb = wave_max(mb);
+          }
+          const float2 pa = pow2_scale(ma);
+          const float2 pb = has_b ? pow2_scale(mb) : make_float2(1.f, 1.f);
+          const real sa = (real)pa.x, sb = (real)pb.x;
+#pragma unroll
+          for (int it = 0; it < HL::IT; ++it)
+#pragma unroll
+            for (int r = 0; r < HL::R; ++r) {
+              const int p = elem(it, r);
+              const bool pos = p < S::KR * T, neg = p > S::NEG0 * T;
+              cpx<real> za = xa[it][r], zbr = xb[it][r];
+              if (pos || neg) {
+                const real kxv = (real)(a.kx_scale * (pos ? p : N - p));
+                if (dxa) za = {-kxv * za.y, kxv * za.x};
+                if (dxb) zbr = {-kxv * zbr.y, kxv * zbr.x};
+                if (neg) {
+                  za.y = -za.y;
+                  zbr.y = -zbr.y;
+                }
+              }
+              xa[it][r] = {za.x * sa - zbr.y * sb, za.y * sa + zbr.x * sb};
+            }
+          settle_tw();
+          if constexpr (PERMUTED) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) z[e] = xa[0][e];
+            perm_ifft<real, T, E, +1>(z, b0, b1, tw, t);
+          } else {
+            fft_in<real, N, E, NB, +1, XP>(xa, z, b0, b1, tw, t);
+          }
+          const real ia = (real)pa.y, ib = (real)pb.y;
+#pragma unroll
+          for (int e = 0; e < E; ++e) z[e] = {z[e].x * ia, z[e].y * ib};
+        };
+        if constexpr (LANES) ld2(std::false_type{}, std::true_type{});
+        else ld2(std::integral_constant<bool, T <= 512 && S::PADDED>{}, std::false_type{});
         break;
       }
       case OP_LDP: {
@@ -590,7 +625,10 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
 #pragma unroll
         for (int e = 0; e < E; ++e) z[e] = {z[e].x * sx, z[e].y * sy};
         settle_tw();
-        const cpx<real> *res = team_fft<real, N, E, NB, -1>(z, b0, b1, tw, t);
+        const cpx<real> *res;
+        // (team_max2's barriers follow every earlier read of the buffers)
+        if constexpr (LANES) res = perm_fft<real, T, E, -1, false>(z, b0, b1, tw, t);
+        else res = team_fft<real, N, E, NB, -1>(z, b0, b1, tw, t);
         cpx<real> *Fa = a.mix + (long long)op.fa * a.mix_stride;
         cpx<real> *Fb = a.mix + (long long)(op.fb >= 0 ? op.fb : 0) * a.mix_stride;
         const real hx = (real)0.5 * (real)px.y, hy = (real)0.5 * (real)py.y;
@@ -1012,7 +1050,7 @@ struct PhysArgs {
 __device__ __forceinline__ BatchItem item_of(const BatchItem *items, int tile0, int first0) {
   return items ? items[blockIdx.y] : BatchItem{tile0, first0 + (int)blockIdx.y};
 }
-template <typename real, int T, int E, bool PAD = (E % 3 == 0)>
+template <typename real, int T, int E, bool PAD = (E % 3 == 0), bool LANES = false>
 __global__ __launch_bounds__(T > 256 ? T : 256) void row_kernel_batch(const RowArgs<real> *__restrict__ args,
                                                         const BatchItem *__restrict__ items, int tile0, int first0,
                                                         const void *sched0, PhysArgs ph) {
@@ -1025,7 +1063,7 @@ __global__ __launch_bounds__(T > 256 ? T : 256) void row_kernel_batch(const RowA
     a.pout0 = ph.out0;
     a.pout1 = ph.out1;
   }
-  row_body<real, T, E, false, 0, PAD>(a, it.index, blockIdx.x, static_cast<const RowProg *>(sched0));
+  row_body<real, T, E, false, 0, PAD, LANES>(a, it.index, blockIdx.x, static_cast<const RowProg *>(sched0));
 }
 // LIFTSYM: the variant that applies ColOut.lift_sym (the bulk velocity
 // lift's column launches); the plain passes never carry its exponentials.
@@ -1152,6 +1190,24 @@ inline bool axis_len_ok(int n) {
 template <typename real>
 hipError_t launch_batch_row(int T, int E, bool pad, dim3 grid, hipStream_t s, const RowArgs<real> *args,
                             const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph);
+// The padded row kernels in the permuted-layout form (ZK_ROW_FFT_LANES),
+// built for every padded row shape with row_lanes_ok: the kernel, or nullptr;
+// the launch, or hipErrorInvalidValue.
+template <typename real>
+const void *lanes_row_kernel(int T, int E);
+template <>
+const void *lanes_row_kernel<double>(int T, int E);
+template <>
+const void *lanes_row_kernel<float>(int T, int E);
+template <typename real>
+hipError_t launch_lanes_row(int T, int E, dim3 grid, hipStream_t s, const RowArgs<real> *args, const BatchItem *items,
+                            int tile0, int first0, const void *sched0, PhysArgs ph);
+template <>
+hipError_t launch_lanes_row<double>(int, int, dim3, hipStream_t, const RowArgs<double> *, const BatchItem *, int, int,
+                                    const void *, PhysArgs);
+template <>
+hipError_t launch_lanes_row<float>(int, int, dim3, hipStream_t, const RowArgs<float> *, const BatchItem *, int, int,
+                                   const void *, PhysArgs);
 template <typename real>
 hipError_t launch_batch_col(int T, int E, bool pad, dim3 grid, hipStream_t s, const ColArgs<real> *args,
                             const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph);

@@ -18,10 +18,12 @@ ZK_OPT_INTEGRATOR = 7
 ZK_INTEGRATOR_RK4, ZK_INTEGRATOR_IFAB2 = 0, 1
 ZK_OPT_BOUNDARY = 8
 ZK_BC_PERIODIC, ZK_BC_REFLECT = 0, 1
+ZK_OPT_ROW_FFT = 9
+ZK_ROW_FFT_STOCKHAM, ZK_ROW_FFT_LANES = 0, 1
 ZK_KERNEL_ROW_PAD, ZK_KERNEL_ROW_BASE, ZK_KERNEL_COL_PAD, ZK_KERNEL_COL_BASE, ZK_KERNEL_REDUCE = 0, 1, 2, 3, 4
 KERNEL_NAMES = {0: "row_pad", 1: "row_base", 2: "col_pad", 3: "col_base", 4: "reduce"}
 
-EXPORTS = ("zk_create", "zk_destroy", "zk_set_option", "zk_workspace_bytes", "zk_bind", "zk_dtn",
+EXPORTS = ("zk_create", "zk_destroy", "zk_set_option", "zk_get_option", "zk_workspace_bytes", "zk_bind", "zk_dtn",
            "zk_rhs", "zk_step", "zk_step_static", "zk_hamiltonian", "zk_kernel_stats", "zk_autotune", "zk_team_shape", "zk_inverse_dtn",
            "zk_depth_velocity", "zk_set_team_shape", "zk_last_error",
            "zk_cnn_create", "zk_cnn_destroy", "zk_cnn_workspace_bytes", "zk_cnn_bind", "zk_cnn_set_params",
@@ -66,6 +68,8 @@ def lib():
     L.zk_destroy.restype = None
     L.zk_set_option.argtypes = [vp, i, d]
     L.zk_set_option.restype = i
+    L.zk_get_option.argtypes = [vp, i, ctypes.POINTER(d)]
+    L.zk_get_option.restype = i
     L.zk_workspace_bytes.argtypes = [vp]
     L.zk_workspace_bytes.restype = sz
     L.zk_bind.argtypes = [vp, vp, sz, vp]
@@ -173,6 +177,12 @@ def zk_destroy(ctx):
 
 def zk_set_option(ctx, key, value):
     return _check(ctx, lib().zk_set_option(ctx, int(key), float(value)))
+
+
+def zk_get_option(ctx, key):
+    v = ctypes.c_double(0.0)
+    _check(ctx, lib().zk_get_option(ctx, int(key), ctypes.byref(v)))
+    return v.value
 
 
 def zk_workspace_bytes(ctx):
@@ -320,6 +330,9 @@ class Solver:
 
     def set_option(self, key, value):
         zk_set_option(self.ctx, key, value)
+
+    def get_option(self, key):
+        return zk_get_option(self.ctx, key)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -7,7 +7,8 @@ k, conjugated for the inverse sign), and the three forms: team_fft (result in
 LDS, natural order), team_fft_keep (the last pass's butterfly j keeps
 elements j + NB r in registers) and team_fft_t (the passes transposed, input
 in that last-pass layout, output element t + T r in registers).  Each is
-checked against numpy's FFT for every team shape the kernels compile."""
+checked against numpy's FFT for every team shape the kernels compile; so are
+the permuted-layout forms of the padded row passes (perm_ifft, perm_fft)."""
 import numpy as np
 import pytest
 
@@ -130,3 +131,126 @@ def test_twiddle_table_slots_are_distinct_and_in_range(T, E):
                 i = ns - E + (r - 1) * ns + k
                 assert 0 <= i < N - E and i not in seen
                 seen.add(i)
+
+
+# ---- the permuted-layout forms (perm_ifft / perm_fft) --------------------------
+# Team of T = 64 W threads, thread t = 64 w + l; twiddles from the natural table
+# W_N^m (forward sign, conjugated for DIR > 0).  Index arithmetic as in the
+# kernels: radix-E step and W_N^(64 w q); wavefront stages (radix 4 over spans
+# (hw, hw/2) while two bits remain, else radix 2), decimation in frequency for
+# the inverse; W_N^(l (q + E bitrev(w))); six radix-2 lane stages l ^ h.
+LANE_SHAPES = [(T, E) for T, E in SHAPES if T % 64 == 0 and E % 3 == 0]
+
+
+def natural(N, m, DIR):
+    w = np.exp(-2j * np.pi * m / N)
+    return np.conj(w) if DIR > 0 else w
+
+
+def bitrev(x, bits):
+    return int(format(x, f"0{bits}b")[::-1], 2) if bits else 0
+
+
+def xw_spans(W):
+    out, hw = [], W // 2
+    while hw >= 1:
+        out.append(hw)
+        hw = hw // 4 if hw >= 2 else hw // 2
+    return out
+
+
+def lane_stages(V, N, DIR, dif):
+    l = np.arange(64)
+    for h in ([32, 16, 8, 4, 2, 1] if dif else [1, 2, 4, 8, 16, 32]):
+        B = (l & h) != 0
+        sg = np.where(B, -1.0, 1.0)[:, None]
+        ws = np.array([natural(N, (li & (h - 1)) * (N // (2 * h)), DIR) if (li & h) and h > 1 else 1.0
+                       for li in l])[:, None]
+        if dif:
+            V = (V[l ^ h] + sg * V) * ws
+        else:
+            c = V * ws
+            V = c[l ^ h] + sg * c
+    return V
+
+
+def xw_stage(v, T, E, N, hw, DIR, dif):
+    out = np.zeros_like(v)
+    iD = 1j * DIR
+    for t in range(T):
+        w = t // 64
+        if hw == 1:
+            p = v[t ^ 64]
+            out[t] = (p - v[t]) if w & 1 else v[t] + p
+            continue
+        h2 = hw // 2
+        t0 = t & ~(96 * hw)
+        w0 = w & ~(hw | h2)
+        B1, B0 = w & hw, w & h2
+        w1 = natural(N, (w0 % hw) * (N // (2 * hw)), DIR)
+        w2 = natural(N, (w0 % h2) * (N // hw), DIR)
+        i0, i1, i2, i3 = v[t0], v[t0 + 32 * hw], v[t0 + 64 * hw], v[t0 + 96 * hw]
+        if dif:
+            x0 = (i0 - i2) * w1 if B1 else i0 + i2
+            x1 = (i1 - i3) * w1 * iD if B1 else i1 + i3
+            out[t] = (x0 - x1) * w2 if B0 else x0 + x1
+        else:
+            c = i0 - w2 * i1 if B0 else i0 + w2 * i1
+            d = i2 - w2 * i3 if B0 else i2 + w2 * i3
+            fd = d * w1 * iD if B0 else d * w1
+            out[t] = c - fd if B1 else c + fd
+    return out
+
+
+def perm_ifft(x, T, E, DIR):
+    N, W = T * E, T // 64
+    v = np.array([small_dft(x[t + T * np.arange(E)], DIR) for t in range(T)])
+    for t in range(T):
+        v[t] *= natural(N, 64 * (t // 64) * np.arange(E), DIR)
+    for hw in xw_spans(W):
+        v = xw_stage(v, T, E, N, hw, DIR, True)
+    for t in range(T):
+        kb = bitrev(t // 64, W.bit_length() - 1)
+        v[t] *= natural(N, (t % 64) * (np.arange(E) + E * kb), DIR)
+    for w in range(W):
+        v[64 * w:64 * w + 64] = lane_stages(v[64 * w:64 * w + 64], N, DIR, True)
+    return v
+
+
+def perm_fft(y, T, E, DIR):
+    N, W = T * E, T // 64
+    v = y.copy()
+    for w in range(W):
+        v[64 * w:64 * w + 64] = lane_stages(v[64 * w:64 * w + 64], N, DIR, False)
+    for t in range(T):
+        kb = bitrev(t // 64, W.bit_length() - 1)
+        v[t] *= natural(N, (t % 64) * (np.arange(E) + E * kb), DIR)
+    for hw in reversed(xw_spans(W)):
+        v = xw_stage(v, T, E, N, hw, DIR, False)
+    for t in range(T):
+        v[t] *= natural(N, 64 * (t // 64) * np.arange(E), DIR)
+    return np.array([small_dft(v[t], DIR) for t in range(T)])
+
+
+def lanes_perm(T, E):
+    W = T // 64
+    return np.array([[s + E * bitrev(t // 64, W.bit_length() - 1) + E * W * bitrev(t % 64, 6) for s in range(E)]
+                     for t in range(T)])
+
+
+@pytest.mark.parametrize("T,E", LANE_SHAPES)
+def test_permuted_forms_match_numpy(T, E):
+    """perm_ifft: natural order in, the transform at point s + E bitrev(w) +
+    E W bitrev6(l) in thread t's register s; perm_fft: that order in, natural
+    order out (element t + T r in register r); both against numpy's FFT."""
+    N = T * E
+    P = lanes_perm(T, E)
+    assert sorted(P.ravel().tolist()) == list(range(N))
+    rng = np.random.default_rng(T * 7 + E)
+    x = rng.standard_normal((N, 2)) @ np.array([1, 1j])
+    ref = np.fft.ifft(x) * N
+    assert np.abs(perm_ifft(x, T, E, +1) - ref[P]).max() / np.abs(ref).max() < 1e-13
+    F = np.fft.fft(x)
+    got = perm_fft(x[P], T, E, -1)
+    want = np.array([[F[t + T * r] for r in range(E)] for t in range(T)])
+    assert np.abs(got - want).max() / np.abs(F).max() < 1e-13
