@@ -624,6 +624,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default team shapes")
+    ap.add_argument("--row-fft", choices=("auto", "stockham", "lanes"), default="auto",
+                    help="form of the padded row transforms (auto: the autotuner's choice)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision-form (2048^2 M=5), closure-form (1024^2) and batch-form (256 tiles) runs")
     ap.add_argument("--headline-only", action="store_true",
@@ -667,6 +669,8 @@ def main():
     p = torch.tensor(psi, dtype=torch.float64, device=dev)
 
     shapes = s.autotune(w["dt"], reps=3) if not args.no_autotune else s.team_shapes()
+    if args.row_fft != "auto":
+        s.set_option(ZK_OPT_ROW_FFT, ZK_ROW_FFT_LANES if args.row_fft == "lanes" else 0)
     # warmup (also uploads the dt-dependent schedule)
     if args.warmup > 0:
         s.step(e, p, w["dt"], args.warmup)

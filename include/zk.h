@@ -147,7 +147,9 @@ void zk_destroy(zk_ctx *ctx);
 /* Set an option (keys above).  EPS, TAPER and FILTER may change at any time
  * and apply from the next call; PRECISION must be set before zk_bind. */
 int zk_set_option(zk_ctx *ctx, int key, double value);
-/* Current value of an option (as set, or as zk_autotune left it).  ZK_EINVAL
+/* Current value of an option (as set, or as zk_autotune left it; for
+ * ZK_OPT_ROW_FFT the form the padded row passes run in at the current team
+ * shape, which is STOCKHAM where the shape has no LANES form).  ZK_EINVAL
  * for an unknown key or a null pointer. */
 int zk_get_option(const zk_ctx *ctx, int key, double *value);
 

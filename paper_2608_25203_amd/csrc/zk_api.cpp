@@ -607,7 +607,13 @@ int zk_get_option(const zk_ctx *c, int key, double *v) {
     case ZK_OPT_PROFILE: *v = c->prof ? 1.0 : 0.0; break;
     case ZK_OPT_INTEGRATOR: *v = c->integrator; break;
     case ZK_OPT_BOUNDARY: *v = c->bc; break;
-    case ZK_OPT_ROW_FFT: *v = c->row_fft; break;
+    case ZK_OPT_ROW_FFT: {  // the form the padded row passes run in at the current team shape
+      const TeamShape sh = ctx_team(c, true, true);
+      *v = c->row_fft == ZK_ROW_FFT_LANES && row_lanes_ok(sh.T, sh.E, true, c->precision == 32 ? 4 : 8)
+               ? ZK_ROW_FFT_LANES
+               : ZK_ROW_FFT_STOCKHAM;
+      break;
+    }
     default: return ZK_EINVAL;
   }
   return ZK_OK;
