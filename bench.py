@@ -176,13 +176,14 @@ def precision_form(segments=(1, 9, 90, 400)):
             "within_1e-4": bool(worst <= 1e-4), "team_shapes": shapes}
 
 
-def closure_form(nsteps=1000, audit_every=10, tol=1e-4):
+def closure_form(nsteps=1000, audit_every=10, tol=1e-4, floor_tol=2e-3):
     """Learned closure on its training geometry (1024 x 1024, 2 pi, deep,
     k_p = 32, dt = 0.007, JONSWAP steepness 0.1, seed 42) against plain
     order 6 in FP64 over nsteps RK4 steps: grid-point-steps/s and the max
     relative eta error of order 2 alone, of order 2 + network (low order in
     FP64 and in FP32), and of the audited closure (audit every `audit_every`
-    steps, fallback to order 6 while the DtN error exceeds `tol`)."""
+    steps, fallback to order 6 while the DtN error exceeds `tol`; again at
+    `floor_tol`, above the network's error floor)."""
     import json as _json
 
     import numpy as np
@@ -225,28 +226,34 @@ def closure_form(nsteps=1000, audit_every=10, tol=1e-4):
            "unit": "grid-point-steps/s", "order6_fp64_value": round(n * n * nsteps / t6, 1)}
     cases = {"order2_fp64": lambda e, p, k: low64.step(e, p, dt, k),
              "closure_fp64": lambda e, p, k: clo64.step(e, p, dt, k),
-             "closure_fp32": lambda e, p, k: clo32.step(e, p, dt, k),
-             "closure_audited_fp32": lambda e, p, k: clo32.step(e, p, dt, k, audit_every, tol)}
+             "closure_fp32": lambda e, p, k: clo32.step(e, p, dt, k)}
     for name, adv in cases.items():
-        if name == "closure_audited_fp32":
-            clo32.close()
-            clo32 = Closure(low32, full, net, meta["k0"], meta["eta_scale"], meta["out_scale"])
-            adv = lambda e, p, k: clo32.step(e, p, dt, k, audit_every, tol)  # noqa: E731
-        e, t = run(adv, warm=name != "closure_audited_fp32")
+        e, t = run(adv)
         out[name] = {"value": round(n * n * nsteps / t, 1), "speedup_vs_order6": round(t6 / t, 3),
                      "eta_rel_err_vs_order6": rel_max(e, e6)}
         print(f"# closure form: {name} {t:.2f} s, eta err {out[name]['eta_rel_err_vs_order6']:.3e}",
               file=sys.stderr, flush=True)
-    st = clo32.stats()
-    out["closure_audited_fp32"].update({"audit_every": audit_every, "tol": tol, "closure_steps": st["closure_steps"],
-                                        "fallback_steps": st["fallback_steps"], "audits": st["audits"],
-                                        "acceptance_rate": st["closure_steps"] / max(1, nsteps),
-                                        "max_audited_dtn_err": st["max_err"]})
+    # audited runs: at the benchmark's tolerance, and at one just above the
+    # network's DtN error floor on this workload (which it can pass)
+    for name, tl in (("closure_audited_fp32", tol), ("closure_audited_fp32_above_floor", floor_tol)):
+        clo32.close()
+        clo32 = Closure(low32, full, net, meta["k0"], meta["eta_scale"], meta["out_scale"])
+        e, t = run(lambda e, p, k: clo32.step(e, p, dt, k, audit_every, tl), warm=False)  # noqa: B023
+        st = clo32.stats()
+        out[name] = {"value": round(n * n * nsteps / t, 1), "speedup_vs_order6": round(t6 / t, 3),
+                     "eta_rel_err_vs_order6": rel_max(e, e6), "audit_every": audit_every, "tol": tl,
+                     "closure_steps": st["closure_steps"], "fallback_steps": st["fallback_steps"],
+                     "audits": st["audits"], "acceptance_rate": st["closure_steps"] / max(1, nsteps),
+                     "max_audited_dtn_err": st["max_err"]}
+        print(f"# closure form: {name} {t:.2f} s, accepted {st['closure_steps']} of {nsteps}", file=sys.stderr,
+              flush=True)
+    st = out["closure_audited_fp32"]
     if st["closure_steps"] < nsteps / 2:
         out["note"] = (f"the audited closure accepted {st['closure_steps']} of {nsteps} steps at tol {tol:g} (largest "
-                       f"audited DtN error {st['max_err']:.2e}): the network's DtN error sits above the tolerance, so "
-                       "of the reduced forms only the FP32 precision form meets the 1e-4 bound with a speed-up "
-                       "(precision_form); the unaudited closure rows are speed and eta error without that bound")
+                       f"audited DtN error {st['max_audited_dtn_err']:.2e}): the network's DtN error sits above the "
+                       "tolerance, so of the reduced forms only the FP32 precision form meets the 1e-4 bound with a "
+                       "speed-up (precision_form); the unaudited closure rows are speed and eta error without that "
+                       f"bound, and closure_audited_fp32_above_floor is the audited form at tol {floor_tol:g}")
     for o in (clo64, clo32, net, low64, low32, full):
         o.close()
     torch.cuda.empty_cache()
@@ -563,7 +570,7 @@ def paper_tank(nsteps=2000):
     return out
 
 
-def c2_diagnostics(w, H_before, H_after):
+def c2_diagnostics(w, H_before, H_after, timed_steps):
     """Hamiltonian drift of the timed run and the linear-limit dispersion error
     (eps = 0, filter off) of single modes on the benchmark grid: measured
     frequency against omega = sqrt(g k tanh(k h)), beside the closed form
@@ -573,7 +580,8 @@ def c2_diagnostics(w, H_before, H_after):
 
     from paper_2608_25203_amd.zk import Solver
 
-    out = {"H_drift_rel": (H_after - H_before) / H_before}
+    # H_drift_rel spans the timed run (timed_steps steps, filter on)
+    out = {"H_drift_rel": (H_after - H_before) / H_before, "H_drift_steps": timed_steps}
     dev = torch.device("cuda:0")
     # the same run with the state filter off separates its damping from the drift
     from paper_2608_25203_amd.inputs import jonswap_state
@@ -586,7 +594,7 @@ def c2_diagnostics(w, H_before, H_after):
     H0 = s.hamiltonian(e, p)
     s.step(e, p, w["dt"], w["steps"])
     out["H_drift_rel_filter_off"] = (s.hamiltonian(e, p) - H0) / H0
-    out["H_drift_steps"] = w["steps"]
+    out["H_drift_filter_off_steps"] = w["steps"]
     s.close()
     nx, ny, Lx, h, g, dt = w["nx"], w["ny"], w["Lx"], w["depth"], w["g"], w["dt"]
     s = Solver(nx, ny, Lx, w["Ly"], h, g, w["M"], eps=0.0, filt=False, check=False, device=dev)
@@ -755,7 +763,7 @@ def main():
     if args.headline_only:
         args.no_forms = args.no_cpu_baseline = True
     elif args.workload == "c2_512_m4":
-        out["c2_diagnostics"] = c2_diagnostics(w, H_before, H_after)
+        out["c2_diagnostics"] = c2_diagnostics(w, H_before, H_after, args.steps)
         out["c2_diagnostics"]["H_before"] = H_before
         out["ifab2_form"] = ifab2_form(w, args.warmup, args.steps, value, e_timed)
         out["paper_tank"] = paper_tank()
