@@ -18,7 +18,7 @@ FOLD_SHAPES = [(T, E) for T in (64, 128, 256) for E in (2, 3)]  # as fold_team_s
 def lanes_ok(T, E, pad, real_bytes):
     """as row_lanes_ok() in zk_kernels.hpp"""
     N, tpb = T * E, max(T, 256) // T
-    return pad and T % 64 == 0 and T <= 1024 and (2 * tpb * N + N) * 2 * real_bytes <= 100 * 1024
+    return pad and T % 64 == 0 and T <= 1024 and 2 * tpb * N * 2 * real_bytes <= 100 * 1024
 
 
 def bs(T):

@@ -219,13 +219,19 @@ template <>
 const void *lanes_row_kernel<double>(int T, int E) {
   if (T == 64 && E == 3) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 3, true, true>);
   if (T == 64 && E == 6) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 6, true, true>);
+  if (T == 64 && E == 12) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 12, true, true>);
   if (T == 128 && E == 3) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 3, true, true>);
   if (T == 128 && E == 6) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 6, true, true>);
+  if (T == 128 && E == 12) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 12, true, true>);
   if (T == 256 && E == 3) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 3, true, true>);
   if (T == 256 && E == 6) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 6, true, true>);
+  if (T == 256 && E == 12) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 12, true, true>);
   if (T == 512 && E == 3) return reinterpret_cast<const void *>(&row_kernel_batch<double, 512, 3, true, true>);
+  if (T == 512 && E == 6) return reinterpret_cast<const void *>(&row_kernel_batch<double, 512, 6, true, true>);
+  if (T == 1024 && E == 3) return reinterpret_cast<const void *>(&row_kernel_batch<double, 1024, 3, true, true>);
   if (T == 64 && E == 9) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 9, true, true>);
   if (T == 128 && E == 9) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 9, true, true>);
+  if (T == 256 && E == 9) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 9, true, true>);
   return nullptr;
 }
 
@@ -240,12 +246,20 @@ hipError_t launch_lanes_row<double>(int T, int E, dim3 grid, hipStream_t s, cons
     hipLaunchKernelGGL((row_kernel_batch<double, 64, 6, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
+  if (T == 64 && E == 12) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 64, 12, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
   if (T == 128 && E == 3) {
     hipLaunchKernelGGL((row_kernel_batch<double, 128, 3, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 128 && E == 6) {
     hipLaunchKernelGGL((row_kernel_batch<double, 128, 6, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 12) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 128, 12, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 256 && E == 3) {
@@ -256,8 +270,20 @@ hipError_t launch_lanes_row<double>(int T, int E, dim3 grid, hipStream_t s, cons
     hipLaunchKernelGGL((row_kernel_batch<double, 256, 6, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
+  if (T == 256 && E == 12) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 256, 12, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
   if (T == 512 && E == 3) {
     hipLaunchKernelGGL((row_kernel_batch<double, 512, 3, true, true>), grid, dim3(512), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 512 && E == 6) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 512, 6, true, true>), grid, dim3(512), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 1024 && E == 3) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 1024, 3, true, true>), grid, dim3(1024), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 64 && E == 9) {
@@ -266,6 +292,10 @@ hipError_t launch_lanes_row<double>(int T, int E, dim3 grid, hipStream_t s, cons
   }
   if (T == 128 && E == 9) {
     hipLaunchKernelGGL((row_kernel_batch<double, 128, 9, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 256 && E == 9) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 256, 9, true, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;

@@ -222,10 +222,11 @@ __device__ __forceinline__ float2 pow2_scale(float m) {
 // slot "first negative, t = 0" is the Nyquist mode (never stored).
 // Whether a row team shape (T threads, E elements, default block of
 // max(T, 256) threads) has the permuted-layout transforms: padded, whole
-// wavefronts, and two LDS buffers per team (the rule of Shape::nbuf).
+// wavefronts, and room for two LDS buffers per team (the twiddle table goes
+// to LDS only if it fits beside them).
 __host__ __device__ constexpr bool row_lanes_ok(int T, int E, bool padded, int real_bytes) {
   const int N = T * E, tpb = (T > 256 ? T : 256) / T;
-  return padded && T % 64 == 0 && T <= 1024 && (2 * tpb * N + N) * 2 * real_bytes <= 100 * 1024;
+  return padded && T % 64 == 0 && T <= 1024 && 2 * tpb * N * 2 * real_bytes <= 100 * 1024;
 }
 
 template <int T, int E, int BSZ = 0, bool PAD = (E % 3 == 0)>
@@ -238,14 +239,15 @@ struct Shape {
   static constexpr int BS = BSZ ? BSZ : (T > 256 ? T : 256);  // threads per block (default max(T, 256))
   static constexpr int TPB = BS / T;                   // teams per block
   static constexpr int L = lds_len(N);
-  // two LDS buffers per team when they fit comfortably, else one
-  template <typename real>
+  // two LDS buffers per team when they fit comfortably beside the twiddle
+  // table, else one (the permuted-layout forms, LANES, always take two)
+  template <typename real, bool LANES = false>
   static constexpr int nbuf() {
-    return (2 * TPB * L + N) * (int)sizeof(cpx<real>) <= 100 * 1024 ? 2 : 1;
+    return LANES || (2 * TPB * L + N) * (int)sizeof(cpx<real>) <= 100 * 1024 ? 2 : 1;
   }
-  template <typename real>
+  template <typename real, bool LANES = false>
   static constexpr bool tw_in_lds() {
-    return (nbuf<real>() * TPB * L + N) * (int)sizeof(cpx<real>) <= 100 * 1024;
+    return (nbuf<real, LANES>() * TPB * L + N) * (int)sizeof(cpx<real>) <= 100 * 1024;
   }
   // Padded row passes of whole-wavefront teams with two buffers can also run
   // their transforms in the permuted layout with lane-exchange butterflies
@@ -343,11 +345,11 @@ __device__ __forceinline__ void stage_twiddles(cpx<R> *dst, const cpx<R> *src) {
 // standalone kernels declare them as static arrays; the persistent batch
 // kernel (DYN) carves them from one dynamic region that every team shape it
 // hosts shares, sized on the host from these functions.
-template <typename real, int T, int E, int BSZ = 0, bool PAD = (E % 3 == 0)>
+template <typename real, int T, int E, int BSZ = 0, bool PAD = (E % 3 == 0), bool LANES = false>
 struct BodyLds {
   using S = Shape<T, E, BSZ, PAD>;
-  static constexpr int TWN = S::template tw_in_lds<real>() ? S::N : 16 / (int)sizeof(cpx<real>);
-  static constexpr int BUF = S::TPB * S::template nbuf<real>() * S::L;  // row and plain column bodies
+  static constexpr int TWN = S::template tw_in_lds<real, LANES>() ? S::N : 16 / (int)sizeof(cpx<real>);
+  static constexpr int BUF = S::TPB * S::template nbuf<real, LANES>() * S::L;  // row and plain column bodies
   static constexpr int RED = 2 * (S::BS / 64);
   static constexpr int bytes() { return (BUF + TWN) * (int)sizeof(cpx<real>) + RED * (int)sizeof(float); }
 };
@@ -366,8 +368,8 @@ struct BatchItem {
 template <typename real, int T, int E, bool DYN = false, int BSZ = 0, bool PAD = (E % 3 == 0), bool LANES = false>
 __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int blk, const RowProg *progs0) {
   using S = Shape<T, E, BSZ, PAD>;
-  constexpr int N = S::N, L = S::L, NB = S::template nbuf<real>();
-  constexpr bool TWL = S::template tw_in_lds<real>();
+  constexpr int N = S::N, L = S::L, NB = S::template nbuf<real, LANES>();
+  constexpr bool TWL = S::template tw_in_lds<real, LANES>();
   static_assert(!LANES || S::template lanes_ok<real>(), "no permuted-layout form for this shape");
   // A single grid passes its program table as a kernel argument, so the
   // program record loads alongside the argument record, not after it (the
@@ -379,7 +381,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   } else {
     pg = uniform_load(a.progs + prog);
   }
-  using LD = BodyLds<real, T, E, BSZ, PAD>;
+  using LD = BodyLds<real, T, E, BSZ, PAD, LANES>;
   cpx<real> *smem, *twl;
   float *red;
   if constexpr (DYN) {

@@ -34,13 +34,14 @@ def rel(a, b):
 # (nx, ny, M, precision, padded-row team size T): E = 3 nx / 2 / T
 CASES = [(128, 64, 4, 64, 64), (256, 128, 3, 64, 128), (512, 64, 4, 64, 256), (1024, 64, 3, 64, 512),
          (512, 64, 3, 64, 128), (512, 64, 3, 32, 64), (384, 64, 3, 64, 64), (768, 64, 2, 64, 128),
-         (1536, 64, 2, 32, 256), (256, 1, 4, 64, 128), (2048, 64, 2, 32, 1024)]
+         (1536, 64, 2, 32, 256), (256, 1, 4, 64, 128), (2048, 64, 2, 32, 1024), (2048, 64, 2, 64, 1024),
+         (1536, 64, 2, 64, 256), (512, 64, 3, 64, 64)]
 
 
 def lanes_built(T, E, real_bytes):
     """the shapes the permuted-layout row kernels are built for (row_lanes_ok)"""
     N, tpb = T * E, max(T, 256) // T
-    return T % 64 == 0 and T <= 1024 and (2 * tpb * N + N) * 2 * real_bytes <= 100 * 1024
+    return T % 64 == 0 and T <= 1024 and 2 * tpb * N * 2 * real_bytes <= 100 * 1024
 
 
 @pytest.mark.parametrize("nx,ny,M,prec,T", CASES)
