@@ -48,12 +48,15 @@ __global__ __launch_bounds__(256) void sumsq_partial(const double *__restrict__ 
   }
 }
 
-__global__ __launch_bounds__(64) void sumsq_final(const double *__restrict__ part, double *__restrict__ out) {
-  if (threadIdx.x < 2) {
-    double s = 0.0;
-    for (int i = 0; i < kRedBlocks; ++i) s += part[threadIdx.x * kRedBlocks + i];
-    out[threadIdx.x] = s;
-  }
+// One wavefront per sum: lane l adds the partials l, l + 64, ... in order,
+// then a butterfly over the lanes (fixed order: the same bits every run).
+__global__ __launch_bounds__(128) void sumsq_final(const double *__restrict__ part, double *__restrict__ out) {
+  const int which = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int i = lane; i < kRedBlocks; i += 64) s += part[which * kRedBlocks + i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) out[which] = s;
 }
 
 __global__ __launch_bounds__(256) void pack_kernel(const double *__restrict__ eta, const double *__restrict__ psi,
@@ -137,7 +140,7 @@ unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t sumsq(const double *a, const double *b, long long n, double *part, double *out, hipStream_t s) {
   hipLaunchKernelGGL(sumsq_partial, dim3(kRedBlocks), dim3(256), 0, s, a, b, n, part);
-  hipLaunchKernelGGL(sumsq_final, dim3(1), dim3(64), 0, s, (const double *)part, out);
+  hipLaunchKernelGGL(sumsq_final, dim3(1), dim3(128), 0, s, (const double *)part, out);
   return hipGetLastError();
 }
 hipError_t pack(const double *eta, const double *psi, const double *g2, const double *sum, long long n, double c_eta,
