@@ -6,6 +6,10 @@ namespace zk {
 
 template <>
 const void *batch_col_kernel<double>(int T, int E, bool pad) {
+  if (T == 16 && E == 2 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<double, 16, 2>);
+  if (T == 16 && E == 3 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<double, 16, 3>);
+  if (T == 16 && E == 4 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<double, 16, 4>);
+  if (T == 16 && E == 6 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<double, 16, 6>);
   if (T == 32 && E == 2 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<double, 32, 2>);
   if (T == 32 && E == 3 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<double, 32, 3>);
   if (T == 32 && E == 4 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<double, 32, 4>);
@@ -52,6 +56,22 @@ const void *batch_col_kernel<double>(int T, int E, bool pad) {
 template <>
 hipError_t launch_batch_col<double>(int T, int E, bool pad, dim3 grid, hipStream_t s, const ColArgs<double> *args,
                                    const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {
+  if (T == 16 && E == 2 && pad == false) {
+    hipLaunchKernelGGL((col_kernel_batch<double, 16, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 16 && E == 3 && pad == true) {
+    hipLaunchKernelGGL((col_kernel_batch<double, 16, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 16 && E == 4 && pad == false) {
+    hipLaunchKernelGGL((col_kernel_batch<double, 16, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 16 && E == 6 && pad == true) {
+    hipLaunchKernelGGL((col_kernel_batch<double, 16, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
   if (T == 32 && E == 2 && pad == false) {
     hipLaunchKernelGGL((col_kernel_batch<double, 32, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
@@ -218,6 +238,14 @@ hipError_t launch_batch_col<double>(int T, int E, bool pad, dim3 grid, hipStream
 template <>
 hipError_t launch_batch_col_lift<double>(int T, int E, dim3 grid, hipStream_t s, const ColArgs<double> *args,
                                         const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {
+  if (T == 16 && E == 2) {
+    hipLaunchKernelGGL((col_kernel_batch<double, 16, 2, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 16 && E == 4) {
+    hipLaunchKernelGGL((col_kernel_batch<double, 16, 4, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
   if (T == 32 && E == 2) {
     hipLaunchKernelGGL((col_kernel_batch<double, 32, 2, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();

@@ -675,3 +675,27 @@ def test_1d_stokes_regimes_through_c_abi(torch, ka, kh):
     m = HOSModel(Grid(nx, 1, TWO_PI, 1.0, kh), 3, filt=False)
     e0, p0 = m.step(eta, psi, dt, nst)
     assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
+
+
+@pytest.mark.parametrize("M", [2, 3, 4])
+@pytest.mark.parametrize("shape", [(32, 32), (64, 32), (32, 128), (1, 32)])
+def test_32_point_axes(torch, M, shape):
+    """Axes of 32 points (padded transforms of 48 points, teams of 16
+    threads) and a 1D grid of 32: G psi, the RHS and two RK4 steps at the
+    FP64 bar, random data filling the band, finite depth."""
+    ny, nx = shape
+    Lx, Ly, h = 1.0, max(1.0 * ny / nx, 0.05), 0.3
+    kmax = math.hypot(math.pi * nx / Lx, math.pi * ny / Ly)
+    eta, psi = random_band_fields(nx, ny, 90 + M, nx // 2 - 1 if ny == 1 else min(nx, ny) // 2 - 1,
+                                  amplitude=0.1 / kmax)
+    s = solver(torch, nx, ny, Lx, Ly, h, M)
+    print(" ", s.team_shapes(), flush=True)
+    m = HOSModel(Grid(nx, ny, Lx, Ly, h), M)
+    e, p = dev(torch, eta), dev(torch, psi)
+    assert rel(host(s.dtn(e, p)), m.dtn(eta, psi)) < 1e-10
+    a, b = s.rhs(e, p)
+    a0, b0 = m.rhs(eta, psi)
+    assert rel(host(a), a0) < 1e-10 and rel(host(b), b0) < 1e-10
+    s.step(e, p, 0.002, 2)
+    e0, p0 = m.step(eta, psi, 0.002, 2)
+    assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10

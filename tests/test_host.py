@@ -22,7 +22,8 @@ def rel(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
-@pytest.mark.parametrize("nx,ny", [(64, 64), (128, 64), (512, 512), (2048, 2048), (96, 96), (384, 64), (1536, 192)])
+@pytest.mark.parametrize("nx,ny", [(64, 64), (128, 64), (512, 512), (2048, 2048), (96, 96), (384, 64), (1536, 192),
+                                   (32, 32), (32, 128)])
 @pytest.mark.parametrize("M", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_plan_builds_and_validates(nx, ny, M):
     p = load_plan(nx, ny, M)
@@ -177,6 +178,13 @@ def test_library_host_side_argument_checks():
     assert not L.zk_create(63, 64, 1.0, 1.0, 1.0, 9.81, 3)       # neither 2^k nor 3 2^k
     assert not L.zk_create(100, 64, 1.0, 1.0, 1.0, 9.81, 3)      # neither 2^k nor 3 2^k
     assert not L.zk_create(48, 64, 1.0, 1.0, 1.0, 9.81, 3)       # 3 2^k below 96
+    assert not L.zk_create(16, 64, 1.0, 1.0, 1.0, 9.81, 3)       # 2^k below 32
+    c32 = L.zk_create(32, 32, 1.0, 1.0, 1.0, 9.81, 3)             # 2^k from 32 up: teams of 16
+    assert c32
+    T, E = ctypes.c_int(0), ctypes.c_int(0)
+    assert L.zk_team_shape(c32, 1, 1, ctypes.byref(T), ctypes.byref(E)) == 0 and (T.value, E.value) == (16, 3)
+    assert L.zk_team_shape(c32, 1, 0, ctypes.byref(T), ctypes.byref(E)) == 0 and (T.value, E.value) == (16, 2)
+    L.zk_destroy(c32)
     assert not L.zk_create(3072, 64, 1.0, 1.0, 1.0, 9.81, 3)     # 3 2^k above 1536
     for n in (96, 192, 384, 768, 1536):                            # 3 2^k axes are built
         c3 = L.zk_create(n, 64, 1.0, 1.0, 1.0, 9.81, 3)
