@@ -431,7 +431,7 @@ TeamShape ctx_team(const zk_ctx *c, bool row, bool pad) {
   sh.E = N / sh.T;
   const int tpb = sh.T < 256 ? 256 / sh.T : 1;
   // (rows of a 1D grid: 1, in a block whose other teams idle)
-  sh.blocks = row ? ((pad ? 3 * c->pp.ny / 2 : c->pp.ny) + tpb - 1) / tpb : (c->pp.nx / 2) / tpb;
+  sh.blocks = row ? ((pad ? 3 * c->pp.ny / 2 : c->pp.ny) + tpb - 1) / tpb : (c->pp.nx / 2 + tpb - 1) / tpb;
   return sh;
 }
 
@@ -863,7 +863,7 @@ int zk_autotune(zk_ctx *c, double dt, int reps) {
       for (int ci = 0; ci < ncand; ++ci) {
         const int E = cand[ci];
         const int T = N / E;
-        if (N % E || T < 16 || T > 1024 || (T & (T - 1))) continue;
+        if (N % E || T < 8 || T > 1024 || (T & (T - 1))) continue;
         const void *fn = c->precision == 32
                              ? (row ? batch_row_kernel<float>(T, E, pad) : batch_col_kernel<float>(T, E, pad))
                              : (row ? batch_row_kernel<double>(T, E, pad) : batch_col_kernel<double>(T, E, pad));
@@ -928,7 +928,7 @@ int zk_set_team_shape(zk_ctx *c, int row, int pad, int T) {
   const int n = row ? c->pp.nx : c->pp.ny;
   const int N = pad ? 3 * n / 2 : n;
   if (!row && n == 1) return fail(c, ZK_EINVAL, "a 1D grid's column passes have no team shape");
-  if (T < 16 || T > 1024 || (T & (T - 1)) || N % T) return fail(c, ZK_EINVAL, "team size must divide the transform length");
+  if (T < 8 || T > 1024 || (T & (T - 1)) || N % T) return fail(c, ZK_EINVAL, "team size must divide the transform length");
   const int E = N / T;
   const void *fn = c->precision == 32 ? (row ? batch_row_kernel<float>(T, E, pad) : batch_col_kernel<float>(T, E, pad))
                                       : (row ? batch_row_kernel<double>(T, E, pad) : batch_col_kernel<double>(T, E, pad));

@@ -119,7 +119,7 @@ std::vector<std::pair<int, int>> candidates(const zk_batch *b, bool row, bool pa
     if (N % E) continue;
     const int T = N / E;
     if (b->persistent && persist_shape(row, T, E) < 0) continue;  // not hosted by the persistent kernel
-    if (T >= 16 && T <= 1024 && !(T & (T - 1)) && kernel_for(b, row, T, E, pad)) out.push_back({T, E});
+    if (T >= 8 && T <= 1024 && !(T & (T - 1)) && kernel_for(b, row, T, E, pad)) out.push_back({T, E});
   }
   return out;
 }
@@ -134,8 +134,8 @@ std::pair<int, int> shape_of(zk_batch *b, bool row, bool pad, int nx, int ny) {
 }
 
 int blocks_of(bool row, bool pad, int nx, int ny, int T) {
-  const int per = T < 256 ? 256 / T : 1;
-  return row ? (pad ? 3 * ny / 2 : ny) / per : (nx / 2) / per;
+  const int per = T < 256 ? 256 / T : 1;  // teams per block; a partial last block idles its spare teams
+  return row ? ((pad ? 3 * ny / 2 : ny) + per - 1) / per : (nx / 2 + per - 1) / per;
 }
 
 // Merge the tiles' sequences of one segment into phases and append items.
@@ -253,7 +253,7 @@ int build_graph(zk_batch *b, int s) {
 // Blocks of kPBlock threads (kPBlock / T teams each) covering a pass.
 int pblocks_of(bool row, bool pad, int nx, int ny, int T) {
   const int per = kPBlock / T;
-  return row ? (pad ? 3 * ny / 2 : ny) / per : (nx / 2) / per;
+  return row ? ((pad ? 3 * ny / 2 : ny) + per - 1) / per : (nx / 2 + per - 1) / per;
 }
 
 // Units of the persistent form, segment by segment, in phase order: each

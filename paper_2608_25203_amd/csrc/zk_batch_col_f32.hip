@@ -6,6 +6,10 @@ namespace zk {
 
 template <>
 const void *batch_col_kernel<float>(int T, int E, bool pad) {
+  if (T == 8 && E == 2 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 8, 2>);
+  if (T == 8 && E == 3 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 8, 3>);
+  if (T == 8 && E == 4 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 8, 4>);
+  if (T == 8 && E == 6 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 8, 6>);
   if (T == 16 && E == 2 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 16, 2>);
   if (T == 16 && E == 3 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 16, 3>);
   if (T == 16 && E == 4 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 16, 4>);
@@ -40,11 +44,13 @@ const void *batch_col_kernel<float>(int T, int E, bool pad) {
   if (T == 512 && E == 6 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 512, 6>);
   if (T == 1024 && E == 2 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 1024, 2>);
   if (T == 1024 && E == 3 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 1024, 3>);
+  if (T == 8 && E == 9 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 8, 9>);
   if (T == 16 && E == 9 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 16, 9>);
   if (T == 32 && E == 9 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 32, 9>);
   if (T == 64 && E == 9 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 64, 9>);
   if (T == 128 && E == 9 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 128, 9>);
   if (T == 256 && E == 9 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 256, 9>);
+  if (T == 8 && E == 6 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 8, 6, false, false>);
   if (T == 16 && E == 6 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 16, 6, false, false>);
   if (T == 32 && E == 6 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 32, 6, false, false>);
   if (T == 64 && E == 6 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 64, 6, false, false>);
@@ -56,6 +62,22 @@ const void *batch_col_kernel<float>(int T, int E, bool pad) {
 template <>
 hipError_t launch_batch_col<float>(int T, int E, bool pad, dim3 grid, hipStream_t s, const ColArgs<float> *args,
                                    const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {
+  if (T == 8 && E == 2 && pad == false) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 8, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 8 && E == 3 && pad == true) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 8, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 8 && E == 4 && pad == false) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 8, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 8 && E == 6 && pad == true) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 8, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
   if (T == 16 && E == 2 && pad == false) {
     hipLaunchKernelGGL((col_kernel_batch<float, 16, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
@@ -192,6 +214,10 @@ hipError_t launch_batch_col<float>(int T, int E, bool pad, dim3 grid, hipStream_
     hipLaunchKernelGGL((col_kernel_batch<float, 1024, 3>), grid, dim3(1024), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
+  if (T == 8 && E == 9 && pad == true) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 8, 9>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
   if (T == 16 && E == 9 && pad == true) {
     hipLaunchKernelGGL((col_kernel_batch<float, 16, 9>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
@@ -210,6 +236,10 @@ hipError_t launch_batch_col<float>(int T, int E, bool pad, dim3 grid, hipStream_
   }
   if (T == 256 && E == 9 && pad == true) {
     hipLaunchKernelGGL((col_kernel_batch<float, 256, 9>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 8 && E == 6 && pad == false) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 8, 6, false, false>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 16 && E == 6 && pad == false) {
@@ -238,6 +268,14 @@ hipError_t launch_batch_col<float>(int T, int E, bool pad, dim3 grid, hipStream_
 template <>
 hipError_t launch_batch_col_lift<float>(int T, int E, dim3 grid, hipStream_t s, const ColArgs<float> *args,
                                         const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {
+  if (T == 8 && E == 2) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 8, 2, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 8 && E == 4) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 8, 4, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
   if (T == 16 && E == 2) {
     hipLaunchKernelGGL((col_kernel_batch<float, 16, 2, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
@@ -304,6 +342,10 @@ hipError_t launch_batch_col_lift<float>(int T, int E, dim3 grid, hipStream_t s, 
   }
   if (T == 1024 && E == 2) {
     hipLaunchKernelGGL((col_kernel_batch<float, 1024, 2, true>), grid, dim3(1024), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 8 && E == 6) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 8, 6, true, false>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 16 && E == 6) {

@@ -778,8 +778,13 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   const int t = threadIdx.x % T;
   // columns of one tile share 128-byte lines; keep a tile's blocks on one XCD
   constexpr int CBMAX = MixTile<real>::CB > CBB ? MixTile<real>::CB : CBB;
-  const int col = FT == 1 ? xcd_unit(blk, a.nx / 2 / CB::TPB, CBMAX / CB::TPB) * CB::TPB + team
-                          : xcd_unit(blk, a.nx / 2, CBMAX);
+  const int col_raw = FT == 1 ? xcd_unit(blk, a.nx / 2 / CB::TPB, CBMAX / CB::TPB) * CB::TPB + team
+                              : xcd_unit(blk, a.nx / 2, CBMAX);
+  // A grid with fewer columns than a block has teams (nx / 2 < 256 / T):
+  // the spare teams run the last column's transforms alongside (they share
+  // its barriers) and store nothing.
+  const bool in_col = col_raw < a.nx / 2;
+  const int col = in_col ? col_raw : a.nx / 2 - 1;
   cpx<real> *b0 = smem + team * NB * L;
   cpx<real> *b1 = b0 + (NB - 1) * L;
   const int ny = a.ny;
@@ -985,7 +990,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
       }
     }
     if (t == 0) acc[S::KR] = {0.0, 0.0};
-    const bool writer = FT == 1 || team == 0;  // fold teams: team 0 writes
+    const bool writer = (FT == 1 || team == 0) && in_col;  // fold teams: team 0 writes
     if (out.dst_base >= 0 && writer) {
       cpx<double> *B = a.base + (long long)out.dst_base * a.base_stride;
 #pragma unroll
@@ -1006,7 +1011,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
       }
       float m = 0.f;
       cpx<real> *F = a.mix + (long long)out.dst_mixed * a.mix_stride;
-      auto put = [&](int e, const cpx<real> &w) {  // element e of the lifted column
+      auto put = [&](int e, const cpx<real> &w) {  // element e of the lifted column (writers only)
         gstore(F, mix_index<real>(col, e, a.rows), w);
         m = fmaxf(m, fmaxf(fabsf((float)w.x), fabsf((float)w.y)));
       };
@@ -1146,14 +1151,14 @@ hipError_t launch_col_1d(bool liftsym, dim3 grid, hipStream_t s, const ColArgs<r
 }
 
 // Team shapes (T, E) compiled for the batched kernels.  Power-of-two axes
-// (n = 2^k in [32, 2048]): T = 16 with E in {2, 3, 4, 6}, T in {32, 64, 128,
-// 256} threads with E in {2, 3, 4, 6, 8, 12}, and T = 512 (E in {2, 3, 4, 6})
-// and 1024 (E in {2, 3})
+// (n = 2^k in [16, 2048]): T in {8, 16} with E in {2, 3, 4, 6}, T in {32, 64,
+// 128, 256} threads with E in {2, 3, 4, 6, 8, 12}, and T = 512 (E in {2, 3, 4,
+// 6}) and 1024 (E in {2, 3})
 // as blocks of their own, so each length has two to four candidates for its
 // padded (3n/2, E in {3, 6, 12}) and base (n, E in {2, 4, 8}) transforms;
-// the autotuner picks among them.  Axes with a factor 3 (n = 3 2^k in [96,
+// the autotuner picks among them.  Axes with a factor 3 (n = 3 2^k in [48,
 // 1536]): the padded transform of 9 2^(k-1) points with E = 9 and the base
-// transform with E = 6, T in {16, ..., 256}.  `pad` tells a base transform
+// transform with E = 6, T in {8, ..., 256}.  `pad` tells a base transform
 // with E = 6 from a padded one.  A block has max(256, T) threads.  These
 // return the kernel for (T, E, pad), or nullptr if that shape is not built.
 template <typename real>
@@ -1183,11 +1188,11 @@ inline int radix_candidates(int n, bool pad, int *e) {
   e[2] = pad ? 12 : 8;
   return 3;
 }
-// Axis lengths the kernels are built for: 2^k in [32, 2048] and 3 2^k in [96, 1536].
+// Axis lengths the kernels are built for: 2^k in [16, 2048] and 3 2^k in [48, 1536].
 inline bool axis_len_ok(int n) {
   const int m = n % 3 ? n : n / 3;
   const bool pow2 = m > 0 && (m & (m - 1)) == 0;
-  return pow2 && (n % 3 ? (n >= 32 && n <= 2048) : (n >= 96 && n <= 1536));
+  return pow2 && (n % 3 ? (n >= 16 && n <= 2048) : (n >= 48 && n <= 1536));
 }
 // Launch the kernel of shape (T, E, pad) (hipErrorInvalidValue if not built).
 template <typename real>

@@ -23,7 +23,7 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("nx,ny", [(64, 64), (128, 64), (512, 512), (2048, 2048), (96, 96), (384, 64), (1536, 192),
-                                   (32, 32), (32, 128)])
+                                   (32, 32), (32, 128), (16, 16), (48, 16), (16, 48)])
 @pytest.mark.parametrize("M", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_plan_builds_and_validates(nx, ny, M):
     p = load_plan(nx, ny, M)
@@ -177,16 +177,18 @@ def test_library_host_side_argument_checks():
     L = zk.lib()
     assert not L.zk_create(63, 64, 1.0, 1.0, 1.0, 9.81, 3)       # neither 2^k nor 3 2^k
     assert not L.zk_create(100, 64, 1.0, 1.0, 1.0, 9.81, 3)      # neither 2^k nor 3 2^k
-    assert not L.zk_create(48, 64, 1.0, 1.0, 1.0, 9.81, 3)       # 3 2^k below 96
-    assert not L.zk_create(16, 64, 1.0, 1.0, 1.0, 9.81, 3)       # 2^k below 32
-    c32 = L.zk_create(32, 32, 1.0, 1.0, 1.0, 9.81, 3)             # 2^k from 32 up: teams of 16
-    assert c32
-    T, E = ctypes.c_int(0), ctypes.c_int(0)
-    assert L.zk_team_shape(c32, 1, 1, ctypes.byref(T), ctypes.byref(E)) == 0 and (T.value, E.value) == (16, 3)
-    assert L.zk_team_shape(c32, 1, 0, ctypes.byref(T), ctypes.byref(E)) == 0 and (T.value, E.value) == (16, 2)
-    L.zk_destroy(c32)
+    assert not L.zk_create(24, 64, 1.0, 1.0, 1.0, 9.81, 3)       # 3 2^k below 48
+    assert not L.zk_create(8, 64, 1.0, 1.0, 1.0, 9.81, 3)        # 2^k below 16
+    for n, T0 in ((16, 8), (32, 16), (48, 8)):                     # the smallest axes: teams of 8 and 16
+        cs = L.zk_create(n, n, 1.0, 1.0, 1.0, 9.81, 3)
+        assert cs
+        T, E = ctypes.c_int(0), ctypes.c_int(0)
+        assert L.zk_team_shape(cs, 1, 1, ctypes.byref(T), ctypes.byref(E)) == 0 and T.value == T0
+        assert T.value * E.value == 3 * n // 2
+        assert L.zk_team_shape(cs, 1, 0, ctypes.byref(T), ctypes.byref(E)) == 0 and T.value * E.value == n
+        L.zk_destroy(cs)
     assert not L.zk_create(3072, 64, 1.0, 1.0, 1.0, 9.81, 3)     # 3 2^k above 1536
-    for n in (96, 192, 384, 768, 1536):                            # 3 2^k axes are built
+    for n in (96, 192, 384, 768, 1536):                            # 3 2^k axes from 96: teams of n / 6
         c3 = L.zk_create(n, 64, 1.0, 1.0, 1.0, 9.81, 3)
         assert c3
         T, E = ctypes.c_int(0), ctypes.c_int(0)
