@@ -25,9 +25,11 @@
  *   Errors     0 on success, a negative ZK_E* code otherwise, with a message
  *              in zk_last_error.  No exception crosses the ABI.
  *   Threads    a context is not thread-safe; use one context per stream.
- *   Sizes      nx and ny must each be a power of two in [16, 2048] or three
- *              times one in [48, 1536] (48, 96, 192, 384, 768, 1536), and ny
- *              may be 1 (a 1D grid); nx is the
+ *   Sizes      nx and ny must each be a power of two in [4, 2048] or three
+ *              times one in [12, 1536] (12, 24, ..., 1536), with nx a
+ *              multiple of 16 (the mixed fields are tiled in 64-byte groups
+ *              of columns: at least 16 or 48 points), and ny may be 1 (a
+ *              1D grid); nx is the
  *              fast (row) axis.  The dealiased products run on the
  *              3nx/2 x 3ny/2 grid.  Spectra keep their Nyquist row and column at zero, so
  *              input fields are projected onto |m_x| < nx/2, |m_y| < ny/2.

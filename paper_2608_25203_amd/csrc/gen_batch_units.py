@@ -5,12 +5,13 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 # power-of-two axes: padded iff E % 3 == 0
-POW2 = ([(T, E) for T in (8, 16) for E in (2, 3, 4, 6)]
+POW2 = ([(T, E) for T in (2, 4, 8, 16) for E in (2, 3, 4, 6)]
         + [(T, E) for T in (32, 64, 128, 256) for E in (2, 3, 4, 6, 8, 12)]
         + [(512, E) for E in (2, 3, 4, 6)] + [(1024, E) for E in (2, 3)])
 SHAPES = [(T, E, E % 3 == 0) for T, E in POW2]
 # axes of n = 3 2^k points: padded transforms with E = 9, base transforms with E = 6
-SHAPES += [(T, 9, True) for T in (8, 16, 32, 64, 128, 256)] + [(T, 6, False) for T in (8, 16, 32, 64, 128, 256)]
+SHAPES += ([(T, 9, True) for T in (2, 4, 8, 16, 32, 64, 128, 256)]
+           + [(T, 6, False) for T in (2, 4, 8, 16, 32, 64, 128, 256)])
 
 
 FOLD_SHAPES = [(T, E) for T in (64, 128, 256) for E in (2, 3)]  # as fold_team_shape() in zk_kernels.hpp

@@ -509,7 +509,9 @@ int ctx_run(zk_ctx *c, const std::vector<Launch> &seq, const Phys &ph) { return 
 extern "C" {
 
 zk_ctx *zk_create(int nx, int ny, double Lx, double Ly, double depth, double g, int M) {
-  if (!axis_len_ok(nx) || !(axis_len_ok(ny) || ny == 1)) return nullptr;  // ny = 1: a 1D grid
+  // ny = 1: a 1D grid.  nx / 2 columns must fill the mixed fields' tiles of
+  // 64-byte column groups (8 FP32 or 4 FP64 columns): nx % 16 == 0.
+  if (!axis_len_ok(nx) || nx % 16 != 0 || !(axis_len_ok(ny) || ny == 1)) return nullptr;
   if (!(Lx > 0) || !(Ly > 0) || !(g > 0) || M < 1 || M > 8) return nullptr;
   zk_ctx *c = new (std::nothrow) zk_ctx();
   if (!c) return nullptr;
@@ -863,7 +865,7 @@ int zk_autotune(zk_ctx *c, double dt, int reps) {
       for (int ci = 0; ci < ncand; ++ci) {
         const int E = cand[ci];
         const int T = N / E;
-        if (N % E || T < 8 || T > 1024 || (T & (T - 1))) continue;
+        if (N % E || T < 2 || T > 1024 || (T & (T - 1))) continue;
         const void *fn = c->precision == 32
                              ? (row ? batch_row_kernel<float>(T, E, pad) : batch_col_kernel<float>(T, E, pad))
                              : (row ? batch_row_kernel<double>(T, E, pad) : batch_col_kernel<double>(T, E, pad));
@@ -928,7 +930,7 @@ int zk_set_team_shape(zk_ctx *c, int row, int pad, int T) {
   const int n = row ? c->pp.nx : c->pp.ny;
   const int N = pad ? 3 * n / 2 : n;
   if (!row && n == 1) return fail(c, ZK_EINVAL, "a 1D grid's column passes have no team shape");
-  if (T < 8 || T > 1024 || (T & (T - 1)) || N % T) return fail(c, ZK_EINVAL, "team size must divide the transform length");
+  if (T < 2 || T > 1024 || (T & (T - 1)) || N % T) return fail(c, ZK_EINVAL, "team size must divide the transform length");
   const int E = N / T;
   const void *fn = c->precision == 32 ? (row ? batch_row_kernel<float>(T, E, pad) : batch_col_kernel<float>(T, E, pad))
                                       : (row ? batch_row_kernel<double>(T, E, pad) : batch_col_kernel<double>(T, E, pad));

@@ -119,7 +119,7 @@ std::vector<std::pair<int, int>> candidates(const zk_batch *b, bool row, bool pa
     if (N % E) continue;
     const int T = N / E;
     if (b->persistent && persist_shape(row, T, E) < 0) continue;  // not hosted by the persistent kernel
-    if (T >= 8 && T <= 1024 && !(T & (T - 1)) && kernel_for(b, row, T, E, pad)) out.push_back({T, E});
+    if (T >= 2 && T <= 1024 && !(T & (T - 1)) && kernel_for(b, row, T, E, pad)) out.push_back({T, E});
   }
   return out;
 }

@@ -6,6 +6,14 @@ namespace zk {
 
 template <>
 const void *batch_row_kernel<double>(int T, int E, bool pad) {
+  if (T == 2 && E == 2 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 2, 2>);
+  if (T == 2 && E == 3 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 2, 3>);
+  if (T == 2 && E == 4 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 2, 4>);
+  if (T == 2 && E == 6 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 2, 6>);
+  if (T == 4 && E == 2 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 4, 2>);
+  if (T == 4 && E == 3 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 4, 3>);
+  if (T == 4 && E == 4 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 4, 4>);
+  if (T == 4 && E == 6 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 4, 6>);
   if (T == 8 && E == 2 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 8, 2>);
   if (T == 8 && E == 3 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 8, 3>);
   if (T == 8 && E == 4 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 8, 4>);
@@ -44,12 +52,16 @@ const void *batch_row_kernel<double>(int T, int E, bool pad) {
   if (T == 512 && E == 6 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 512, 6>);
   if (T == 1024 && E == 2 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 1024, 2>);
   if (T == 1024 && E == 3 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 1024, 3>);
+  if (T == 2 && E == 9 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 2, 9>);
+  if (T == 4 && E == 9 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 4, 9>);
   if (T == 8 && E == 9 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 8, 9>);
   if (T == 16 && E == 9 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 16, 9>);
   if (T == 32 && E == 9 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 32, 9>);
   if (T == 64 && E == 9 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 9>);
   if (T == 128 && E == 9 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 9>);
   if (T == 256 && E == 9 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 9>);
+  if (T == 2 && E == 6 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 2, 6, false>);
+  if (T == 4 && E == 6 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 4, 6, false>);
   if (T == 8 && E == 6 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 8, 6, false>);
   if (T == 16 && E == 6 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 16, 6, false>);
   if (T == 32 && E == 6 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 32, 6, false>);
@@ -62,6 +74,38 @@ const void *batch_row_kernel<double>(int T, int E, bool pad) {
 template <>
 hipError_t launch_batch_row<double>(int T, int E, bool pad, dim3 grid, hipStream_t s, const RowArgs<double> *args,
                                    const BatchItem *items, int tile0, int first0, const void *sched0, PhysArgs ph) {
+  if (T == 2 && E == 2 && pad == false) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 2, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 2 && E == 3 && pad == true) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 2, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 2 && E == 4 && pad == false) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 2, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 2 && E == 6 && pad == true) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 2, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 4 && E == 2 && pad == false) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 4, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 4 && E == 3 && pad == true) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 4, 3>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 4 && E == 4 && pad == false) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 4, 4>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 4 && E == 6 && pad == true) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 4, 6>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
   if (T == 8 && E == 2 && pad == false) {
     hipLaunchKernelGGL((row_kernel_batch<double, 8, 2>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
@@ -214,6 +258,14 @@ hipError_t launch_batch_row<double>(int T, int E, bool pad, dim3 grid, hipStream
     hipLaunchKernelGGL((row_kernel_batch<double, 1024, 3>), grid, dim3(1024), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
+  if (T == 2 && E == 9 && pad == true) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 2, 9>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 4 && E == 9 && pad == true) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 4, 9>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
   if (T == 8 && E == 9 && pad == true) {
     hipLaunchKernelGGL((row_kernel_batch<double, 8, 9>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
@@ -236,6 +288,14 @@ hipError_t launch_batch_row<double>(int T, int E, bool pad, dim3 grid, hipStream
   }
   if (T == 256 && E == 9 && pad == true) {
     hipLaunchKernelGGL((row_kernel_batch<double, 256, 9>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 2 && E == 6 && pad == false) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 2, 6, false>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 4 && E == 6 && pad == false) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 4, 6, false>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   if (T == 8 && E == 6 && pad == false) {

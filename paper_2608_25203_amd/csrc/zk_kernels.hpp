@@ -1151,14 +1151,14 @@ hipError_t launch_col_1d(bool liftsym, dim3 grid, hipStream_t s, const ColArgs<r
 }
 
 // Team shapes (T, E) compiled for the batched kernels.  Power-of-two axes
-// (n = 2^k in [16, 2048]): T in {8, 16} with E in {2, 3, 4, 6}, T in {32, 64,
-// 128, 256} threads with E in {2, 3, 4, 6, 8, 12}, and T = 512 (E in {2, 3, 4,
-// 6}) and 1024 (E in {2, 3})
+// (n = 2^k in [4, 2048]): T in {2, 4, 8, 16} with E in {2, 3, 4, 6}, T in
+// {32, 64, 128, 256} threads with E in {2, 3, 4, 6, 8, 12}, and T = 512 (E in
+// {2, 3, 4, 6}) and 1024 (E in {2, 3})
 // as blocks of their own, so each length has two to four candidates for its
 // padded (3n/2, E in {3, 6, 12}) and base (n, E in {2, 4, 8}) transforms;
-// the autotuner picks among them.  Axes with a factor 3 (n = 3 2^k in [48,
+// the autotuner picks among them.  Axes with a factor 3 (n = 3 2^k in [12,
 // 1536]): the padded transform of 9 2^(k-1) points with E = 9 and the base
-// transform with E = 6, T in {8, ..., 256}.  `pad` tells a base transform
+// transform with E = 6, T in {2, ..., 256}.  `pad` tells a base transform
 // with E = 6 from a padded one.  A block has max(256, T) threads.  These
 // return the kernel for (T, E, pad), or nullptr if that shape is not built.
 template <typename real>
@@ -1188,11 +1188,11 @@ inline int radix_candidates(int n, bool pad, int *e) {
   e[2] = pad ? 12 : 8;
   return 3;
 }
-// Axis lengths the kernels are built for: 2^k in [16, 2048] and 3 2^k in [48, 1536].
+// Axis lengths the kernels are built for: 2^k in [4, 2048] and 3 2^k in [12, 1536].
 inline bool axis_len_ok(int n) {
   const int m = n % 3 ? n : n / 3;
   const bool pow2 = m > 0 && (m & (m - 1)) == 0;
-  return pow2 && (n % 3 ? (n >= 16 && n <= 2048) : (n >= 48 && n <= 1536));
+  return pow2 && (n % 3 ? (n >= 4 && n <= 2048) : (n >= 12 && n <= 1536));
 }
 // Launch the kernel of shape (T, E, pad) (hipErrorInvalidValue if not built).
 template <typename real>

@@ -12,9 +12,9 @@ the permuted-layout forms of the padded row passes (perm_ifft, perm_fft)."""
 import numpy as np
 import pytest
 
-SHAPES = ([(T, E) for T in (8, 16) for E in (2, 3, 4, 6)]
+SHAPES = ([(T, E) for T in (2, 4, 8, 16) for E in (2, 3, 4, 6)]
           + [(T, E) for T in (32, 64, 128, 256) for E in (2, 3, 4, 6, 8, 12)] + [(512, E) for E in (2, 3, 4, 6)]
-          + [(1024, 2), (1024, 3)] + [(T, E) for T in (8, 16, 32, 64, 128, 256) for E in (6, 9)])
+          + [(1024, 2), (1024, 3)] + [(T, E) for T in (2, 4, 8, 16, 32, 64, 128, 256) for E in (6, 9)])
 SHAPES = sorted(set(SHAPES))
 
 

@@ -679,12 +679,13 @@ def test_1d_stokes_regimes_through_c_abi(torch, ka, kh):
 
 @pytest.mark.parametrize("M", [2, 3, 4])
 @pytest.mark.parametrize("shape", [(32, 32), (64, 32), (32, 128), (1, 32), (16, 16), (16, 48), (48, 48), (1, 16),
-                                   (16, 96)])
+                                   (16, 96), (4, 16), (8, 16), (4, 64), (12, 48), (24, 48), (12, 96)])
 def test_small_axes(torch, M, shape):
-    """The smallest axes: 16 and 32 points (padded transforms of 24 and 48
-    points, teams of 8 and 16 threads), 48 (radix 9 and 6 with teams of 8),
-    and 1D grids of 16 and 32: G psi, the RHS and two RK4 steps at the FP64
-    bar, random data filling the band, finite depth."""
+    """The smallest axes: columns of 4 to 32 points (padded transforms of 6
+    to 48 points, teams of 2 to 16 threads) and of 12 to 48 (radix 9 and 6,
+    teams of 2 to 8), rows of 16 to 48, and 1D grids of 16 and 32: G psi,
+    the RHS and two RK4 steps at the FP64 bar, random data filling the band,
+    finite depth."""
     ny, nx = shape
     Lx, Ly, h = 1.0, max(1.0 * ny / nx, 0.05), 0.3
     kmax = math.hypot(math.pi * nx / Lx, math.pi * ny / Ly)

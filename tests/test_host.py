@@ -23,7 +23,7 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("nx,ny", [(64, 64), (128, 64), (512, 512), (2048, 2048), (96, 96), (384, 64), (1536, 192),
-                                   (32, 32), (32, 128), (16, 16), (48, 16), (16, 48)])
+                                   (32, 32), (32, 128), (16, 16), (48, 16), (16, 48), (16, 4), (16, 12), (48, 4)])
 @pytest.mark.parametrize("M", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_plan_builds_and_validates(nx, ny, M):
     p = load_plan(nx, ny, M)
@@ -177,15 +177,18 @@ def test_library_host_side_argument_checks():
     L = zk.lib()
     assert not L.zk_create(63, 64, 1.0, 1.0, 1.0, 9.81, 3)       # neither 2^k nor 3 2^k
     assert not L.zk_create(100, 64, 1.0, 1.0, 1.0, 9.81, 3)      # neither 2^k nor 3 2^k
-    assert not L.zk_create(24, 64, 1.0, 1.0, 1.0, 9.81, 3)       # 3 2^k below 48
-    assert not L.zk_create(8, 64, 1.0, 1.0, 1.0, 9.81, 3)        # 2^k below 16
-    for n, T0 in ((16, 8), (32, 16), (48, 8)):                     # the smallest axes: teams of 8 and 16
-        cs = L.zk_create(n, n, 1.0, 1.0, 1.0, 9.81, 3)
+    assert not L.zk_create(64, 6, 1.0, 1.0, 1.0, 9.81, 3)        # 3 2^k below 12
+    assert not L.zk_create(64, 2, 1.0, 1.0, 1.0, 9.81, 3)        # 2^k below 4
+    for nx in (4, 8, 12, 24):                                      # nx / 2 below a 64-byte column group
+        assert not L.zk_create(nx, 64, 1.0, 1.0, 1.0, 9.81, 3)
+    for nx, ny, T0 in ((16, 4, 2), (16, 8, 4), (16, 16, 8), (32, 32, 16), (48, 12, 2), (48, 24, 4),
+                       (48, 48, 8)):  # the smallest axes: teams of 2 to 16 threads on the columns
+        cs = L.zk_create(nx, ny, 1.0, 1.0, 1.0, 9.81, 3)
         assert cs
         T, E = ctypes.c_int(0), ctypes.c_int(0)
-        assert L.zk_team_shape(cs, 1, 1, ctypes.byref(T), ctypes.byref(E)) == 0 and T.value == T0
-        assert T.value * E.value == 3 * n // 2
-        assert L.zk_team_shape(cs, 1, 0, ctypes.byref(T), ctypes.byref(E)) == 0 and T.value * E.value == n
+        assert L.zk_team_shape(cs, 0, 1, ctypes.byref(T), ctypes.byref(E)) == 0 and T.value == T0
+        assert T.value * E.value == 3 * ny // 2
+        assert L.zk_team_shape(cs, 0, 0, ctypes.byref(T), ctypes.byref(E)) == 0 and T.value * E.value == ny
         L.zk_destroy(cs)
     assert not L.zk_create(3072, 64, 1.0, 1.0, 1.0, 9.81, 3)     # 3 2^k above 1536
     for n in (96, 192, 384, 768, 1536):                            # 3 2^k axes from 96: teams of n / 6
