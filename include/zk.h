@@ -25,8 +25,9 @@
  *   Errors     0 on success, a negative ZK_E* code otherwise, with a message
  *              in zk_last_error.  No exception crosses the ABI.
  *   Threads    a context is not thread-safe; use one context per stream.
- *   Sizes      nx and ny must each be a power of two in [4, 2048] or three
- *              times one in [12, 1536] (12, 24, ..., 1536), with nx a
+ *   Sizes      nx and ny must each be a power of two in [4, 2048], three
+ *              times one in [12, 1536] (12, 24, ..., 1536) or five times one
+ *              in [20, 1280] (20, 40, ..., 1280), with nx a
  *              multiple of 16 (the mixed fields are tiled in 64-byte groups
  *              of columns: at least 16 or 48 points), and ny may be 1 (a
  *              1D grid); nx is the

@@ -12,6 +12,8 @@ SHAPES = [(T, E, E % 3 == 0) for T, E in POW2]
 # axes of n = 3 2^k points: padded transforms with E = 9, base transforms with E = 6
 SHAPES += ([(T, 9, True) for T in (2, 4, 8, 16, 32, 64, 128, 256)]
            + [(T, 6, False) for T in (2, 4, 8, 16, 32, 64, 128, 256)])
+# axes of n = 5 2^k points: padded transforms with E = 15, base transforms with E = 10
+SHAPES += [(T, 15, True) for T in (2, 4, 8, 16, 32, 64, 128)] + [(T, 10, False) for T in (2, 4, 8, 16, 32, 64, 128)]
 
 
 FOLD_SHAPES = [(T, E) for T in (64, 128, 256) for E in (2, 3)]  # as fold_team_shape() in zk_kernels.hpp
@@ -20,7 +22,7 @@ FOLD_SHAPES = [(T, E) for T in (64, 128, 256) for E in (2, 3)]  # as fold_team_s
 def lanes_ok(T, E, pad, real_bytes):
     """as row_lanes_ok() in zk_kernels.hpp"""
     N, tpb = T * E, max(T, 256) // T
-    return pad and T % 64 == 0 and T <= 1024 and 2 * tpb * N * 2 * real_bytes <= 100 * 1024
+    return pad and E % 5 != 0 and T % 64 == 0 and T <= 1024 and 2 * tpb * N * 2 * real_bytes <= 100 * 1024
 
 
 def bs(T):

@@ -146,8 +146,10 @@ std::vector<cpx<real>> twiddles(int n) {
     t[(size_t)kTwNatural * n + m] = {(real)cosl(a), (real)sinl(a)};
   }
   // candidate first-pass radices of this length, one per slot (tw_slot)
-  const int cand[kTwNatural] = {n % 9 == 0 ? 9 : (n % 3 == 0 ? 3 : 2), n % 9 == 0 ? 18 : (n % 3 == 0 ? 6 : 4),
-                                n % 9 == 0 ? 0 : (n % 3 == 0 ? 12 : 8)};
+  const bool f5 = n % 5 == 0;  // 5 2^k lengths: one candidate, 15 (padded) or 10 (base)
+  const int cand[kTwNatural] = {f5 ? (n % 3 == 0 ? 15 : 10) : (n % 9 == 0 ? 9 : (n % 3 == 0 ? 3 : 2)),
+                                f5 ? 0 : (n % 9 == 0 ? 18 : (n % 3 == 0 ? 6 : 4)),
+                                f5 || n % 9 == 0 ? 0 : (n % 3 == 0 ? 12 : 8)};
   for (int s = 0; s < kTwNatural; ++s) {
     const int E = cand[s];
     if (E == 0) continue;

@@ -277,8 +277,8 @@ int build_units(zk_batch *b) {
       for (const BL &l : ph) {
         const int shape = persist_shape(l.row, l.T, l.E);
         if (shape < 0)
-          return fail(b, ZK_EINVAL, "persistent form: the tiles' transforms must be 128 to 1024 points per axis "
-                                    "with the smallest first-pass radix");
+          return fail(b, ZK_EINVAL, "persistent form: the tiles' axes must be powers of two whose transforms "
+                                    "are 128 to 1024 points, with the smallest first-pass radix");
         const int lds = b->precision == 32 ? persist_lds_bytes<float>(shape) : persist_lds_bytes<double>(shape);
         b->useg_lds[s] = std::max(b->useg_lds[s], lds);
         const int nblk = pblocks_of(l.row, l.pad, l.nx, l.ny, l.T);

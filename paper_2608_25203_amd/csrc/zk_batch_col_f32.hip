@@ -68,6 +68,20 @@ const void *batch_col_kernel<float>(int T, int E, bool pad) {
   if (T == 64 && E == 6 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 64, 6, false, false>);
   if (T == 128 && E == 6 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 128, 6, false, false>);
   if (T == 256 && E == 6 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 256, 6, false, false>);
+  if (T == 2 && E == 15 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 2, 15>);
+  if (T == 4 && E == 15 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 4, 15>);
+  if (T == 8 && E == 15 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 8, 15>);
+  if (T == 16 && E == 15 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 16, 15>);
+  if (T == 32 && E == 15 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 32, 15>);
+  if (T == 64 && E == 15 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 64, 15>);
+  if (T == 128 && E == 15 && pad == true) return reinterpret_cast<const void *>(&col_kernel_batch<float, 128, 15>);
+  if (T == 2 && E == 10 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 2, 10>);
+  if (T == 4 && E == 10 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 4, 10>);
+  if (T == 8 && E == 10 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 8, 10>);
+  if (T == 16 && E == 10 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 16, 10>);
+  if (T == 32 && E == 10 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 32, 10>);
+  if (T == 64 && E == 10 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 64, 10>);
+  if (T == 128 && E == 10 && pad == false) return reinterpret_cast<const void *>(&col_kernel_batch<float, 128, 10>);
   return nullptr;
 }
 
@@ -322,6 +336,62 @@ hipError_t launch_batch_col<float>(int T, int E, bool pad, dim3 grid, hipStream_
     hipLaunchKernelGGL((col_kernel_batch<float, 256, 6, false, false>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
+  if (T == 2 && E == 15 && pad == true) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 2, 15>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 4 && E == 15 && pad == true) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 4, 15>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 8 && E == 15 && pad == true) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 8, 15>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 16 && E == 15 && pad == true) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 16, 15>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 32 && E == 15 && pad == true) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 32, 15>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 64 && E == 15 && pad == true) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 64, 15>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 15 && pad == true) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 128, 15>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 2 && E == 10 && pad == false) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 2, 10>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 4 && E == 10 && pad == false) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 4, 10>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 8 && E == 10 && pad == false) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 8, 10>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 16 && E == 10 && pad == false) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 16, 10>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 32 && E == 10 && pad == false) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 32, 10>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 64 && E == 10 && pad == false) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 64, 10>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 10 && pad == false) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 128, 10>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
   return hipErrorInvalidValue;
 }
 
@@ -450,6 +520,34 @@ hipError_t launch_batch_col_lift<float>(int T, int E, dim3 grid, hipStream_t s, 
   }
   if (T == 256 && E == 6) {
     hipLaunchKernelGGL((col_kernel_batch<float, 256, 6, true, false>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 2 && E == 10) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 2, 10, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 4 && E == 10) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 4, 10, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 8 && E == 10) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 8, 10, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 16 && E == 10) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 16, 10, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 32 && E == 10) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 32, 10, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 64 && E == 10) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 64, 10, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 10) {
+    hipLaunchKernelGGL((col_kernel_batch<float, 128, 10, true>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;

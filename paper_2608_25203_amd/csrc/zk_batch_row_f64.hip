@@ -68,6 +68,20 @@ const void *batch_row_kernel<double>(int T, int E, bool pad) {
   if (T == 64 && E == 6 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 6, false>);
   if (T == 128 && E == 6 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 6, false>);
   if (T == 256 && E == 6 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 256, 6, false>);
+  if (T == 2 && E == 15 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 2, 15>);
+  if (T == 4 && E == 15 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 4, 15>);
+  if (T == 8 && E == 15 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 8, 15>);
+  if (T == 16 && E == 15 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 16, 15>);
+  if (T == 32 && E == 15 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 32, 15>);
+  if (T == 64 && E == 15 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 15>);
+  if (T == 128 && E == 15 && pad == true) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 15>);
+  if (T == 2 && E == 10 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 2, 10>);
+  if (T == 4 && E == 10 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 4, 10>);
+  if (T == 8 && E == 10 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 8, 10>);
+  if (T == 16 && E == 10 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 16, 10>);
+  if (T == 32 && E == 10 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 32, 10>);
+  if (T == 64 && E == 10 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 64, 10>);
+  if (T == 128 && E == 10 && pad == false) return reinterpret_cast<const void *>(&row_kernel_batch<double, 128, 10>);
   return nullptr;
 }
 
@@ -320,6 +334,62 @@ hipError_t launch_batch_row<double>(int T, int E, bool pad, dim3 grid, hipStream
   }
   if (T == 256 && E == 6 && pad == false) {
     hipLaunchKernelGGL((row_kernel_batch<double, 256, 6, false>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 2 && E == 15 && pad == true) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 2, 15>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 4 && E == 15 && pad == true) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 4, 15>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 8 && E == 15 && pad == true) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 8, 15>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 16 && E == 15 && pad == true) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 16, 15>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 32 && E == 15 && pad == true) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 32, 15>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 64 && E == 15 && pad == true) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 64, 15>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 15 && pad == true) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 128, 15>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 2 && E == 10 && pad == false) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 2, 10>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 4 && E == 10 && pad == false) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 4, 10>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 8 && E == 10 && pad == false) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 8, 10>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 16 && E == 10 && pad == false) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 16, 10>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 32 && E == 10 && pad == false) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 32, 10>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 64 && E == 10 && pad == false) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 64, 10>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
+    return hipGetLastError();
+  }
+  if (T == 128 && E == 10 && pad == false) {
+    hipLaunchKernelGGL((row_kernel_batch<double, 128, 10>), grid, dim3(256), 0, s, args, items, tile0, first0, sched0, ph);
     return hipGetLastError();
   }
   return hipErrorInvalidValue;

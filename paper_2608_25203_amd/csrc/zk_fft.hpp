@@ -192,6 +192,27 @@ struct DFT<4, DIR, R> {
   }
 };
 
+// Five points: with t1 = x1 + x4, t2 = x2 + x3, t3 = x1 - x4, t4 = x2 - x3,
+// X1,4 = x0 + c1 t1 + c2 t2 +- DIR i (s1 t3 + s2 t4) and
+// X2,3 = x0 + c2 t1 + c1 t2 +- DIR i (s2 t3 - s1 t4), c_j + i s_j = e^(2 pi i j / 5).
+template <int DIR, typename R>
+struct DFT<5, DIR, R> {
+  __device__ __forceinline__ static void run(cpx<R> *x) {
+    constexpr double c1 = cos_sin_frac(1, 5, false), s1 = cos_sin_frac(1, 5, true);
+    constexpr double c2 = cos_sin_frac(2, 5, false), s2 = cos_sin_frac(2, 5, true);
+    const cpx<R> t1 = cadd(x[1], x[4]), t2 = cadd(x[2], x[3]), t3 = csub(x[1], x[4]), t4 = csub(x[2], x[3]);
+    const cpx<R> a1 = {x[0].x + (R)c1 * t1.x + (R)c2 * t2.x, x[0].y + (R)c1 * t1.y + (R)c2 * t2.y};
+    const cpx<R> a2 = {x[0].x + (R)c2 * t1.x + (R)c1 * t2.x, x[0].y + (R)c2 * t1.y + (R)c1 * t2.y};
+    const cpx<R> b1 = mul_diri<DIR>(cpx<R>{(R)s1 * t3.x + (R)s2 * t4.x, (R)s1 * t3.y + (R)s2 * t4.y});
+    const cpx<R> b2 = mul_diri<DIR>(cpx<R>{(R)s2 * t3.x - (R)s1 * t4.x, (R)s2 * t3.y - (R)s1 * t4.y});
+    x[0] = cadd(x[0], cadd(t1, t2));
+    x[1] = cadd(a1, b1);
+    x[4] = csub(a1, b1);
+    x[2] = cadd(a2, b2);
+    x[3] = csub(a2, b2);
+  }
+};
+
 // Composite RR = A * B, A in {4, 2, 3}:  n = B n1 + n2, k = k1 + A k2,
 // X[k1 + A k2] = sum_n2 W_RR^(n2 k1) W_B^(n2 k2) [sum_n1 x[B n1 + n2] W_A^(n1 k1)].
 template <int RR, int DIR, typename R>
@@ -262,14 +283,14 @@ __host__ __device__ constexpr int lds_len(int N) { return N; }
 // host stores them at Ns_p - E + (r-1) Ns_p + k (N - E entries), so a lane's
 // consecutive k read adjacent words instead of a stride of r step_p.  Each
 // transform length keeps one table per candidate E, slot tw_slot(E).
-// Slots: E in {2, 3, 9} -> 0, {4, 6, 18} -> 1, {8, 12} -> 2 (a length uses at
-// most one E of each group).
+// Slots: E in {2, 3, 9, 10, 15} -> 0, {4, 6, 18} -> 1, {8, 12} -> 2 (a length
+// uses at most one E of each group).
 // Slot 3 holds the natural table W_N^m, m < N (the permuted-layout forms
 // below).
 constexpr int kTwSlots = 4;
 constexpr int kTwNatural = 3;
 __host__ __device__ constexpr int tw_slot(int E) {
-  return (E == 2 || E == 3 || E == 9) ? 0 : ((E == 4 || E == 6 || E == 18) ? 1 : 2);
+  return (E == 2 || E == 3 || E == 9 || E == 10 || E == 15) ? 0 : ((E == 4 || E == 6 || E == 18) ? 1 : 2);
 }
 
 // Last pass of a team FFT of N = E T points: radix R, NB = N / R butterflies,

@@ -226,7 +226,7 @@ __device__ __forceinline__ float2 pow2_scale(float m) {
 // to LDS only if it fits beside them).
 __host__ __device__ constexpr bool row_lanes_ok(int T, int E, bool padded, int real_bytes) {
   const int N = T * E, tpb = (T > 256 ? T : 256) / T;
-  return padded && T % 64 == 0 && T <= 1024 && 2 * tpb * N * 2 * real_bytes <= 100 * 1024;
+  return padded && E % 5 != 0 && T % 64 == 0 && T <= 1024 && 2 * tpb * N * 2 * real_bytes <= 100 * 1024;
 }
 
 template <int T, int E, int BSZ = 0, bool PAD = (E % 3 == 0)>
@@ -1158,7 +1158,8 @@ hipError_t launch_col_1d(bool liftsym, dim3 grid, hipStream_t s, const ColArgs<r
 // padded (3n/2, E in {3, 6, 12}) and base (n, E in {2, 4, 8}) transforms;
 // the autotuner picks among them.  Axes with a factor 3 (n = 3 2^k in [12,
 // 1536]): the padded transform of 9 2^(k-1) points with E = 9 and the base
-// transform with E = 6, T in {2, ..., 256}.  `pad` tells a base transform
+// transform with E = 6, T in {2, ..., 256}; with a factor 5 (n = 5 2^k in
+// [20, 1280]): padded E = 15 and base E = 10, T in {2, ..., 128}.  `pad` tells a base transform
 // with E = 6 from a padded one.  A block has max(256, T) threads.  These
 // return the kernel for (T, E, pad), or nullptr if that shape is not built.
 template <typename real>
@@ -1174,13 +1175,16 @@ const void *batch_col_kernel<double>(int T, int E, bool pad);
 template <>
 const void *batch_col_kernel<float>(int T, int E, bool pad);
 // The default first-pass radix of an axis of n base points: the smallest
-// compiled one (n = 2^k: 3 padded, 2 base; n = 3 2^k: 9 padded, 6 base).
-inline int default_radix(int n, bool pad) { return n % 3 ? (pad ? 3 : 2) : (pad ? 9 : 6); }
+// compiled one (n = 2^k: 3 padded, 2 base; n = 3 2^k: 9 padded, 6 base;
+// n = 5 2^k: 15 padded, 10 base).
+inline int default_radix(int n, bool pad) {
+  return n % 5 == 0 ? (pad ? 15 : 10) : (n % 3 ? (pad ? 3 : 2) : (pad ? 9 : 6));
+}
 // The compiled first-pass radices of that axis's padded or base transform
 // (the autotuner's candidates): writes up to three into e, returns the count.
 inline int radix_candidates(int n, bool pad, int *e) {
-  if (n % 3 == 0) {
-    e[0] = pad ? 9 : 6;
+  if (n % 3 == 0 || n % 5 == 0) {
+    e[0] = default_radix(n, pad);
     return 1;
   }
   e[0] = pad ? 3 : 2;
@@ -1188,11 +1192,13 @@ inline int radix_candidates(int n, bool pad, int *e) {
   e[2] = pad ? 12 : 8;
   return 3;
 }
-// Axis lengths the kernels are built for: 2^k in [4, 2048] and 3 2^k in [12, 1536].
+// Axis lengths the kernels are built for: 2^k in [4, 2048], 3 2^k in [12,
+// 1536] and 5 2^k in [20, 1280].
 inline bool axis_len_ok(int n) {
-  const int m = n % 3 ? n : n / 3;
-  const bool pow2 = m > 0 && (m & (m - 1)) == 0;
-  return pow2 && (n % 3 ? (n >= 4 && n <= 2048) : (n >= 12 && n <= 1536));
+  const int f = n % 3 == 0 ? 3 : (n % 5 == 0 ? 5 : 1);
+  const int m = n / f;
+  if (n % f || m <= 0 || (m & (m - 1))) return false;
+  return f == 1 ? (n >= 4 && n <= 2048) : (f == 3 ? (n >= 12 && n <= 1536) : (n >= 20 && n <= 1280));
 }
 // Launch the kernel of shape (T, E, pad) (hipErrorInvalidValue if not built).
 template <typename real>

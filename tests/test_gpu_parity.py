@@ -113,6 +113,59 @@ def test_non_power_of_two_fp32_walls_and_lift(torch):
         assert rel(uvw[i], ref[i]) < 1e-10
 
 
+@pytest.mark.parametrize("M", [2, 3, 5])
+@pytest.mark.parametrize("shape", [(20, 80), (40, 160), (1, 80), (80, 80), (160, 320), (1280, 16), (20, 1280),
+                                   (96, 80), (80, 64)])
+def test_factor_five_grids(torch, M, shape):
+    """Axes of 5 2^k points (padded transforms of 15 2^(k-1) points with a
+    radix-15 first pass, base transforms with radix 10, teams of 2 to 128
+    threads), alone and beside 2^k and 3 2^k axes: G psi, the RHS and two
+    RK4 steps at the FP64 bar, random data filling the band, finite depth."""
+    ny, nx = shape
+    Lx, Ly, h = 2.0, max(2.0 * ny / nx, 0.05), 0.6
+    kmax = math.hypot(math.pi * nx / Lx, math.pi * ny / Ly)
+    eta, psi = random_band_fields(nx, ny, 50 + M, nx // 2 - 1 if ny == 1 else min(nx, ny) // 2 - 1,
+                                  amplitude=0.1 / kmax)
+    s = solver(torch, nx, ny, Lx, Ly, h, M)
+    print(" ", s.team_shapes(), flush=True)
+    m = HOSModel(Grid(nx, ny, Lx, Ly, h), M)
+    e, p = dev(torch, eta), dev(torch, psi)
+    assert rel(host(s.dtn(e, p)), m.dtn(eta, psi)) < 1e-10
+    a, b = s.rhs(e, p)
+    a0, b0 = m.rhs(eta, psi)
+    assert rel(host(a), a0) < 1e-10 and rel(host(b), b0) < 1e-10
+    s.step(e, p, 0.002, 2)
+    e0, p0 = m.step(eta, psi, 0.002, 2)
+    assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
+
+
+def test_factor_five_fp32_walls_and_lift(torch):
+    """An 80 x 160 grid (5 2^k on both axes) in the FP32 form (2e-5 per RHS
+    against the FP64 oracle), with reflecting walls (doubled axes 160 and
+    320; 1e-10) and the depth lift (1e-10)."""
+    from oracle.hos import ReflectingModel
+
+    nx, ny, L, h, M = 80, 160, 2.0, 0.8, 3
+    kmax = math.hypot(math.pi * nx / L, math.pi * ny / (2 * L))
+    eta, psi = random_band_fields(nx, ny, 83, nx // 2 - 1, amplitude=0.1 / kmax)
+    m = HOSModel(Grid(nx, ny, L, 2 * L, h), M)
+    s32 = solver(torch, nx, ny, L, 2 * L, h, M, precision=32)
+    a, b = s32.rhs(dev(torch, eta), dev(torch, psi))
+    a0, b0 = m.rhs(eta, psi)
+    assert rel(host(a), a0) < 2e-5 and rel(host(b), b0) < 2e-5
+    sw = solver(torch, nx, ny, L, 2 * L, h, M, boundary="reflect")
+    e, p = dev(torch, eta), dev(torch, psi)
+    sw.step(e, p, 0.002, 2)
+    e0, p0 = ReflectingModel(nx, ny, L, 2 * L, h, M).step(eta, psi, 0.002, 2)
+    assert rel(host(e), e0) < 1e-10 and rel(host(p), p0) < 1e-10
+    s64 = solver(torch, nx, ny, L, 2 * L, h, M)
+    ys = [0.0, 0.3]
+    uvw = host(s64.depth_velocity(dev(torch, eta), dev(torch, psi), ys))
+    ref = m.depth_velocity(eta, psi, ys)
+    for i in range(len(ys)):
+        assert rel(uvw[i], ref[i]) < 1e-10
+
+
 @pytest.mark.parametrize("M", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("shape", [(64, 64), (128, 64), (64, 256)])
 def test_dtn_rhs_parity_small(torch, M, shape):

@@ -23,7 +23,8 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("nx,ny", [(64, 64), (128, 64), (512, 512), (2048, 2048), (96, 96), (384, 64), (1536, 192),
-                                   (32, 32), (32, 128), (16, 16), (48, 16), (16, 48), (16, 4), (16, 12), (48, 4)])
+                                   (32, 32), (32, 128), (16, 16), (48, 16), (16, 48), (16, 4), (16, 12), (48, 4),
+                                   (80, 20), (160, 80), (1280, 640), (80, 1)])
 @pytest.mark.parametrize("M", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_plan_builds_and_validates(nx, ny, M):
     p = load_plan(nx, ny, M)
@@ -175,8 +176,11 @@ def test_library_exports_every_declared_symbol():
 def test_library_host_side_argument_checks():
     from paper_2608_25203_amd import zk
     L = zk.lib()
-    assert not L.zk_create(63, 64, 1.0, 1.0, 1.0, 9.81, 3)       # neither 2^k nor 3 2^k
-    assert not L.zk_create(100, 64, 1.0, 1.0, 1.0, 9.81, 3)      # neither 2^k nor 3 2^k
+    assert not L.zk_create(63, 64, 1.0, 1.0, 1.0, 9.81, 3)       # not 2^k, 3 2^k or 5 2^k
+    assert not L.zk_create(100, 64, 1.0, 1.0, 1.0, 9.81, 3)      # 25 2^2: not 2^k, 3 2^k or 5 2^k
+    assert not L.zk_create(64, 10, 1.0, 1.0, 1.0, 9.81, 3)       # 5 2^k below 20
+    assert not L.zk_create(2560, 64, 1.0, 1.0, 1.0, 9.81, 3)     # 5 2^k above 1280
+    assert not L.zk_create(160, 720, 1.0, 1.0, 1.0, 9.81, 3)     # 45 2^4: factors 3 and 5 together
     assert not L.zk_create(64, 6, 1.0, 1.0, 1.0, 9.81, 3)        # 3 2^k below 12
     assert not L.zk_create(64, 2, 1.0, 1.0, 1.0, 9.81, 3)        # 2^k below 4
     for nx in (4, 8, 12, 24):                                      # nx / 2 below a 64-byte column group
@@ -198,6 +202,14 @@ def test_library_host_side_argument_checks():
         assert L.zk_team_shape(c3, 1, 1, ctypes.byref(T), ctypes.byref(E)) == 0 and (T.value, E.value) == (n // 6, 9)
         assert L.zk_team_shape(c3, 1, 0, ctypes.byref(T), ctypes.byref(E)) == 0 and (T.value, E.value) == (n // 6, 6)
         L.zk_destroy(c3)
+    for n in (80, 160, 320, 640, 1280):                            # 5 2^k axes: teams of n / 10, radix 15 and 10
+        c5 = L.zk_create(n, 20, 1.0, 1.0, 1.0, 9.81, 3)
+        assert c5
+        T, E = ctypes.c_int(0), ctypes.c_int(0)
+        assert L.zk_team_shape(c5, 1, 1, ctypes.byref(T), ctypes.byref(E)) == 0 and (T.value, E.value) == (n // 10, 15)
+        assert L.zk_team_shape(c5, 1, 0, ctypes.byref(T), ctypes.byref(E)) == 0 and (T.value, E.value) == (n // 10, 10)
+        assert L.zk_team_shape(c5, 0, 1, ctypes.byref(T), ctypes.byref(E)) == 0 and (T.value, E.value) == (2, 15)
+        L.zk_destroy(c5)
     assert not L.zk_create(64, 4096, 1.0, 1.0, 1.0, 9.81, 3)     # too large
     assert not L.zk_create(64, 64, -1.0, 1.0, 1.0, 9.81, 3)      # bad length
     assert not L.zk_create(64, 64, 1.0, 1.0, 1.0, 9.81, 9)       # M out of range
