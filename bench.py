@@ -634,6 +634,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default team shapes")
     ap.add_argument("--row-fft", choices=("auto", "stockham", "lanes"), default="auto",
                     help="form of the padded row transforms (auto: the autotuner's choice)")
+    ap.add_argument("--row-programs", choices=("compiled", "interpreted"), default="compiled",
+                    help="padded row programs as compiled straight-line shapes where built, or all interpreted")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision-form (2048^2 M=5), closure-form (1024^2) and batch-form (256 tiles) runs")
     ap.add_argument("--headline-only", action="store_true",
@@ -665,7 +667,7 @@ def main():
     import torch
 
     from paper_2608_25203_amd.inputs import WORKLOADS, jonswap_state
-    from paper_2608_25203_amd.zk import ZK_OPT_PROFILE, ZK_OPT_ROW_FFT, ZK_ROW_FFT_LANES, Solver
+    from paper_2608_25203_amd.zk import ZK_OPT_PROFILE, ZK_OPT_ROW_FFT, ZK_OPT_ROW_PROGRAMS, ZK_ROW_FFT_LANES, Solver
 
     w = dict(WORKLOADS[args.workload])
     eta, psi = jonswap_state(w["nx"], w["ny"], w["Lx"], w["Ly"], w["depth"], w["g"], w["kp"], w["steepness"],
@@ -676,6 +678,8 @@ def main():
     e = torch.tensor(eta, dtype=torch.float64, device=dev)
     p = torch.tensor(psi, dtype=torch.float64, device=dev)
 
+    if args.row_programs != "compiled":
+        s.set_option(ZK_OPT_ROW_PROGRAMS, 0)
     shapes = s.autotune(w["dt"], reps=3) if not args.no_autotune else s.team_shapes()
     if args.row_fft != "auto":
         s.set_option(ZK_OPT_ROW_FFT, ZK_ROW_FFT_LANES if args.row_fft == "lanes" else 0)
@@ -758,6 +762,7 @@ def main():
         "kernel_ms_per_step": round(step_kernel_ms, 4),
         "team_shapes": {k: {"T": v[0], "E": v[1]} for k, v in shapes.items()},
         "row_fft": "lanes" if s.get_option(ZK_OPT_ROW_FFT) == ZK_ROW_FFT_LANES else "stockham",
+        "row_programs": "compiled" if s.get_option(ZK_OPT_ROW_PROGRAMS) else "interpreted",
         "finite": finite,
     }
     if args.headline_only:

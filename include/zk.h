@@ -78,6 +78,14 @@ enum {
                              ZK_ROW_FFT_STOCKHAM (default) or ZK_ROW_FFT_LANES;
                              zk_autotune times both at the chosen team shape
                              and keeps the faster.  Same results to rounding. */
+    ZK_OPT_ROW_PROGRAMS = 10, /* 1 (default): padded row passes of the team
+                             shapes that compile them (E = 3 teams of 64 to
+                             1024 threads; FP32 also T = 512, E = 6) run each
+                             row program whose operation sequence is one of
+                             the compiled shapes as straight-line code; other
+                             programs and shapes interpret the op list.
+                             0: interpret every program.  Same results
+                             bit for bit.                                     */
     ZK_OPT_PROFILE = 6    /* 1: bracket every kernel launch with HIP events on
                              the bound stream and accumulate per-kind times for
                              zk_kernel_stats (adds event records between

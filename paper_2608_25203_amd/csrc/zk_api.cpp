@@ -170,6 +170,21 @@ std::vector<cpx<real>> twiddles(int n) {
   return t;
 }
 
+// The compiled shape (zk_row_shapes.hpp) whose op sequence a program's ops
+// match in (code, a, b, c), or -1.
+static int row_shape_of(const RowOp *ops, int nop) {
+  for (int sh = 0; sh < kRowShapes; ++sh) {
+    if (kRowShapeLen[sh] != nop) continue;
+    bool same = true;
+    for (int i = 0; i < nop && same; ++i) {
+      const RowOp &o = ops[i];
+      same = kRowShapeOps[sh][i] == ((uint32_t)o.code | (uint32_t)o.a << 8 | (uint32_t)o.b << 16 | (uint32_t)o.c << 24);
+    }
+    if (same) return sh;
+  }
+  return -1;
+}
+
 int upload(zk_ctx *c, double dt) {
   if (!c->bound) return fail(c, ZK_ENOWS, "workspace not bound");
   const bool need = !c->have_plan || c->dirty || !(dt == c->plan_dt || (std::isnan(dt) && std::isnan(c->plan_dt)));
@@ -191,7 +206,12 @@ int upload(zk_ctx *c, double dt) {
     return hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream);
   };
   HIP_TRY(c, put(c->off_ops, p.ops.data(), p.ops.size() * sizeof(RowOp)));
-  HIP_TRY(c, put(c->off_progs, p.progs.data(), p.progs.size() * sizeof(RowProg)));
+  // Tag each program with its compiled shape (kernels without compiled
+  // shapes, and untagged programs, interpret the op list).
+  std::vector<RowProg> progs = p.progs;
+  if (c->row_programs)
+    for (RowProg &pg : progs) pg.shape1 = 1 + row_shape_of(p.ops.data() + pg.op0, pg.nop);
+  HIP_TRY(c, put(c->off_progs, progs.data(), progs.size() * sizeof(RowProg)));
   HIP_TRY(c, put(c->off_terms, p.terms.data(), p.terms.size() * sizeof(ColTerm)));
   HIP_TRY(c, put(c->off_outs, p.outs.data(), p.outs.size() * sizeof(ColOut)));
   HIP_TRY(c, put(c->off_tasks, p.tasks.data(), p.tasks.size() * sizeof(ColTask)));
@@ -574,6 +594,11 @@ int zk_set_option(zk_ctx *c, int key, double v) {
       if (v != ZK_ROW_FFT_STOCKHAM && v != ZK_ROW_FFT_LANES) return fail(c, ZK_EINVAL, "unknown row transform form");
       c->row_fft = (int)v;
       return ZK_OK;
+    case ZK_OPT_ROW_PROGRAMS:
+      if (v != 0.0 && v != 1.0) return fail(c, ZK_EINVAL, "row programs option must be 0 or 1");
+      c->row_programs = (int)v;
+      c->dirty = true;  // re-tag the uploaded programs; the plan itself is unchanged
+      return ZK_OK;
     case ZK_OPT_BOUNDARY:
       if (v != ZK_BC_PERIODIC && v != ZK_BC_REFLECT) return fail(c, ZK_EINVAL, "unknown boundary");
       if (c->bound && (int)v != c->bc) return fail(c, ZK_EINVAL, "set the boundary before zk_bind");
@@ -611,6 +636,7 @@ int zk_get_option(const zk_ctx *c, int key, double *v) {
     case ZK_OPT_PROFILE: *v = c->prof ? 1.0 : 0.0; break;
     case ZK_OPT_INTEGRATOR: *v = c->integrator; break;
     case ZK_OPT_BOUNDARY: *v = c->bc; break;
+    case ZK_OPT_ROW_PROGRAMS: *v = c->row_programs; break;
     case ZK_OPT_ROW_FFT: {  // the form the padded row passes run in at the current team shape
       const TeamShape sh = ctx_team(c, true, true);
       *v = c->row_fft == ZK_ROW_FFT_LANES && row_lanes_ok(sh.T, sh.E, true, c->precision == 32 ? 4 : 8)

@@ -41,7 +41,8 @@ struct zk_ctx {
   size_t off_layer = 0;   // (C, S) of one depth layer per band element
   double ifsym_dt = NAN;  // dt the table holds
   int tuneT[2][2] = {{0, 0}, {0, 0}};  // [row][pad] autotuned threads per transform (0: default)
-  int row_fft = 0;                      // ZK_OPT_ROW_FFT
+  int row_fft = 0;
+  int row_programs = 1;  // ZK_OPT_ROW_PROGRAMS                      // ZK_OPT_ROW_FFT
   size_t off_red = 0, off_cmax = 0, off_sym = 0, off_fx = 0, off_fy = 0, off_base = 0, off_mix = 0, total = 0;
   long long base_stride = 0, mix_stride = 0;
   size_t sched_cap[5] = {0, 0, 0, 0, 0};  // capacities (elements) reserved for the schedules

@@ -17,6 +17,7 @@
 #pragma once
 #include "zk_fft.hpp"
 #include "zk_program.hpp"
+#include "zk_row_shapes.hpp"
 
 namespace zk {
 
@@ -227,6 +228,13 @@ __device__ __forceinline__ float2 pow2_scale(float m) {
 __host__ __device__ constexpr bool row_lanes_ok(int T, int E, bool padded, int real_bytes) {
   const int N = T * E, tpb = (T > 256 ? T : 256) / T;
   return padded && E % 5 != 0 && T % 64 == 0 && T <= 1024 && 2 * tpb * N * 2 * real_bytes <= 100 * 1024;
+}
+
+// Padded row shapes whose kernels also hold every program shape of
+// zk_row_shapes.hpp as straight-line code (the team shapes the autotuner
+// picks for the large grids; the others interpret every program).
+__host__ __device__ constexpr bool row_compiled_shapes(int T, int E, bool padded, int real_bytes) {
+  return padded && ((E == 3 && T >= 64 && T <= 1024) || (real_bytes == 4 && E == 6 && T == 512));
 }
 
 template <int T, int E, int BSZ = 0, bool PAD = (E % 3 == 0)>
@@ -443,112 +451,232 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
     else return R[s - 2][e];
   };
 
+  // The operations, shared by the interpreter and the compiled shapes.
+  auto do_ld2 = [&](const RowOp &op) {
+    const cpx<real> *Fa = a.mix + (long long)op.fa * a.mix_stride;
+    const bool has_b = op.fb >= 0;
+    const cpx<real> *Fb = a.mix + (long long)(has_b ? op.fb : op.fa) * a.mix_stride;
+    const bool dxa = op.fla & FL_DX, dxb = op.flb & FL_DX;
+    // The two real fields share one complex transform; each is scaled by
+    // a power of two from its field maximum (published by the lifts that
+    // wrote it) so that neither drowns in the rounding of the other, and
+    // unscaled exactly afterwards.
+    // Data loads first; the field maxima (one per column, published by
+    // the lifts) are reduced over all columns by each wavefront on its
+    // own, so no block barrier sits between the loads and their use.
+    // Padded passes up to 512-thread teams load the half spectra in the
+    // layout of the transposed transform's first butterflies (element
+    // p = j + NB r of butterfly j = t + T it); its result arrives in z[]
+    // as element t + T e without an LDS readout.  (1024-thread teams, and
+    // base lengths, whose last pass keeps only half the team busy,
+    // measured faster with team_fft from the t + T e layout.)  The
+    // permuted form loads element t + T e and leaves in z[s] the point
+    // s + E bitrev(t / 64) + E (T / 64) bitrev6(t % 64) of the row.
+    auto ld2 = [&](auto xp_c, auto lanes_c) {
+      constexpr bool XP = decltype(xp_c)::value, PERMUTED = decltype(lanes_c)::value;
+      using HL = HbmLayout<N, E, XP>;
+      cpx<real> xa[HL::IT][HL::R], xb[HL::IT][HL::R];
+      auto elem = [&](int it, int r) { return HL::elem(t, it, r); };
+      auto live = [&](int it) { return HL::live(t, it); };
+#pragma unroll
+      for (int it = 0; it < HL::IT; ++it)
+#pragma unroll
+        for (int r = 0; r < HL::R; ++r) {
+          const int p = elem(it, r);
+          const bool pos = p < S::KR * T, neg = p > S::NEG0 * T;  // kept band, upper half by symmetry
+          xa[it][r] = {(real)0, (real)0};
+          xb[it][r] = {(real)0, (real)0};
+          if (in_row && live(it) && (pos || neg)) {
+            const int idx = mix_index<real>(pos ? p : N - p, row, a.rows);
+            xa[it][r] = gload(Fa, idx);
+            if (has_b) xb[it][r] = gload(Fb, idx);
+          }
+        }
+      float ma = 0.f, mb = 0.f;
+      {
+        constexpr int NC = S::KR * T;  // nx / 2 columns
+        const float *ca = a.colmax + (long long)op.fa * NC;
+        const float *cb = a.colmax + (long long)(has_b ? op.fb : op.fa) * NC;
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int c = lane; c < NC; c += 64) {
+          ma = fmaxf(ma, gload1(ca, c));
+          mb = fmaxf(mb, gload1(cb, c));
+        }
+        ma = wave_max(ma);
+        mb = wave_max(mb);
+      }
+      const float2 pa = pow2_scale(ma);
+      const float2 pb = has_b ? pow2_scale(mb) : make_float2(1.f, 1.f);
+      const real sa = (real)pa.x, sb = (real)pb.x;
+#pragma unroll
+      for (int it = 0; it < HL::IT; ++it)
+#pragma unroll
+        for (int r = 0; r < HL::R; ++r) {
+          const int p = elem(it, r);
+          const bool pos = p < S::KR * T, neg = p > S::NEG0 * T;
+          cpx<real> za = xa[it][r], zbr = xb[it][r];
+          if (pos || neg) {
+            const real kxv = (real)(a.kx_scale * (pos ? p : N - p));
+            if (dxa) za = {-kxv * za.y, kxv * za.x};
+            if (dxb) zbr = {-kxv * zbr.y, kxv * zbr.x};
+            if (neg) {
+              za.y = -za.y;
+              zbr.y = -zbr.y;
+            }
+          }
+          xa[it][r] = {za.x * sa - zbr.y * sb, za.y * sa + zbr.x * sb};
+        }
+      settle_tw();
+      if constexpr (PERMUTED) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) z[e] = xa[0][e];
+        perm_ifft<real, T, E, +1>(z, b0, b1, tw, t);
+      } else {
+        fft_in<real, N, E, NB, +1, XP>(xa, z, b0, b1, tw, t);
+      }
+      const real ia = (real)pa.y, ib = (real)pb.y;
+#pragma unroll
+      for (int e = 0; e < E; ++e) z[e] = {z[e].x * ia, z[e].y * ib};
+    };
+    if constexpr (LANES) ld2(std::false_type{}, std::true_type{});
+    else ld2(std::integral_constant<bool, T <= 512 && S::PADDED>{}, std::false_type{});
+  };
+  // LDP and STP act on caller fields, whose rows have the base length only.
+  auto do_ldp = [&](const RowOp &op) {
+    if constexpr (!S::PADDED) {
+      const double *pa = op.fa == 0 ? a.pin0 : (op.fa == 1 ? a.pin1 : a.pin2);
+      const double *pb = op.fb == 0 ? a.pin0 : (op.fb == 1 ? a.pin1 : a.pin2);
+      const long long off = (long long)row * a.nx;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        z[e].x = in_row ? (real)gload1(pa, off + t + T * e) : (real)0;
+        z[e].y = in_row && op.fb >= 0 ? (real)gload1(pb, off + t + T * e) : (real)0;
+      }
+    }
+  };
+  auto do_zero = [&]() {  // clears all three outputs
+#pragma unroll
+    for (int e = 0; e < E; ++e) R[RS_O0 - 2][e] = R[RS_O1 - 2][e] = R[RS_O2 - 2][e] = (real)0;
+  };
+  auto do_bern = [&](const RowOp &op) {
+    const real eps = (real)op.coef;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const real Sv = (real)1 + eps * eps * R[RS_O0 - 2][e];
+      const real W = (z[e].x + eps * R[RS_O1 - 2][e]) / Sv;
+      R[RS_O0 - 2][e] = eps * ((real)-0.5 * R[RS_O2 - 2][e] + (real)0.5 * Sv * W * W);
+    }
+  };
+  // forward transform of (u, v) once they hold the op's sources; split and store
+  auto do_st2 = [&](const RowOp &op) {
+    float mx = 0.f, my = 0.f;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      mx = fmaxf(mx, fabsf((float)z[e].x));
+      my = fmaxf(my, fabsf((float)z[e].y));
+    }
+    const float2 mxy = team_max2<T>(mx, my, red);
+    const float2 px = pow2_scale(mxy.x);
+    const float2 py = pow2_scale(mxy.y);
+    const real sx = (real)px.x, sy = (real)py.x;
+#pragma unroll
+    for (int e = 0; e < E; ++e) z[e] = {z[e].x * sx, z[e].y * sy};
+    settle_tw();
+    const cpx<real> *res;
+    // (team_max2's barriers follow every earlier read of the buffers)
+    if constexpr (LANES) res = perm_fft<real, T, E, -1, false>(z, b0, b1, tw, t);
+    else res = team_fft<real, N, E, NB, -1>(z, b0, b1, tw, t);
+    cpx<real> *Fa = a.mix + (long long)op.fa * a.mix_stride;
+    cpx<real> *Fb = a.mix + (long long)(op.fb >= 0 ? op.fb : 0) * a.mix_stride;
+    const real hx = (real)0.5 * (real)px.y, hy = (real)0.5 * (real)py.y;
+#pragma unroll
+    for (int q = 0; q < S::KR; ++q) {
+      const int k = t + T * q;
+      const cpx<real> zk = res[lpad(k)];
+      const cpx<real> zm = res[lpad(k == 0 ? 0 : N - k)];
+      const int idx = mix_index<real>(k, row, a.rows);
+      if (in_row) gstore(Fa, idx, cpx<real>{hx * (zk.x + zm.x), hx * (zk.y - zm.y)});
+      if (in_row && op.fb >= 0) gstore(Fb, idx, cpx<real>{hy * (zk.y + zm.y), -hy * (zk.x - zm.x)});
+    }
+  };
+  auto do_stp = [&](const RowOp &op, auto X) {
+    if constexpr (!S::PADDED) {
+      double *po = op.fa == 0 ? a.pout0 : a.pout1;
+      const long long off = ((long long)(op.fb > 0 ? op.fb : 0) * a.rows + row) * a.nx;
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (in_row) gstore1(po, off + t + T * e, (double)reg(X, e));
+    }
+  };
+
+  // A program of a compiled shape runs as straight-line code: its register
+  // sets are fixed at compile time, so no interpreter state merges between
+  // operations (and no operation dispatch remains); only the field ids, flags
+  // and coefficients come from the op records.
+  if constexpr (row_compiled_shapes(T, E, S::PADDED, (int)sizeof(real)) && !DYN && !LANES && BSZ == 0) {
+    if (pg.shape1 > 0) {
+      static_for<0, kRowShapes>([&](auto shc) {
+        constexpr int SH = decltype(shc)::value;
+        if (pg.shape1 == SH + 1) {
+          static_for<0, kRowShapeLen[SH]>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            constexpr uint32_t w = kRowShapeOps[SH][I];
+            constexpr int code = w & 255, A = (w >> 8) & 255, B = (w >> 16) & 255, C = (int)(w >> 24);
+            using IA = std::integral_constant<int, A>;
+            using IB = std::integral_constant<int, B>;
+            using IC = std::integral_constant<int, C>;
+            const RowOp op = uniform_load(a.ops + pg.op0 + I);
+            if constexpr (code == OP_LD2) {
+              do_ld2(op);
+            } else if constexpr (code == OP_MOV) {
+#pragma unroll
+              for (int e = 0; e < E; ++e) R[RS_A - 2][e] = reg(IB{}, e);
+            } else if constexpr (code == OP_MAC) {
+              const real c = (real)op.coef;
+#pragma unroll
+              for (int e = 0; e < E; ++e) {
+                const real pr = reg(IB{}, e) * reg(IC{}, e);
+                reg(IA{}, e) += c * pr;
+              }
+            } else if constexpr (code == OP_ZERO) {
+              do_zero();
+            } else if constexpr (code == OP_BERN) {
+              do_bern(op);
+            } else if constexpr (code == OP_ST2) {
+              if constexpr (A != RS_U) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) z[e].x = reg(IA{}, e);
+              }
+              if constexpr (B == RS_NONE) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) z[e].y = (real)0;
+              } else if constexpr (B != RS_V) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) z[e].y = reg(IB{}, e);
+              }
+              do_st2(op);
+            }
+            // keep each operation's instructions together, as the
+            // interpreter does, so the register peak stays that of one op
+            __builtin_amdgcn_sched_barrier(0);
+          });
+        }
+      });
+      settle_tw();  // no load into LDS may outlive the block
+      return;
+    }
+  }
+
   for (int i = 0; i < pg.nop; ++i) {
     const RowOp op = uniform_load(a.ops + pg.op0 + i);
     switch (op.code) {
-      case OP_LD2: {
-        const cpx<real> *Fa = a.mix + (long long)op.fa * a.mix_stride;
-        const bool has_b = op.fb >= 0;
-        const cpx<real> *Fb = a.mix + (long long)(has_b ? op.fb : op.fa) * a.mix_stride;
-        const bool dxa = op.fla & FL_DX, dxb = op.flb & FL_DX;
-        // The two real fields share one complex transform; each is scaled by
-        // a power of two from its field maximum (published by the lifts that
-        // wrote it) so that neither drowns in the rounding of the other, and
-        // unscaled exactly afterwards.
-        // Data loads first; the field maxima (one per column, published by
-        // the lifts) are reduced over all columns by each wavefront on its
-        // own, so no block barrier sits between the loads and their use.
-        // Padded passes up to 512-thread teams load the half spectra in the
-        // layout of the transposed transform's first butterflies (element
-        // p = j + NB r of butterfly j = t + T it); its result arrives in z[]
-        // as element t + T e without an LDS readout.  (1024-thread teams, and
-        // base lengths, whose last pass keeps only half the team busy,
-        // measured faster with team_fft from the t + T e layout.)  The
-        // permuted form loads element t + T e and leaves in z[s] the point
-        // s + E bitrev(t / 64) + E (T / 64) bitrev6(t % 64) of the row.
-        auto ld2 = [&](auto xp_c, auto lanes_c) {
-          constexpr bool XP = decltype(xp_c)::value, PERMUTED = decltype(lanes_c)::value;
-          using HL = HbmLayout<N, E, XP>;
-          cpx<real> xa[HL::IT][HL::R], xb[HL::IT][HL::R];
-          auto elem = [&](int it, int r) { return HL::elem(t, it, r); };
-          auto live = [&](int it) { return HL::live(t, it); };
-#pragma unroll
-          for (int it = 0; it < HL::IT; ++it)
-#pragma unroll
-            for (int r = 0; r < HL::R; ++r) {
-              const int p = elem(it, r);
-              const bool pos = p < S::KR * T, neg = p > S::NEG0 * T;  // kept band, upper half by symmetry
-              xa[it][r] = {(real)0, (real)0};
-              xb[it][r] = {(real)0, (real)0};
-              if (in_row && live(it) && (pos || neg)) {
-                const int idx = mix_index<real>(pos ? p : N - p, row, a.rows);
-                xa[it][r] = gload(Fa, idx);
-                if (has_b) xb[it][r] = gload(Fb, idx);
-              }
-            }
-          float ma = 0.f, mb = 0.f;
-          {
-            constexpr int NC = S::KR * T;  // nx / 2 columns
-            const float *ca = a.colmax + (long long)op.fa * NC;
-            const float *cb = a.colmax + (long long)(has_b ? op.fb : op.fa) * NC;
-            const int lane = threadIdx.x & 63;
-#pragma unroll
-            for (int c = lane; c < NC; c += 64) {
-              ma = fmaxf(ma, gload1(ca, c));
-              mb = fmaxf(mb, gload1(cb, c));
-            }
-            ma = wave_max(ma);
-            mb = wave_max(mb);
-          }
-          const float2 pa = pow2_scale(ma);
-          const float2 pb = has_b ? pow2_scale(mb) : make_float2(1.f, 1.f);
-          const real sa = (real)pa.x, sb = (real)pb.x;
-#pragma unroll
-          for (int it = 0; it < HL::IT; ++it)
-#pragma unroll
-            for (int r = 0; r < HL::R; ++r) {
-              const int p = elem(it, r);
-              const bool pos = p < S::KR * T, neg = p > S::NEG0 * T;
-              cpx<real> za = xa[it][r], zbr = xb[it][r];
-              if (pos || neg) {
-                const real kxv = (real)(a.kx_scale * (pos ? p : N - p));
-                if (dxa) za = {-kxv * za.y, kxv * za.x};
-                if (dxb) zbr = {-kxv * zbr.y, kxv * zbr.x};
-                if (neg) {
-                  za.y = -za.y;
-                  zbr.y = -zbr.y;
-                }
-              }
-              xa[it][r] = {za.x * sa - zbr.y * sb, za.y * sa + zbr.x * sb};
-            }
-          settle_tw();
-          if constexpr (PERMUTED) {
-#pragma unroll
-            for (int e = 0; e < E; ++e) z[e] = xa[0][e];
-            perm_ifft<real, T, E, +1>(z, b0, b1, tw, t);
-          } else {
-            fft_in<real, N, E, NB, +1, XP>(xa, z, b0, b1, tw, t);
-          }
-          const real ia = (real)pa.y, ib = (real)pb.y;
-#pragma unroll
-          for (int e = 0; e < E; ++e) z[e] = {z[e].x * ia, z[e].y * ib};
-        };
-        if constexpr (LANES) ld2(std::false_type{}, std::true_type{});
-        else ld2(std::integral_constant<bool, T <= 512 && S::PADDED>{}, std::false_type{});
+      case OP_LD2:
+        do_ld2(op);
         break;
-      }
-      case OP_LDP: {
-        if constexpr (S::PADDED) break;  // caller fields have base-length rows only
-        const double *pa = op.fa == 0 ? a.pin0 : (op.fa == 1 ? a.pin1 : a.pin2);
-        const double *pb = op.fb == 0 ? a.pin0 : (op.fb == 1 ? a.pin1 : a.pin2);
-        const long long off = (long long)row * a.nx;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          z[e].x = in_row ? (real)gload1(pa, off + t + T * e) : (real)0;
-          z[e].y = in_row && op.fb >= 0 ? (real)gload1(pb, off + t + T * e) : (real)0;
-        }
+      case OP_LDP:
+        do_ldp(op);
         break;
-      }
       // MOV, MAC and ZERO write their targets without a branch on the target
       // register: a switch per target would make the compiler copy every
       // register set at each merge of the interpreter loop.
@@ -581,21 +709,12 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
         }
         break;
       }
-      case OP_ZERO: {  // clears all three outputs
-#pragma unroll
-        for (int e = 0; e < E; ++e) R[RS_O0 - 2][e] = R[RS_O1 - 2][e] = R[RS_O2 - 2][e] = (real)0;
+      case OP_ZERO:
+        do_zero();
         break;
-      }
-      case OP_BERN: {
-        const real eps = (real)op.coef;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const real Sv = (real)1 + eps * eps * R[RS_O0 - 2][e];
-          const real W = (z[e].x + eps * R[RS_O1 - 2][e]) / Sv;
-          R[RS_O0 - 2][e] = eps * ((real)-0.5 * R[RS_O2 - 2][e] + (real)0.5 * Sv * W * W);
-        }
+      case OP_BERN:
+        do_bern(op);
         break;
-      }
       case OP_ST2: {
         // Sources are (u, v) in place, or sets outside the FFT buffer (the
         // planner never pairs u or v with another set).
@@ -614,48 +733,12 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
             for (int e = 0; e < E; ++e) z[e].y = reg(Y, e);
           });
         }
-        float mx = 0.f, my = 0.f;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          mx = fmaxf(mx, fabsf((float)z[e].x));
-          my = fmaxf(my, fabsf((float)z[e].y));
-        }
-        const float2 mxy = team_max2<T>(mx, my, red);
-        const float2 px = pow2_scale(mxy.x);
-        const float2 py = pow2_scale(mxy.y);
-        const real sx = (real)px.x, sy = (real)py.x;
-#pragma unroll
-        for (int e = 0; e < E; ++e) z[e] = {z[e].x * sx, z[e].y * sy};
-        settle_tw();
-        const cpx<real> *res;
-        // (team_max2's barriers follow every earlier read of the buffers)
-        if constexpr (LANES) res = perm_fft<real, T, E, -1, false>(z, b0, b1, tw, t);
-        else res = team_fft<real, N, E, NB, -1>(z, b0, b1, tw, t);
-        cpx<real> *Fa = a.mix + (long long)op.fa * a.mix_stride;
-        cpx<real> *Fb = a.mix + (long long)(op.fb >= 0 ? op.fb : 0) * a.mix_stride;
-        const real hx = (real)0.5 * (real)px.y, hy = (real)0.5 * (real)py.y;
-#pragma unroll
-        for (int q = 0; q < S::KR; ++q) {
-          const int k = t + T * q;
-          const cpx<real> zk = res[lpad(k)];
-          const cpx<real> zm = res[lpad(k == 0 ? 0 : N - k)];
-          const int idx = mix_index<real>(k, row, a.rows);
-          if (in_row) gstore(Fa, idx, cpx<real>{hx * (zk.x + zm.x), hx * (zk.y - zm.y)});
-          if (in_row && op.fb >= 0) gstore(Fb, idx, cpx<real>{hy * (zk.y + zm.y), -hy * (zk.x - zm.x)});
-        }
+        do_st2(op);
         break;
       }
-      case OP_STP: {
-        if constexpr (S::PADDED) break;
-        double *po = op.fa == 0 ? a.pout0 : a.pout1;
-        const long long off = ((long long)(op.fb > 0 ? op.fb : 0) * a.rows + row) * a.nx;
-        with_any(op.a, [&](auto X) {
-#pragma unroll
-          for (int e = 0; e < E; ++e)
-            if (in_row) gstore1(po, off + t + T * e, (double)reg(X, e));
-        });
+      case OP_STP:
+        with_any(op.a, [&](auto X) { do_stp(op, X); });
         break;
-      }
       default:
         break;
     }

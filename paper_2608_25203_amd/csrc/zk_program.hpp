@@ -46,6 +46,8 @@ struct RowOp {
 
 struct RowProg {
   int32_t op0, nop;
+  int32_t shape1;  // 1 + the program's compiled shape (zk_row_shapes.hpp), or 0: interpreted
+  int32_t pad_;
 };
 
 // ---- column tasks -------------------------------------------------------

@@ -19,6 +19,7 @@ ZK_INTEGRATOR_RK4, ZK_INTEGRATOR_IFAB2 = 0, 1
 ZK_OPT_BOUNDARY = 8
 ZK_BC_PERIODIC, ZK_BC_REFLECT = 0, 1
 ZK_OPT_ROW_FFT = 9
+ZK_OPT_ROW_PROGRAMS = 10
 ZK_ROW_FFT_STOCKHAM, ZK_ROW_FFT_LANES = 0, 1
 ZK_KERNEL_ROW_PAD, ZK_KERNEL_ROW_BASE, ZK_KERNEL_COL_PAD, ZK_KERNEL_COL_BASE, ZK_KERNEL_REDUCE = 0, 1, 2, 3, 4
 KERNEL_NAMES = {0: "row_pad", 1: "row_base", 2: "col_pad", 3: "col_base", 4: "reduce"}

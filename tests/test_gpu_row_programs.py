@@ -1,0 +1,69 @@
+"""GPU: padded row programs compiled as straight-line shapes
+(ZK_OPT_ROW_PROGRAMS = 1, the default) give the same bits as the op-list
+interpreter (0) for G psi, the RHS and RK4 steps -- the two run the same
+arithmetic in the same order -- on every team shape that compiles them, at
+HOS orders whose programs are all compiled (3 to 5) and at order 6, where the
+longest level program stays interpreted beside compiled ones; and the
+compiled path matches the CPU oracle at the FP64 bar."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.hos import Grid, HOSModel
+from paper_2608_25203_amd.inputs import random_band_fields
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def rel(a, b):
+    r = float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+    print(f"  rel err {r:.3e}", flush=True)
+    return r
+
+
+# (nx, ny, M, precision, padded-row team T or 0 = default); E = 3 nx / 2 / T
+CASES = [(512, 512, 4, 64, 0), (128, 64, 3, 64, 64), (256, 128, 5, 64, 128), (1024, 64, 4, 64, 512),
+         (2048, 32, 5, 64, 1024), (256, 64, 6, 64, 128), (512, 64, 4, 32, 256), (2048, 32, 5, 32, 512),
+         (1024, 32, 3, 32, 512), (256, 1, 4, 64, 128)]
+
+
+@pytest.mark.parametrize("nx,ny,M,prec,T", CASES)
+def test_compiled_row_programs_bit_identical_to_interpreter(torch, nx, ny, M, prec, T):
+    from paper_2608_25203_amd.zk import ZK_OPT_ROW_PROGRAMS, Solver
+
+    Lx, Ly, h = 2.0, max(2.0 * ny / nx, 0.05), 0.6
+    kmax = math.hypot(math.pi * nx / Lx, math.pi * ny / Ly)
+    eta, psi = random_band_fields(nx, ny, 500 + M + T, nx // 2 - 1 if ny == 1 else min(nx, ny) // 2 - 1,
+                                  amplitude=0.1 / kmax)
+    runs = []
+    for compiled in (1, 0):
+        s = Solver(nx, ny, Lx, Ly, h, 9.81, M, precision=prec)
+        if T:
+            s.set_team_shape(1, 1, T)
+        s.set_option(ZK_OPT_ROW_PROGRAMS, compiled)
+        assert s.get_option(ZK_OPT_ROW_PROGRAMS) == compiled
+        print(f"  {nx}x{ny} M={M} FP{prec} compiled={compiled}: {s.team_shapes()['row_pad']}", flush=True)
+        e = torch.tensor(eta, dtype=torch.float64, device="cuda")
+        p = torch.tensor(psi, dtype=torch.float64, device="cuda")
+        g = s.dtn(e, p).cpu().numpy()
+        a, b = (x.cpu().numpy() for x in s.rhs(e, p))
+        s.step(e, p, 0.002, 3)
+        runs.append((g, a, b, e.cpu().numpy(), p.cpu().numpy()))
+        s.close()
+    for x, y in zip(*runs):
+        assert np.array_equal(x, y)
+    if prec == 64:
+        m = HOSModel(Grid(nx, ny, Lx, Ly, h), M)
+        assert rel(runs[0][0], m.dtn(eta, psi)) < 1e-10
+        a0, b0 = m.rhs(eta, psi)
+        assert rel(runs[0][1], a0) < 1e-10 and rel(runs[0][2], b0) < 1e-10

@@ -301,3 +301,28 @@ def test_schedule_algebra_1d_grid(M):
     s, t = I.step(eta, psi, 0.002, 2)
     s0, t0 = m.step(eta, psi, 0.002, 2)
     assert rel(s, s0) < 1e-13 and rel(t, t0) < 1e-13
+
+
+def test_row_shape_table_is_current():
+    """zk_row_shapes.hpp lists exactly the operation sequences (at most
+    MAX_LEN ops) of the padded row programs the planner writes for HOS orders
+    1 to 8, as gen_row_shapes.py collects them; and the C2 workload's
+    programs (512^2, M = 4) and the 2048^2 M = 5 programs are all among them,
+    so their padded row passes run compiled."""
+    import re
+    import sys
+
+    from plan_interp import build_checker
+
+    sys.path.insert(0, os.path.join(ROOT, "paper_2608_25203_amd", "csrc"))
+    import gen_row_shapes as G
+
+    txt = open(os.path.join(ROOT, "paper_2608_25203_amd", "csrc", "zk_row_shapes.hpp")).read()
+    table = [tuple(int(x.rstrip("u"), 16) for x in row.split(", ")) for row in re.findall(r"\{(0x[^}]*)\}", txt)]
+    lens = [int(x) for x in re.search(r"kRowShapeLen\[kRowShapes\] = \{([^}]*)\}", txt).group(1).split(", ")]
+    assert [len(r) for r in table] == lens
+    want = [tuple(G.word(o) for o in sh) for sh in G.collect(build_checker())]
+    assert table == want
+    for nx, M in ((512, 4), (2048, 5)):
+        for sh in G.program_shapes(load_plan(nx, nx, M)):
+            assert tuple(G.word(o) for o in sh) in table
