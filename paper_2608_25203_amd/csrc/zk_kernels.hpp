@@ -230,6 +230,25 @@ __host__ __device__ constexpr bool row_lanes_ok(int T, int E, bool padded, int r
   return padded && E % 5 != 0 && T % 64 == 0 && T <= 1024 && 2 * tpb * N * 2 * real_bytes <= 100 * 1024;
 }
 
+// Number of LD2 operations among the first i operations of compiled shape sh
+// (at an LD2: its ordinal among the shape's LD2s).
+constexpr int row_shape_ld2_ordinal(int sh, int i) {
+  int n = 0;
+  for (int k = 0; k < i; ++k) n += (kRowShapeOps[sh][k] & 255) == OP_LD2 ? 1 : 0;
+  return n;
+}
+constexpr int row_shapes_max_ld2() {
+  int m = 0;
+  for (int sh = 0; sh < kRowShapes; ++sh) {
+    const int n = row_shape_ld2_ordinal(sh, kRowShapeLen[sh]);
+    m = n > m ? n : m;
+  }
+  return m;
+}
+constexpr int kRowShapeMaxLd2 = row_shapes_max_ld2();
+// Column-maxima count from which compiled programs reduce them per block.
+constexpr int kBlockMaximaCols = 1024;
+
 // Padded row shapes whose kernels also hold every program shape of
 // zk_row_shapes.hpp as straight-line code (the team shapes the autotuner
 // picks for the large grids; the others interpret every program).
@@ -359,7 +378,14 @@ struct BodyLds {
   static constexpr int TWN = S::template tw_in_lds<real, LANES>() ? S::N : 16 / (int)sizeof(cpx<real>);
   static constexpr int BUF = S::TPB * S::template nbuf<real, LANES>() * S::L;  // row and plain column bodies
   static constexpr int RED = 2 * (S::BS / 64);
-  static constexpr int bytes() { return (BUF + TWN) * (int)sizeof(cpx<real>) + RED * (int)sizeof(float); }
+  // per-wavefront partial maxima of the fields of a compiled program's LD2s
+  static constexpr int FMX = (!LANES && BSZ == 0 && row_compiled_shapes(T, E, PAD, (int)sizeof(real)) &&
+                              S::KR * T >= kBlockMaximaCols)
+                                 ? 2 * kRowShapeMaxLd2 * (S::BS / 64)
+                                 : 0;
+  static constexpr int bytes() {
+    return (BUF + TWN) * (int)sizeof(cpx<real>) + (RED + FMX) * (int)sizeof(float);
+  }
 };
 
 // One entry of a batched launch: the tile's argument record and the
@@ -400,11 +426,12 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   } else {
     __shared__ cpx<real> s_smem[LD::BUF];
     __shared__ __attribute__((aligned(16))) cpx<real> s_twl[LD::TWN];
-    __shared__ float s_red[LD::RED];
+    __shared__ float s_red[LD::RED + LD::FMX];
     smem = s_smem;
     twl = s_twl;
     red = s_red;
   }
+  float *fmx = red + LD::RED;  // LD::FMX floats (compiled programs only)
   const int team = threadIdx.x / T;
   const int t = threadIdx.x % T;
   // rows y and y+1 share 128-byte lines of the tiled fields
@@ -452,7 +479,8 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   };
 
   // The operations, shared by the interpreter and the compiled shapes.
-  auto do_ld2 = [&](const RowOp &op) {
+  // maxima(op, ma, mb): the two fields' maxima over all columns
+  auto do_ld2 = [&](const RowOp &op, auto &&maxima) {
     const cpx<real> *Fa = a.mix + (long long)op.fa * a.mix_stride;
     const bool has_b = op.fb >= 0;
     const cpx<real> *Fb = a.mix + (long long)(has_b ? op.fb : op.fa) * a.mix_stride;
@@ -493,19 +521,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
           }
         }
       float ma = 0.f, mb = 0.f;
-      {
-        constexpr int NC = S::KR * T;  // nx / 2 columns
-        const float *ca = a.colmax + (long long)op.fa * NC;
-        const float *cb = a.colmax + (long long)(has_b ? op.fb : op.fa) * NC;
-        const int lane = threadIdx.x & 63;
-#pragma unroll
-        for (int c = lane; c < NC; c += 64) {
-          ma = fmaxf(ma, gload1(ca, c));
-          mb = fmaxf(mb, gload1(cb, c));
-        }
-        ma = wave_max(ma);
-        mb = wave_max(mb);
-      }
+      maxima(op, ma, mb);
       const float2 pa = pow2_scale(ma);
       const float2 pb = has_b ? pow2_scale(mb) : make_float2(1.f, 1.f);
       const real sa = (real)pa.x, sb = (real)pb.x;
@@ -541,6 +557,21 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
     };
     if constexpr (LANES) ld2(std::false_type{}, std::true_type{});
     else ld2(std::integral_constant<bool, T <= 512 && S::PADDED>{}, std::false_type{});
+  };
+  constexpr int NC = S::KR * T;  // nx / 2 columns: the length of a field's column maxima
+  // Each wavefront reduces every column maximum of the two fields on its own
+  // (no barrier between the loads and their use).
+  auto wave_maxima = [&](const RowOp &op, float &ma, float &mb) {
+    const float *ca = a.colmax + (long long)op.fa * NC;
+    const float *cb = a.colmax + (long long)(op.fb >= 0 ? op.fb : op.fa) * NC;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int c = lane; c < NC; c += 64) {
+      ma = fmaxf(ma, gload1(ca, c));
+      mb = fmaxf(mb, gload1(cb, c));
+    }
+    ma = wave_max(ma);
+    mb = wave_max(mb);
   };
   // LDP and STP act on caller fields, whose rows have the base length only.
   auto do_ldp = [&](const RowOp &op) {
@@ -619,6 +650,37 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
       static_for<0, kRowShapes>([&](auto shc) {
         constexpr int SH = decltype(shc)::value;
         if (pg.shape1 == SH + 1) {
+          // Rows of at least 2048 points (1024 column maxima per field): the
+          // column maxima of every LD2's fields are reduced once per block up
+          // front (each wavefront a share of the columns, one barrier)
+          // instead of in full by every wavefront at each LD2 (a quarter
+          // faster row pass at 2048 points; no gain at 1024, a loss at 512).
+          // Shorter rows keep the per-wavefront reductions.
+          constexpr bool BLOCK_MAXIMA = NC >= kBlockMaximaCols;
+          constexpr int NW = S::BS / 64;
+          const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+          static_for<0, kRowShapeLen[SH]>([&](auto ic) {
+            constexpr int I = decltype(ic)::value;
+            if constexpr (BLOCK_MAXIMA && (kRowShapeOps[SH][I] & 255) == OP_LD2) {
+              constexpr int J = row_shape_ld2_ordinal(SH, I);
+              const RowOp op = uniform_load(a.ops + pg.op0 + I);
+              const float *ca = a.colmax + (long long)op.fa * NC;
+              const float *cb = a.colmax + (long long)(op.fb >= 0 ? op.fb : op.fa) * NC;
+              float ma = 0.f, mb = 0.f;
+#pragma unroll
+              for (int c = wv * 64 + lane; c < NC; c += NW * 64) {
+                ma = fmaxf(ma, gload1(ca, c));
+                mb = fmaxf(mb, gload1(cb, c));
+              }
+              ma = wave_max(ma);
+              mb = wave_max(mb);
+              if (lane == 0) {
+                fmx[(2 * J) * NW + wv] = ma;
+                fmx[(2 * J + 1) * NW + wv] = mb;
+              }
+            }
+          });
+          if constexpr (BLOCK_MAXIMA) __syncthreads();
           static_for<0, kRowShapeLen[SH]>([&](auto ic) {
             constexpr int I = decltype(ic)::value;
             constexpr uint32_t w = kRowShapeOps[SH][I];
@@ -627,8 +689,17 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
             using IB = std::integral_constant<int, B>;
             using IC = std::integral_constant<int, C>;
             const RowOp op = uniform_load(a.ops + pg.op0 + I);
-            if constexpr (code == OP_LD2) {
-              do_ld2(op);
+            if constexpr (code == OP_LD2 && BLOCK_MAXIMA) {
+              constexpr int J = row_shape_ld2_ordinal(SH, I);
+              do_ld2(op, [&](const RowOp &, float &ma, float &mb) {
+#pragma unroll
+                for (int k = 0; k < NW; ++k) {
+                  ma = fmaxf(ma, fmx[(2 * J) * NW + k]);
+                  mb = fmaxf(mb, fmx[(2 * J + 1) * NW + k]);
+                }
+              });
+            } else if constexpr (code == OP_LD2) {
+              do_ld2(op, wave_maxima);
             } else if constexpr (code == OP_MOV) {
 #pragma unroll
               for (int e = 0; e < E; ++e) R[RS_A - 2][e] = reg(IB{}, e);
@@ -672,7 +743,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
     const RowOp op = uniform_load(a.ops + pg.op0 + i);
     switch (op.code) {
       case OP_LD2:
-        do_ld2(op);
+        do_ld2(op, wave_maxima);
         break;
       case OP_LDP:
         do_ldp(op);
