@@ -253,7 +253,7 @@ constexpr int kBlockMaximaCols = 1024;
 // zk_row_shapes.hpp as straight-line code (the team shapes the autotuner
 // picks for the large grids; the others interpret every program).
 __host__ __device__ constexpr bool row_compiled_shapes(int T, int E, bool padded, int real_bytes) {
-  return padded && ((E == 3 && T >= 64 && T <= 1024) || (real_bytes == 4 && E == 6 && T == 512));
+  return padded && ((E == 3 && T >= 64 && T <= 1024) || (real_bytes == 4 && E == 6 && T >= 128 && T <= 512));
 }
 
 template <int T, int E, int BSZ = 0, bool PAD = (E % 3 == 0)>
