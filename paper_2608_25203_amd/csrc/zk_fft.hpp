@@ -273,10 +273,12 @@ __host__ __device__ constexpr int lds_len(int N) { return N; }
 // holds element t + T*r in v[r].  The first pass is a radix-E butterfly in
 // registers; later passes exchange through LDS.  NBUF = 2 ping-pongs between
 // buf0 and buf1 (one barrier per pass); NBUF = 1 works in place in buf0 (two
-// barriers per pass).  Returns the buffer holding the transform in natural
-// order (lpad-indexed); the final barrier is included, so every thread may
-// read any element.  tw: the pass-ordered twiddle table of this (N, E).
-// Every thread of the block must call it.
+// barriers per pass).  The barriers are team_sync<T>: block barriers for
+// teams spanning wavefronts, wavefront-level ordering for teams inside one.
+// Returns the buffer holding the transform in natural order (lpad-indexed);
+// the final barrier is included, so every thread of the team may read any
+// element.  tw: the pass-ordered twiddle table of this (N, E).  Every thread
+// of the team must call it (of the block, for teams spanning wavefronts).
 // Pass-ordered twiddles: the later passes p = 1 .. NP-1 of a team FFT with
 // first-pass radix E read W_N^(r k step_p) for r = 1 .. R_p-1 and
 // k = 0 .. Ns_p-1 (Ns_p = E R_1 ... R_(p-1), step_p = N / (Ns_p R_p)).  The
@@ -308,6 +310,23 @@ struct LastPass {
 template <typename R, int N, int E>
 using LastRegs = cpx<R>[LastPass<N, E>::IT][LastPass<N, E>::R];
 
+// LDS ordering inside one wavefront: its LDS operations complete in issue
+// order, so a compiler barrier is all a wavefront-private exchange needs.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// The synchronisation of a team of T threads around its LDS exchanges: a
+// team of at most 64 threads lies inside one wavefront (teams are aligned)
+// and owns its buffers, so it orders them without a block barrier; larger
+// teams span wavefronts and take one.
+template <int T>
+__device__ __forceinline__ void team_sync() {
+  if constexpr (T <= 64) wave_lds_sync();
+  else __syncthreads();
+}
+
 // Shared body of the two forward-order forms.  KEEP = false: the last pass
 // writes LDS and a final barrier follows (team_fft).  KEEP = true: the last
 // pass leaves butterfly j's outputs in o[it][r] (element j + NB r) and no
@@ -326,7 +345,7 @@ __device__ __forceinline__ cpx<R> *team_fft_impl(cpx<R> (&v)[E], cpx<R> *buf0, c
   // kept live for the whole kernel.
   asm volatile("" : "+v"(t));
   DFT<E, DIR, R>::run(v);
-  __syncthreads();  // readers of the previous transform's result are done
+  team_sync<T>();  // readers of the previous transform's result are done
 #pragma unroll
   for (int r = 0; r < E; ++r) buf0[lpad(t * E + r)] = v[r];
   cpx<R> *in = buf0;
@@ -342,7 +361,7 @@ __device__ __forceinline__ cpx<R> *team_fft_impl(cpx<R> (&v)[E], cpx<R> *buf0, c
       return ns;
     }();
     constexpr bool to_regs = KEEP && p == NP - 1;
-    __syncthreads();
+    team_sync<T>();
     cpx<R> w[IT][Rp];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -352,7 +371,7 @@ __device__ __forceinline__ cpx<R> *team_fft_impl(cpx<R> (&v)[E], cpx<R> *buf0, c
         for (int r = 0; r < Rp; ++r) w[it][r] = in[lpad(j + r * nb)];
       }
     }
-    if constexpr (NBUF == 1 && !to_regs) __syncthreads();
+    if constexpr (NBUF == 1 && !to_regs) team_sync<T>();
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int j = t + T * it;
@@ -381,7 +400,7 @@ __device__ __forceinline__ cpx<R> *team_fft_impl(cpx<R> (&v)[E], cpx<R> *buf0, c
       out = tmp;
     }
   });
-  if constexpr (!KEEP) __syncthreads();
+  if constexpr (!KEEP) team_sync<T>();
   return in;
 }
 
@@ -408,7 +427,8 @@ __device__ __forceinline__ void team_fft_keep(cpx<R> (&v)[E], cpx<R> *buf0, cpx<
 // x[j + NB r] for butterfly j = t + T it < NB of LastPass<N, E> (unused where
 // j >= NB), the layout in which the caller loads it; out: v[r] = X[t + T r],
 // the layout of team_fft's input.  No LDS readout: the last (radix-E) step
-// runs in registers.  Every thread of the block must call it.
+// runs in registers.  Every thread of the team must call it (of the block, for
+// teams spanning wavefronts).
 template <typename R, int N, int E, int NBUF, int DIR>
 __device__ __forceinline__ void team_fft_t(LastRegs<R, N, E> &x, cpx<R> (&v)[E], cpx<R> *buf0, cpx<R> *buf1,
                                            const cpx<R> *__restrict__ tw, int t) {
@@ -418,7 +438,7 @@ __device__ __forceinline__ void team_fft_t(LastRegs<R, N, E> &x, cpx<R> (&v)[E],
   asm volatile("" : "+v"(t));
   cpx<R> *in = buf0;
   cpx<R> *out = buf0;
-  __syncthreads();  // readers of the previous transform's buffers are done
+  team_sync<T>();  // readers of the previous transform's buffers are done
   static_for<1, NP>([&](auto qc) {
     constexpr int p = NP - decltype(qc)::value;  // NP - 1 down to 1
     constexpr int Rp = later_radix(T, p);
@@ -432,7 +452,7 @@ __device__ __forceinline__ void team_fft_t(LastRegs<R, N, E> &x, cpx<R> (&v)[E],
     constexpr bool from_regs = p == NP - 1;
     cpx<R> w[IT][Rp];
     if constexpr (!from_regs) {
-      __syncthreads();
+      team_sync<T>();
 #pragma unroll
       for (int it = 0; it < IT; ++it) {
         const int j = t + T * it;
@@ -442,7 +462,7 @@ __device__ __forceinline__ void team_fft_t(LastRegs<R, N, E> &x, cpx<R> (&v)[E],
           for (int r = 0; r < Rp; ++r) w[it][r] = in[lpad(base + r * Ns)];
         }
       }
-      if constexpr (NBUF == 1) __syncthreads();
+      if constexpr (NBUF == 1) team_sync<T>();
     }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
@@ -467,7 +487,7 @@ __device__ __forceinline__ void team_fft_t(LastRegs<R, N, E> &x, cpx<R> (&v)[E],
     in = out;
     if constexpr (NBUF == 2) out = (out == buf0) ? buf1 : buf0;
   });
-  __syncthreads();
+  team_sync<T>();
 #pragma unroll
   for (int r = 0; r < E; ++r) v[r] = in[lpad(t * E + r)];
   DFT<E, DIR, R>::run(v);
@@ -527,14 +547,6 @@ __device__ __forceinline__ void fft_in(HbmRegs<R, N, E, LAST> &x, cpx<R> (&v)[E]
 // register DFT last.  Twiddles come from the natural table W_N^m (forward
 // sign; conjugated for DIR > 0).
 
-// LDS ordering inside one wavefront: its LDS operations complete in issue
-// order, so a compiler barrier is all a wavefront-private exchange needs
-// (a one-wavefront team's result readout).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <int DIR, typename R>
 __device__ __forceinline__ cpx<R> twn(const cpx<R> *tw, int m) {

@@ -448,16 +448,18 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
     stage_twiddles_async<S::BS, LANES ? N : N - E>(twl, tw);
     tw = twl;
   }
-  // No barrier here: every pass-ordered transform form opens with one before
-  // its first twiddle read, which publishes the staged table once each wave
-  // has waited for its share (settle_tw, before the first transform).  The
-  // permuted forms need not open with one, so settle_tw publishes the table
-  // with a barrier of its own.
+  // No barrier here: every pass-ordered transform form of a team spanning
+  // wavefronts opens with one before its first twiddle read, which publishes
+  // the staged table once each wave has waited for its share (settle_tw,
+  // before the first transform).  The permuted forms, and teams inside one
+  // wavefront (whose transforms order their LDS within the wavefront), need
+  // not open with one, so there settle_tw publishes the table with a barrier
+  // of its own.
   bool tw_pending = TWL;
   auto settle_tw = [&]() {
     if (tw_pending) {
       twiddles_landed();
-      if constexpr (LANES) __syncthreads();
+      if constexpr (LANES || T <= 64) __syncthreads();
       tw_pending = false;
     }
   };
@@ -953,6 +955,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
   auto settle_tw = [&]() {
     if (tw_pending) {
       twiddles_landed();
+      if constexpr (T <= 64) __syncthreads();  // one-wavefront teams' transforms open without one
       tw_pending = false;
     }
   };
