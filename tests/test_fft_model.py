@@ -1,7 +1,8 @@
 """Host model of the team FFT schedules in csrc/zk_fft.hpp (no GPU).
 
 The model follows the kernels' own index arithmetic: the pass plan (radix-E
-step in registers, then radix-4/2 passes), the pass-ordered twiddle table as
+step in registers, then radix-4/2 passes, radix 8 first for teams of 1024
+threads), the pass-ordered twiddle table as
 the host builds it (pass p's factor W^(r k step_p) at Ns_p - E + (r-1) Ns_p +
 k, conjugated for the inverse sign), and the three forms: team_fft (result in
 LDS, natural order), team_fft_keep (the last pass's butterfly j keeps
@@ -19,17 +20,23 @@ SHAPES = ([(T, E) for T in (2, 4, 8, 16) for E in (2, 3, 4, 6)]
 SHAPES = sorted(set(SHAPES))
 
 
+def pass_radix(T, rem):
+    if T >= 1024 and rem % 8 == 0 and rem != 16:
+        return 8
+    return 4 if rem % 4 == 0 else 2
+
+
 def later_radix(T, p):
     rem = T
     for _ in range(1, p):
-        rem //= 4 if rem % 4 == 0 else 2
-    return 4 if rem % 4 == 0 else 2
+        rem //= pass_radix(T, rem)
+    return pass_radix(T, rem)
 
 
 def num_passes(T):
     n, rem = 1, T
     while rem > 1:
-        rem //= 4 if rem % 4 == 0 else 2
+        rem //= pass_radix(T, rem)
         n += 1
     return n
 
