@@ -154,11 +154,11 @@ std::vector<cpx<real>> twiddles(int n) {
     const int E = cand[s];
     if (E == 0) continue;
     const int T = n / E;
-    if (n % E || T < 2 || (T & (T - 1)) || num_passes(T) < 2) continue;
+    if (n % E || T < 2 || (T & (T - 1)) || num_passes(T, E) < 2) continue;
     cpx<real> *tab = t.data() + (size_t)s * n;
     int ns = E;
-    for (int p = 1; p < num_passes(T); ++p) {
-      const int rp = later_radix(T, p), step = n / (ns * rp);
+    for (int p = 1; p < num_passes(T, E); ++p) {
+      const int rp = later_radix(T, E, p), step = n / (ns * rp);
       for (int r = 1; r < rp; ++r)
         for (int k = 0; k < ns; ++k) {
           const long double a = -two_pi * (long double)(r * k * step) / (long double)n;

@@ -247,23 +247,26 @@ struct DFT {
 // ---- pass plan ----------------------------------------------------------
 // After the radix-E first pass (in registers) the remaining factor T = N / E
 // is split into radix-4 passes (and one radix-2 pass if T is an odd power of
-// two); teams of 1024 threads and more take radix-8 passes first (8, 8, 4, 4
-// for T = 1024: one LDS round trip fewer, 3% faster there, while at 256
-// threads the larger, fewer butterflies measured 10% slower).  Every later
-// pass goes through LDS, its N / R butterflies spread over the T threads of
-// the team.
-__host__ __device__ constexpr int pass_radix(int T, int rem) {
-  return (T >= 1024 && rem % 8 == 0 && rem != 16) ? 8 : ((rem % 4 == 0) ? 4 : 2);
+// two).  Large teams take radix-8 passes first where that keeps enough of
+// the team busy: teams of 1024 threads (8, 8, 4, 4: one LDS round trip fewer,
+// 3% faster at 2048 points in FP64), and teams of 512 threads with E >= 6,
+// whose radix-8 passes keep three quarters of the threads busy (8, 8, 8
+// instead of 4, 4, 4, 4, 2: 14% faster at 3072 points in FP32).  With E = 3
+// at 512 threads, or at 256 threads, the fewer, larger butterflies measured
+// slower.  Every later pass goes through LDS, its N / R butterflies spread
+// over the T threads of the team.
+__host__ __device__ constexpr int pass_radix(int T, int E, int rem) {
+  return ((T >= 1024 || (T >= 512 && E >= 6)) && rem % 8 == 0 && rem != 16) ? 8 : ((rem % 4 == 0) ? 4 : 2);
 }
-__host__ __device__ constexpr int later_radix(int T, int p) {  // p >= 1
+__host__ __device__ constexpr int later_radix(int T, int E, int p) {  // p >= 1
   int rem = T;
-  for (int i = 1; i < p; ++i) rem /= pass_radix(T, rem);
-  return pass_radix(T, rem);
+  for (int i = 1; i < p; ++i) rem /= pass_radix(T, E, rem);
+  return pass_radix(T, E, rem);
 }
-__host__ __device__ constexpr int num_passes(int T) {
+__host__ __device__ constexpr int num_passes(int T, int E) {
   int n = 1, rem = T;
   while (rem > 1) {
-    rem /= pass_radix(T, rem);
+    rem /= pass_radix(T, E, rem);
     ++n;
   }
   return n;
@@ -307,8 +310,8 @@ __host__ __device__ constexpr int tw_slot(int E) {
 template <int N, int E>
 struct LastPass {
   static constexpr int T = N / E;
-  static constexpr int NP = num_passes(T);
-  static constexpr int R = later_radix(T, NP - 1);
+  static constexpr int NP = num_passes(T, E);
+  static constexpr int R = later_radix(T, E, NP - 1);
   static constexpr int NB = N / R;
   static constexpr int IT = (NB + T - 1) / T;
 };
@@ -343,7 +346,7 @@ __device__ __forceinline__ cpx<R> *team_fft_impl(cpx<R> (&v)[E], cpx<R> *buf0, c
                                                  const cpx<R> *__restrict__ tw, int t,
                                                  cpx<R> (*o)[LastPass<N, E>::R]) {
   constexpr int T = N / E;
-  constexpr int NP = num_passes(T);
+  constexpr int NP = num_passes(T, E);
   static_assert(NP >= 2, "team FFT needs at least two passes");
   // Make the lane index opaque (an empty asm statement, no instruction): the
   // per-pass LDS and twiddle addresses derived from it are then recomputed at
@@ -358,12 +361,12 @@ __device__ __forceinline__ cpx<R> *team_fft_impl(cpx<R> (&v)[E], cpx<R> *buf0, c
   cpx<R> *out = NBUF == 2 ? buf1 : buf0;
   static_for<1, NP>([&](auto pc) {
     constexpr int p = decltype(pc)::value;
-    constexpr int Rp = later_radix(T, p);
+    constexpr int Rp = later_radix(T, E, p);
     constexpr int nb = N / Rp;
     constexpr int IT = (nb + T - 1) / T;
     constexpr int Ns = [] {
       int ns = E;
-      for (int i = 1; i < p; ++i) ns *= later_radix(T, i);
+      for (int i = 1; i < p; ++i) ns *= later_radix(T, E, i);
       return ns;
     }();
     constexpr bool to_regs = KEEP && p == NP - 1;
@@ -439,7 +442,7 @@ template <typename R, int N, int E, int NBUF, int DIR>
 __device__ __forceinline__ void team_fft_t(LastRegs<R, N, E> &x, cpx<R> (&v)[E], cpx<R> *buf0, cpx<R> *buf1,
                                            const cpx<R> *__restrict__ tw, int t) {
   constexpr int T = N / E;
-  constexpr int NP = num_passes(T);
+  constexpr int NP = num_passes(T, E);
   static_assert(NP >= 2, "team FFT needs at least two passes");
   asm volatile("" : "+v"(t));
   cpx<R> *in = buf0;
@@ -447,12 +450,12 @@ __device__ __forceinline__ void team_fft_t(LastRegs<R, N, E> &x, cpx<R> (&v)[E],
   team_sync<T>();  // readers of the previous transform's buffers are done
   static_for<1, NP>([&](auto qc) {
     constexpr int p = NP - decltype(qc)::value;  // NP - 1 down to 1
-    constexpr int Rp = later_radix(T, p);
+    constexpr int Rp = later_radix(T, E, p);
     constexpr int nb = N / Rp;
     constexpr int IT = (nb + T - 1) / T;
     constexpr int Ns = [] {
       int ns = E;
-      for (int i = 1; i < p; ++i) ns *= later_radix(T, i);
+      for (int i = 1; i < p; ++i) ns *= later_radix(T, E, i);
       return ns;
     }();
     constexpr bool from_regs = p == NP - 1;

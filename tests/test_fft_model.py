@@ -2,7 +2,7 @@
 
 The model follows the kernels' own index arithmetic: the pass plan (radix-E
 step in registers, then radix-4/2 passes, radix 8 first for teams of 1024
-threads), the pass-ordered twiddle table as
+threads and of 512 with E >= 6), the pass-ordered twiddle table as
 the host builds it (pass p's factor W^(r k step_p) at Ns_p - E + (r-1) Ns_p +
 k, conjugated for the inverse sign), and the three forms: team_fft (result in
 LDS, natural order), team_fft_keep (the last pass's butterfly j keeps
@@ -20,23 +20,23 @@ SHAPES = ([(T, E) for T in (2, 4, 8, 16) for E in (2, 3, 4, 6)]
 SHAPES = sorted(set(SHAPES))
 
 
-def pass_radix(T, rem):
-    if T >= 1024 and rem % 8 == 0 and rem != 16:
+def pass_radix(T, E, rem):
+    if (T >= 1024 or (T >= 512 and E >= 6)) and rem % 8 == 0 and rem != 16:
         return 8
     return 4 if rem % 4 == 0 else 2
 
 
-def later_radix(T, p):
+def later_radix(T, E, p):
     rem = T
     for _ in range(1, p):
-        rem //= pass_radix(T, rem)
-    return pass_radix(T, rem)
+        rem //= pass_radix(T, E, rem)
+    return pass_radix(T, E, rem)
 
 
-def num_passes(T):
+def num_passes(T, E):
     n, rem = 1, T
     while rem > 1:
-        rem //= pass_radix(T, rem)
+        rem //= pass_radix(T, E, rem)
         n += 1
     return n
 
@@ -44,8 +44,8 @@ def num_passes(T):
 def plan(T, E):
     """(p, Rp, nb, Ns, step) for the passes after the radix-E step"""
     N, out, ns = T * E, [], E
-    for p in range(1, num_passes(T)):
-        rp = later_radix(T, p)
+    for p in range(1, num_passes(T, E)):
+        rp = later_radix(T, E, p)
         out.append((p, rp, N // rp, ns, N // (ns * rp)))
         ns *= rp
     return out
