@@ -247,16 +247,16 @@ struct DFT {
 // ---- pass plan ----------------------------------------------------------
 // After the radix-E first pass (in registers) the remaining factor T = N / E
 // is split into radix-4 passes (and one radix-2 pass if T is an odd power of
-// two).  Large teams take radix-8 passes first where that keeps enough of
-// the team busy: teams of 1024 threads (8, 8, 4, 4: one LDS round trip fewer,
-// 3% faster at 2048 points in FP64), and teams of 512 threads with E >= 6,
-// whose radix-8 passes keep three quarters of the threads busy (8, 8, 8
-// instead of 4, 4, 4, 4, 2: 14% faster at 3072 points in FP32).  With E = 3
-// at 512 threads, or at 256 threads, the fewer, larger butterflies measured
-// slower.  Every later pass goes through LDS, its N / R butterflies spread
-// over the T threads of the team.
+// two).  Teams take radix-8 passes first where that keeps enough of the
+// team busy: teams of 128 threads and more with E >= 6, whose radix-8 passes
+// keep three quarters of the threads busy or more (512 threads, E = 6: 8, 8, 8
+// instead of 4, 4, 4, 4, 2, 14% faster at 3072 points in FP32; the batch of
+// tiles 4% faster), and teams of 1024 threads (8, 8, 4, 4: one LDS round trip
+// fewer, 3% faster at 2048 points in FP64).  With E = 3 at 256 or 512 threads
+// the fewer, larger butterflies measured slower.  Every later pass goes
+// through LDS, its N / R butterflies spread over the T threads of the team.
 __host__ __device__ constexpr int pass_radix(int T, int E, int rem) {
-  return ((T >= 1024 || (T >= 512 && E >= 6)) && rem % 8 == 0 && rem != 16) ? 8 : ((rem % 4 == 0) ? 4 : 2);
+  return ((T >= 1024 || (T >= 128 && E >= 6)) && rem % 8 == 0 && rem != 16) ? 8 : ((rem % 4 == 0) ? 4 : 2);
 }
 __host__ __device__ constexpr int later_radix(int T, int E, int p) {  // p >= 1
   int rem = T;

@@ -2,7 +2,7 @@
 
 The model follows the kernels' own index arithmetic: the pass plan (radix-E
 step in registers, then radix-4/2 passes, radix 8 first for teams of 1024
-threads and of 512 with E >= 6), the pass-ordered twiddle table as
+threads and of 128 or more with E >= 6), the pass-ordered twiddle table as
 the host builds it (pass p's factor W^(r k step_p) at Ns_p - E + (r-1) Ns_p +
 k, conjugated for the inverse sign), and the three forms: team_fft (result in
 LDS, natural order), team_fft_keep (the last pass's butterfly j keeps
@@ -21,7 +21,7 @@ SHAPES = sorted(set(SHAPES))
 
 
 def pass_radix(T, E, rem):
-    if (T >= 1024 or (T >= 512 and E >= 6)) and rem % 8 == 0 and rem != 16:
+    if (T >= 1024 or (T >= 128 and E >= 6)) and rem % 8 == 0 and rem != 16:
         return 8
     return 4 if rem % 4 == 0 else 2
 
