@@ -80,8 +80,7 @@ enum {
                              and keeps the faster.  Same results to rounding. */
     ZK_OPT_ROW_PROGRAMS = 10, /* 1 (default): padded row passes of the team
                              shapes that compile them (E = 3 teams of 64 to
-                             1024 threads; FP32 also E = 6 teams of 128 to 512
-                             threads) run each
+                             1024 threads, E = 6 teams of 128 to 512) run each
                              row program whose operation sequence is one of
                              the compiled shapes as straight-line code; other
                              programs and shapes interpret the op list.

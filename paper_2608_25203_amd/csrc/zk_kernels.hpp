@@ -252,8 +252,8 @@ constexpr int kBlockMaximaCols = 1024;
 // Padded row shapes whose kernels also hold every program shape of
 // zk_row_shapes.hpp as straight-line code (the team shapes the autotuner
 // picks for the large grids; the others interpret every program).
-__host__ __device__ constexpr bool row_compiled_shapes(int T, int E, bool padded, int real_bytes) {
-  return padded && ((E == 3 && T >= 64 && T <= 1024) || (real_bytes == 4 && E == 6 && T >= 128 && T <= 512));
+__host__ __device__ constexpr bool row_compiled_shapes(int T, int E, bool padded) {
+  return padded && ((E == 3 && T >= 64 && T <= 1024) || (E == 6 && T >= 128 && T <= 512));
 }
 
 template <int T, int E, int BSZ = 0, bool PAD = (E % 3 == 0)>
@@ -379,7 +379,7 @@ struct BodyLds {
   static constexpr int BUF = S::TPB * S::template nbuf<real, LANES>() * S::L;  // row and plain column bodies
   static constexpr int RED = 2 * (S::BS / 64);
   // per-wavefront partial maxima of the fields of a compiled program's LD2s
-  static constexpr int FMX = (!LANES && BSZ == 0 && row_compiled_shapes(T, E, PAD, (int)sizeof(real)) &&
+  static constexpr int FMX = (!LANES && BSZ == 0 && row_compiled_shapes(T, E, PAD) &&
                               S::KR * T >= kBlockMaximaCols)
                                  ? 2 * kRowShapeMaxLd2 * (S::BS / 64)
                                  : 0;
@@ -647,7 +647,7 @@ __device__ __forceinline__ void row_body(const RowArgs<real> &a, int prog, int b
   // sets are fixed at compile time, so no interpreter state merges between
   // operations (and no operation dispatch remains); only the field ids, flags
   // and coefficients come from the op records.
-  if constexpr (row_compiled_shapes(T, E, S::PADDED, (int)sizeof(real)) && !DYN && !LANES && BSZ == 0) {
+  if constexpr (row_compiled_shapes(T, E, S::PADDED) && !DYN && !LANES && BSZ == 0) {
     if (pg.shape1 > 0) {
       static_for<0, kRowShapes>([&](auto shc) {
         constexpr int SH = decltype(shc)::value;

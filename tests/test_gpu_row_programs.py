@@ -34,7 +34,8 @@ def rel(a, b):
 # (nx, ny, M, precision, padded-row team T or 0 = default); E = 3 nx / 2 / T
 CASES = [(512, 512, 4, 64, 0), (128, 64, 3, 64, 64), (256, 128, 5, 64, 128), (1024, 64, 4, 64, 512),
          (2048, 32, 5, 64, 1024), (256, 64, 6, 64, 128), (512, 64, 4, 32, 256), (2048, 32, 5, 32, 512),
-         (1024, 32, 3, 32, 512), (256, 1, 4, 64, 128), (1024, 32, 4, 32, 256), (512, 32, 5, 32, 128)]
+         (1024, 32, 3, 32, 512), (256, 1, 4, 64, 128), (1024, 32, 4, 32, 256), (512, 32, 5, 32, 128),
+         (1024, 32, 4, 64, 256), (2048, 16, 5, 64, 512), (512, 64, 3, 64, 128)]
 
 
 @pytest.mark.parametrize("nx,ny,M,prec,T", CASES)
