@@ -118,7 +118,7 @@ void compute_layout(zk_ctx *c) {
   c->off_cmax = off;
   off = align_up(off + (size_t)probe.nmix * (nx / 2) * sizeof(float));
   c->off_sym = off;
-  off = align_up(off + (size_t)(nx / 2) * ny * sizeof(SymEl));
+  off = align_up(off + 2 * (size_t)(nx / 2) * ny * sizeof(double));  // G0 table, then the taper table
   c->off_fx = off;
   off = align_up(off + (size_t)(nx / 2) * sizeof(double));
   c->off_fy = off;
@@ -218,7 +218,7 @@ int upload(zk_ctx *c, double dt) {
   if (c->dirty) {
     const int nx = c->pp.nx, ny = c->pp.ny;
     // Fourier symbol tables (long double on the host, stored as FP64):
-    // |k|, G0 = |k| tanh(|k| d), taper exp(-(|k|/kc)^8) per band element in
+    // G0 = |k| tanh(|k| d) and the taper exp(-(|k|/kc)^8) per band element in
     // the tiled base-spectrum layout; separable filter factors per axis.
     {
       const long double pi = 3.14159265358979323846264338327950288L;
@@ -226,18 +226,17 @@ int upload(zk_ctx *c, double dt) {
       // kNyq over the axes that have one (a 1D grid, ny = 1, has only x)
       const long double kc =
           2.0L / 3.0L * (ny > 1 ? std::min(pi * nx / c->pp.Lx, pi * ny / c->pp.Ly) : pi * nx / c->pp.Lx);
-      std::vector<SymEl> tab((size_t)(nx / 2) * ny);
+      const size_t nel = (size_t)(nx / 2) * ny;
+      std::vector<double> tab(2 * nel);  // [G0 | taper]
       for (int col = 0; col < nx / 2; ++col)
         for (int b = 0; b < ny; ++b) {
           const int my = (b < ny / 2 || ny == 1) ? b : b - ny;  // a 1D grid's one row is ky = 0
           const long double kx = kxs * col, ky = kys * my;
           const long double kk = sqrtl(kx * kx + ky * ky);
           const long double r = kk / kc, r2 = r * r, r4 = r2 * r2;
-          SymEl e{};
-          e.kk = (double)kk;
-          e.g0 = (double)(c->pp.depth > 0 ? kk * tanhl(kk * c->pp.depth) : kk);
-          e.tp = (double)expl(-(r4 * r4));
-          tab[((size_t)(col / CBB) * ny + b) * CBB + col % CBB] = e;
+          const size_t e = ((size_t)(col / CBB) * ny + b) * CBB + col % CBB;
+          tab[e] = (double)(c->pp.depth > 0 ? kk * tanhl(kk * c->pp.depth) : kk);
+          tab[nel + e] = (double)expl(-(r4 * r4));
         }
       auto f1 = [&](int m, int n) {
         const long double th = 2 * pi * m / n;
@@ -246,7 +245,7 @@ int upload(zk_ctx *c, double dt) {
       std::vector<double> fx(nx / 2), fy(ny);
       for (int col = 0; col < nx / 2; ++col) fx[col] = f1(col, nx);
       for (int b = 0; b < ny; ++b) fy[b] = f1((b < ny / 2 || ny == 1) ? b : b - ny, ny);
-      HIP_TRY(c, put(c->off_sym, tab.data(), tab.size() * sizeof(SymEl)));
+      HIP_TRY(c, put(c->off_sym, tab.data(), tab.size() * sizeof(double)));
       HIP_TRY(c, put(c->off_fx, fx.data(), fx.size() * sizeof(double)));
       HIP_TRY(c, put(c->off_fy, fy.data(), fy.size() * sizeof(double)));
       HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -503,7 +502,8 @@ ColArgs<real> ctx_col_args(const zk_ctx *c, bool pad, int task0) {
   a.inv_kc = 1.0 / kc;
   a.taper_on = c->pp.taper ? 1 : 0;
   a.colmax = reinterpret_cast<float *>(ws + c->off_cmax);
-  a.sym = reinterpret_cast<const SymEl *>(ws + c->off_sym);
+  a.sym_g0 = reinterpret_cast<const double *>(ws + c->off_sym);
+  a.sym_tp = a.sym_g0 + (size_t)(c->pp.nx / 2) * c->pp.ny;
   a.filt_x = reinterpret_cast<const double *>(ws + c->off_fx);
   a.filt_y = reinterpret_cast<const double *>(ws + c->off_fy);
   a.ifsym = c->off_ifsym ? reinterpret_cast<const double *>(ws + c->off_ifsym) : nullptr;

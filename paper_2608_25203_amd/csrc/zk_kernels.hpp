@@ -44,10 +44,6 @@ struct RowArgs {
   const float *colmax;    // [mixed field][nx/2]: per-column max |value| written by the lifts
 };
 
-// Per band element symbol data (see symval).
-struct SymEl {
-  double kk, g0, tp, pad;
-};
 
 template <typename real>
 struct ColArgs {
@@ -67,7 +63,10 @@ struct ColArgs {
   double inv_kc;  // 1 / kc of the taper
   int taper_on;
   float *colmax;  // [mixed field][nx/2]: max |value| of each lifted column
-  const SymEl *sym;               // symbol table, base-spectrum layout
+  // per band element, base-spectrum layout: G0 = |k| tanh(|k| d) (read only
+  // at finite depth; deep water has G0 = |k|) and the taper exp(-(|k|/kc)^8)
+  // (read only while the taper is on); |k| itself is computed in the kernel
+  const double *sym_g0, *sym_tp;
   const double *filt_x, *filt_y;  // separable state filter factors
   const double *ifsym;            // kIfCoefs per band element (base layout), or null
   const double *layer_y;          // depths of the current chunk of layers (kMaxChunkLayers)
@@ -964,14 +963,17 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
     const int b = t + T * q;
     return (b < ny / 2) ? b : b - ny;
   };
+  // |k| from the wavenumbers; G0 and the taper from their tables only where
+  // the problem has them (a task's symbols read them for every band element,
+  // which at large grids is a fair share of the pass's memory traffic)
   double skk[QB], sg0[QB], stp[QB];
 #pragma unroll
   for (int q = 0; q < QB; ++q) {
-    const double *e = reinterpret_cast<const double *>(a.sym) + 4LL * base_index(col, t + T * q, ny);
-    const typename Vec2<double>::T k01 = ((const __attribute__((address_space(1))) typename Vec2<double>::T *)e)[0];
-    skk[q] = k01.x;
-    sg0[q] = k01.y;
-    stp[q] = gload1(e, 2);
+    const long long e = base_index(col, t + T * q, ny);
+    const double kx = a.kx_scale * col, ky = a.ky_scale * my_of(q);
+    skk[q] = sqrt(kx * kx + ky * ky);
+    sg0[q] = a.depth > 0.0 ? gload1(a.sym_g0, e) : skk[q];
+    stp[q] = a.taper_on ? gload1(a.sym_tp, e) : 1.0;
   }
   auto sym = [&](uint32_t s, int q) -> cpx<double> {
     return symval(s, skk[q], sg0[q], stp[q], col, t + T * q, a.ky_scale * my_of(q), a);
@@ -1258,8 +1260,9 @@ template <typename real, bool LIFTSYM>
 __device__ __forceinline__ void col_body_1d(const ColArgs<real> &a, int task_index, int col) {
   const ColTask task = uniform_load(a.tasks + task_index);
   if (col >= a.nx / 2) return;  // no barriers in this body
-  const double *e = reinterpret_cast<const double *>(a.sym) + 4LL * base_index(col, 0, 1);
-  const double kk = gload1(e, 0), g0 = gload1(e, 1), tp = gload1(e, 2);
+  const long long e = base_index(col, 0, 1);
+  const double kk = a.kx_scale * col;  // ky = 0
+  const double g0 = a.depth > 0.0 ? gload1(a.sym_g0, e) : kk, tp = a.taper_on ? gload1(a.sym_tp, e) : 1.0;
   auto sym = [&](uint32_t s) { return symval(s, kk, g0, tp, col, 0, 0.0, a); };
   auto cmac = [](cpx<double> &acc, cpx<double> x, cpx<double> sv) {
     acc.x += x.x * sv.x - x.y * sv.y;
