@@ -65,7 +65,8 @@ struct ColArgs {
   float *colmax;  // [mixed field][nx/2]: max |value| of each lifted column
   // per band element, base-spectrum layout: G0 = |k| tanh(|k| d) (read only
   // at finite depth; deep water has G0 = |k|) and the taper exp(-(|k|/kc)^8)
-  // (read only while the taper is on); |k| itself is computed in the kernel
+  // (read only while the taper is on, by tasks that fold); |k| itself is
+  // computed in the kernel
   const double *sym_g0, *sym_tp;
   const double *filt_x, *filt_y;  // separable state filter factors
   const double *ifsym;            // kIfCoefs per band element (base layout), or null
@@ -964,8 +965,11 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
     return (b < ny / 2) ? b : b - ny;
   };
   // |k| from the wavenumbers; G0 and the taper from their tables only where
-  // the problem has them (a task's symbols read them for every band element,
-  // which at large grids is a fair share of the pass's memory traffic)
+  // the problem and the task have them (a task's symbols read them for every
+  // band element, which at large grids is a fair share of the pass's memory
+  // traffic).  Only folds carry the taper (the plan validation holds output
+  // terms to that).
+  const bool need_tp = a.taper_on && ((task.fwd_sym[0] | task.fwd_sym[1] | task.fwd_sym[2]) & SYM_TAPER);
   double skk[QB], sg0[QB], stp[QB];
 #pragma unroll
   for (int q = 0; q < QB; ++q) {
@@ -973,7 +977,7 @@ __device__ __forceinline__ void col_body(const ColArgs<real> &a, int task_index,
     const double kx = a.kx_scale * col, ky = a.ky_scale * my_of(q);
     skk[q] = sqrt(kx * kx + ky * ky);
     sg0[q] = a.depth > 0.0 ? gload1(a.sym_g0, e) : skk[q];
-    stp[q] = a.taper_on ? gload1(a.sym_tp, e) : 1.0;
+    stp[q] = need_tp ? gload1(a.sym_tp, e) : 1.0;
   }
   auto sym = [&](uint32_t s, int q) -> cpx<double> {
     return symval(s, skk[q], sg0[q], stp[q], col, t + T * q, a.ky_scale * my_of(q), a);
@@ -1262,7 +1266,8 @@ __device__ __forceinline__ void col_body_1d(const ColArgs<real> &a, int task_ind
   if (col >= a.nx / 2) return;  // no barriers in this body
   const long long e = base_index(col, 0, 1);
   const double kk = a.kx_scale * col;  // ky = 0
-  const double g0 = a.depth > 0.0 ? gload1(a.sym_g0, e) : kk, tp = a.taper_on ? gload1(a.sym_tp, e) : 1.0;
+  const bool need_tp = a.taper_on && ((task.fwd_sym[0] | task.fwd_sym[1] | task.fwd_sym[2]) & SYM_TAPER);
+  const double g0 = a.depth > 0.0 ? gload1(a.sym_g0, e) : kk, tp = need_tp ? gload1(a.sym_tp, e) : 1.0;
   auto sym = [&](uint32_t s) { return symval(s, kk, g0, tp, col, 0, 0.0, a); };
   auto cmac = [](cpx<double> &acc, cpx<double> x, cpx<double> sv) {
     acc.x += x.x * sv.x - x.y * sv.y;

@@ -905,6 +905,8 @@ std::string validate_plan(const Plan &p, int rows_pad, int rows_base) {
         const ColTerm &tm = p.terms[o.t0 + k];
         if (tm.src >= p.nbase) return bad("term src");
         if (tm.src < 0 && t.fwd[0] < 0) return bad("term uses missing fold");
+        // the kernels read the taper table only for tasks that fold
+        if (tm.sym & SYM_TAPER) return bad("taper on an output term");
       }
     }
   }
