@@ -233,7 +233,7 @@ def closure_form(nsteps=1000, audit_every=10, tol=1e-4, floor_tol=2e-3):
                      "eta_rel_err_vs_order6": rel_max(e, e6)}
         print(f"# closure form: {name} {t:.2f} s, eta err {out[name]['eta_rel_err_vs_order6']:.3e}",
               file=sys.stderr, flush=True)
-    # audited runs: at the benchmark's tolerance, and at one just above the
+    # audited runs: at the 1e-4 fallback tolerance, and at one just above the
     # network's DtN error floor on this workload (which it can pass)
     for name, tl in (("closure_audited_fp32", tol), ("closure_audited_fp32_above_floor", floor_tol)):
         clo32.close()
